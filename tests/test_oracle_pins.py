@@ -1,0 +1,311 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test checks one part of the oracle against the mathematics of the paper's
+Section III: exact vertex optima (brute force), an independent LP solver (HiGHS),
+closed forms, the fixed-point property of eq.(hpr), the Halpern rate behind
+Theorem 1, the power-method lambda against a dense eigensolver, and the scaling
+equivalence of Section III-A.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_10891_amd import scuc
+from tests.helpers import dense_lp, highs, rel
+
+TINY_SEEDS = list(range(12))
+
+
+def tiny(seed, m=5, n=4):
+    return scuc.random_lp(np.random.default_rng(seed), m, n)
+
+
+# ----------------------------------------------------------------------------- brute force / KKT
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_brute_force_matches_highs(seed):
+    lp = tiny(seed)
+    obj, x = oracle.brute_force(lp)
+    ref, _, _ = highs(lp)
+    assert rel(obj, ref) < 1e-9
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_kkt_zero_at_vertex_optimum_and_grows_off_it(seed):
+    lp = tiny(seed)
+    obj, x = oracle.brute_force(lp)
+    duals = oracle.vertex_duals(lp, x)
+    if duals is None:
+        pytest.skip("degenerate optimal vertex")
+    y, z = duals
+    for ev in (oracle.kkt(lp, x, y, z), oracle.kkt_c(lp, x, y, z)):
+        assert ev["rel_kkt"] < 1e-12
+        assert abs(ev["pobj"] - obj) < 1e-9
+    rng = np.random.default_rng(seed)
+    j = rng.integers(lp.n)
+    for dx in (1e-3, 1e-1):
+        xp = x.copy()
+        xp[j] += dx if x[j] < lp.col_hi[j] else -dx
+        assert oracle.kkt(lp, xp, y, z)["rel_kkt"] > 1e-5 * dx
+    yp = y.copy()
+    yp[rng.integers(lp.m)] += 0.3
+    assert oracle.kkt(lp, x, yp, z)["rel_d"] > 1e-3
+
+
+def test_kkt_wrong_sign_multiplier_is_infinite_gap():
+    # min x s.t. x >= 1 (one-sided row), 0 <= x <= 2; y < 0 has no finite upper side
+    lp = dense_lp([[1.0]], [1.0], [np.inf], [0.0], [2.0], [1.0])
+    ev = oracle.kkt(lp, [1.0], [-1.0], [2.0])
+    assert ev["rel_gap"] == 1.0
+    ev_c = oracle.kkt_c(lp, [1.0], [-1.0], [2.0])
+    assert ev_c["rel_gap"] == 1.0
+    good = oracle.kkt(lp, [1.0], [1.0], [0.0])
+    assert good["rel_kkt"] < 1e-15
+
+
+def test_numpy_and_c_kkt_agree_on_random_points():
+    rng = np.random.default_rng(7)
+    _, lp = scuc.make_instance("small", 0)
+    for _ in range(3):
+        x = rng.uniform(0, 1, lp.n)
+        y = rng.standard_normal(lp.m) * np.isfinite(lp.row_lo) * np.isfinite(lp.row_hi)
+        z = np.zeros(lp.n)
+        a, b = oracle.kkt(lp, x, y, z), oracle.kkt_c(lp, x, y, z)
+        for key in ("rel_p", "rel_d", "rel_gap", "pobj", "dobj"):
+            assert abs(a[key] - b[key]) <= 1e-12 * (1 + abs(a[key]))
+
+
+# ----------------------------------------------------------------------------- whole solver
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_solver_matches_brute_force(seed):
+    lp = tiny(seed)
+    obj, _ = oracle.brute_force(lp)
+    r = oracle.solve(lp, oracle.Options(tol=1e-9, max_iter=200000))
+    assert r.term == "solved"
+    assert oracle.kkt(lp, r.x, r.y, r.z)["rel_kkt"] <= 1e-9 * 1.0001
+    assert rel(r.pobj, obj) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_solver_matches_highs_on_small_scuc(seed, small_instances):
+    data, lp = small_instances[seed]
+    ref, _, _ = highs(lp)
+    r = oracle.solve(lp, oracle.Options(tol=1e-8, max_iter=400000))
+    assert r.term == "solved"
+    assert rel(r.pobj, ref) < 1e-6
+    r4 = oracle.solve(lp, oracle.Options(tol=1e-4, max_iter=400000))
+    assert r4.term == "solved" and r4.rel_kkt <= 1e-4
+    assert oracle.kkt(lp, r4.x, r4.y, r4.z)["rel_kkt"] <= 1e-4
+
+
+def test_box_only_closed_form():
+    # no rows: the optimum puts each variable at the bound its cost pushes it to
+    rng = np.random.default_rng(3)
+    n = 9
+    c = rng.standard_normal(n)
+    l, u = -rng.uniform(0.5, 2, n), rng.uniform(0.5, 2, n)
+    lp = scuc.LP(0, n, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0),
+                 np.zeros(0), np.zeros(0), l, u, c, 0.0)
+    r = oracle.solve(lp, oracle.Options(tol=1e-12, max_iter=1000))
+    assert np.allclose(r.x, np.where(c > 0, l, u), atol=1e-12)
+    assert abs(r.pobj - c @ np.where(c > 0, l, u)) < 1e-12
+
+
+def test_fractional_knapsack_closed_form():
+    # min c^T x, a^T x >= b, 0 <= x <= 1 (c, a > 0): fill in increasing c_j / a_j
+    rng = np.random.default_rng(11)
+    n = 12
+    c, a = rng.uniform(1, 5, n), rng.uniform(1, 3, n)
+    b = 0.45 * a.sum()
+    order = np.argsort(c / a)
+    x = np.zeros(n)
+    need = b
+    for j in order:
+        take = min(1.0, need / a[j])
+        x[j] = take
+        need -= take * a[j]
+        if need <= 0:
+            break
+    lp = dense_lp([a], [b], [np.inf], np.zeros(n), np.ones(n), c)
+    r = oracle.solve(lp, oracle.Options(tol=1e-10, max_iter=200000))
+    assert r.term == "solved"
+    assert rel(r.pobj, c @ x) < 1e-8
+
+
+def test_merit_order_dispatch_closed_form():
+    # one period, units always on: sum p = D, 0 <= p <= pmax; cheapest units first
+    rng = np.random.default_rng(5)
+    G = 15
+    cost, pmax = rng.uniform(10, 60, G), rng.uniform(50, 300, G)
+    D = 0.55 * pmax.sum()
+    p = np.zeros(G)
+    rest = D
+    for g in np.argsort(cost):
+        p[g] = min(pmax[g], rest)
+        rest -= p[g]
+    lp = dense_lp([np.ones(G)], [D], [D], np.zeros(G), pmax, cost)
+    r = oracle.solve(lp, oracle.Options(tol=1e-10, max_iter=200000))
+    assert r.term == "solved"
+    assert rel(r.pobj, cost @ p) < 1e-8
+    # the balance dual is the marginal unit's cost
+    marginal = cost[np.argsort(cost)][np.searchsorted(np.cumsum(pmax[np.argsort(cost)]), D)]
+    assert abs(r.y[0] - marginal) < 1e-5 * marginal
+
+
+# ----------------------------------------------------------------------------- the iteration eq.(hpr)
+
+def _kkt_point(seed):
+    lp = tiny(seed)
+    _, x = oracle.brute_force(lp)
+    d = oracle.vertex_duals(lp, x)
+    return lp, x, d
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS)
+def test_kkt_point_is_fixed_point_of_one_step(seed):
+    lp, x, d = _kkt_point(seed)
+    if d is None:
+        pytest.skip("degenerate optimal vertex")
+    y, z = d
+    A = lp.to_scipy().toarray()
+    lam = 1.01 * np.linalg.eigvalsh(A @ A.T).max()
+    for sigma in (0.3, 1.0, 4.0):
+        for k in (0, 5):
+            xn, yn, xb, yb, zb = oracle.hpr_step(lp, sigma, lam, k, x, y, x, y)
+            scale = 1 + np.abs(x).max() + np.abs(y).max()
+            assert np.abs(xb - x).max() < 1e-12 * scale
+            assert np.abs(yb - y).max() < 1e-12 * scale
+            assert np.abs(xn - x).max() < 1e-12 * scale
+            assert np.abs(yn - y).max() < 1e-12 * scale
+            assert np.abs(zb - z).max() < 1e-11 * scale
+
+
+def _mnorm(A, sigma, lam, dx, dy):
+    return np.sqrt(max(dx @ dx / sigma + lam * sigma * dy @ dy + 2 * dy @ (A @ dx), 0.0))
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS[:8])
+def test_halpern_rate_without_restarts(seed):
+    """||w^k - wbar^{k+1}||_M <= ||w^0 - w*||_M / (k+1) for the Halpern iteration of eq.(hpr)."""
+    lp, xs, d = _kkt_point(seed)
+    if d is None:
+        pytest.skip("degenerate optimal vertex")
+    ys, _ = d
+    A = lp.to_scipy().toarray()
+    lam = 1.01 * np.linalg.eigvalsh(A @ A.T).max()
+    sigma = 0.8
+    x0 = np.clip(np.zeros(lp.n), lp.col_lo, lp.col_hi)
+    y0 = np.zeros(lp.m)
+    R0 = _mnorm(A, sigma, lam, x0 - xs, y0 - ys)
+    x, y = x0.copy(), y0.copy()
+    for k in range(300):
+        xn, yn, xb, yb, zb = oracle.hpr_step(lp, sigma, lam, k, x0, y0, x, y)
+        r = _mnorm(A, sigma, lam, x - xb, y - yb)
+        assert r <= R0 / (k + 1) * (1 + 1e-9) + 1e-13
+        x, y = xn, yn
+
+
+@pytest.mark.parametrize("seed", TINY_SEEDS[:6])
+def test_theorem1_residual_decays_like_one_over_k(seed):
+    """(k+1) ||R(xbar, ybar, zbar)|| stays bounded without restarts (Theorem 1)."""
+    lp, xs, d = _kkt_point(seed)
+    if d is None:
+        pytest.skip("degenerate optimal vertex")
+    A = lp.to_scipy().toarray()
+    lam = 1.01 * np.linalg.eigvalsh(A @ A.T).max()
+    sigma = 1.0
+    x0 = np.clip(np.zeros(lp.n), lp.col_lo, lp.col_hi)
+    y0 = np.zeros(lp.m)
+    x, y = x0.copy(), y0.copy()
+    vals = []
+    for k in range(2000):
+        x, y, xb, yb, zb = oracle.hpr_step(lp, sigma, lam, k, x0, y0, x, y)
+        if k in (99, 399, 1999):
+            vals.append((k + 1) * oracle.kkt_c(lp, xb, yb, zb)["R"])
+    assert vals[2] <= 4.0 * vals[0] + 1e-9
+
+
+# ----------------------------------------------------------------------------- scaling and lambda
+
+def test_power_method_lambda_matches_eigvalsh(small_instances):
+    _, lp = small_instances[0]
+    dr, dc, bb, bc, lam, its = oracle.scaling(lp)
+    A = lp.to_scipy().toarray()
+    As = dr[:, None] * A * dc[None, :]
+    top = np.linalg.eigvalsh(As @ As.T).max()
+    assert top <= 1.0 + 1e-12           # Pock-Chambolle (alpha = 1) bounds ||A~|| by 1
+    assert lam >= top * (1 - 1e-9)      # a valid step constant: lambda >= lambda_max
+    assert abs(lam - min(1.0, 1.01 * top)) <= 2e-3 * top
+    # without the Pock-Chambolle step nothing caps lambda at 1
+    o = oracle.Options(use_pc=False)
+    dr2, dc2, _, _, lam2, _ = oracle.scaling(lp, o)
+    As2 = dr2[:, None] * A * dc2[None, :]
+    top2 = np.linalg.eigvalsh(As2 @ As2.T).max()
+    assert abs(lam2 - 1.01 * top2) <= 2e-3 * top2
+
+
+def test_power_start_vector_is_splitmix64():
+    # first outputs of SplitMix64 seeded with 0 (Vigna's reference sequence)
+    ref = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    v = oracle.start_vector(0, 3)
+    exp = [2.0 * ((r >> 11) * 2.0 ** -53) - 1.0 for r in ref]
+    assert np.allclose(v, exp, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("variant", [dict(use_pc=False, use_bc=False), dict(ruiz_iters=10),
+                                     dict(use_bc=False), dict(use_pc=False)])
+def test_scaling_does_not_change_the_optimum(variant, small_instances):
+    """Scaled-then-unscaled optimum equals the unscaled optimum (Section III-A)."""
+    _, lp = small_instances[1]
+    ref, _, _ = highs(lp)
+    r = oracle.solve(lp, oracle.Options(tol=1e-7, max_iter=400000, **variant))
+    assert r.term == "solved"
+    assert rel(r.pobj, ref) < 1e-5
+
+
+def test_instance_scaling_recovers_original_objective():
+    data = scuc.make_scuc_data(scuc.SMALL, 4)
+    lp_s = scuc.build_lp(data, instance_scaling=True)
+    lp_u = scuc.build_lp(data, instance_scaling=False)
+    a, _, _ = highs(lp_s)
+    b, _, _ = highs(lp_u)
+    assert rel(a * lp_s.meta["eta_c"], b) < 1e-7
+    r = oracle.solve(lp_s, oracle.Options(tol=1e-8, max_iter=400000))
+    assert rel(r.pobj * lp_s.meta["eta_c"], b) < 1e-6
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_validation_rejects_bad_inputs():
+    good = dense_lp([[1.0, 2.0]], [0.0], [1.0], [0, 0], [1, 1], [1.0, 1.0])
+    assert oracle.validate(good)
+    bad = [
+        good.replace(val=np.array([np.nan, 1.0])),
+        good.replace(row_lo=np.array([2.0])),
+        good.replace(col_lo=np.array([0.0, 2.0])),
+        good.replace(c=np.array([np.inf, 0.0])),
+        good.replace(col_idx=np.array([0, 2], np.int32)),
+        good.replace(col_idx=np.array([1, 1], np.int32)),
+        good.replace(row_ptr=np.array([0, 3], np.int64)),
+        good.replace(row_lo=np.array([np.inf])),
+    ]
+    for b in bad:
+        assert not oracle.validate(b)
+        with pytest.raises(ValueError):
+            oracle.solve(b)
+
+
+def test_iteration_limit_and_single_iteration():
+    lp = tiny(2)
+    r1 = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=1))
+    assert r1.term == "iter_limit" and r1.iters == 1
+    ev = oracle.kkt(lp, r1.x, r1.y, r1.z)
+    assert abs(ev["rel_kkt"] - r1.rel_kkt) < 1e-12
+
+
+def test_infeasible_lp_is_not_reported_solved():
+    # x1 + x2 >= 3 with 0 <= x <= 1 has no solution
+    lp = dense_lp([[1.0, 1.0]], [3.0], [np.inf], [0, 0], [1, 1], [1.0, 1.0])
+    r = oracle.solve(lp, oracle.Options(tol=1e-6, max_iter=5000))
+    assert r.term != "solved"
