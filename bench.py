@@ -1,0 +1,174 @@
+"""Benchmark: time to 1e-4 relative KKT of the LP relaxation of a synthetic 2,000-bus SCUC
+instance (500 units, 48 h, 300 monitored lines x (1 + 10 outages)) on one MI355X.
+
+A step is one cold-start solve (hpr_solve) of the instance already resident in HBM: the
+whole iteration with its FP64 checks, restarts and sigma updates, until the first check
+with rel_kkt <= 1e-4 (FP64-verified). The headline runs with FP32 storage of A and the
+iterates (FP64 reductions); the plain FP64 solve of the same instance is timed beside it.
+
+Printed: one JSON line with the metric, iterations/s, the roofline of the dominant fused
+kernel (algorithmic bytes / event-timed duration against 8 TB/s), and the CPU oracle
+timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(lp, fp32: bool):
+    """Bytes one launch of each fused kernel must move (per the iteration of eq.(hpr)).
+
+    Dual step (rows of A): nnz values + nnz column indices + row offsets, reads y, y0, lo, hi,
+    writes y, gathers each entry of xhat once.  Primal step (rows of A^T): nnz values + indices
+    + offsets, reads x, x0, c, l, u, writes xhat and x, gathers each entry of y once.
+    Index width 4 bytes; value width 4 (FP32 storage) or 8 (FP64).
+    """
+    sv = 4 if fp32 else 8
+    nnz, m, n = lp.nnz, lp.m, lp.n
+    dual = nnz * (sv + 4) + 4 * m + sv * (5 * m) + sv * n
+    primal = nnz * (sv + 4) + 4 * n + sv * (7 * n) + sv * m
+    return primal, dual
+
+
+def run_solves(hprlp, h, steps, warmup, torch):
+    infos = []
+    for _ in range(warmup):
+        hprlp.hpr_set_start(h, None, None)
+        hprlp.hpr_solve(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hprlp.hpr_set_start(h, None, None)
+        infos.append(hprlp.hpr_solve(h))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return infos, (t1 - t0) / steps
+
+
+def cpu_baseline(lp, gpu_fp64_iters, sample_iters):
+    """The oracle (plain C, FP64, OpenMP row loops) on a bounded sample: `sample_iters`
+    iterations of the same instance; time to 1e-4 is extrapolated to the iteration count
+    the FP64 solve needs (the oracle takes the same iterations: same algorithm)."""
+    import oracle
+    oracle.build()
+    r = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=sample_iters))
+    its_per_s = r.iters / r.solve_s
+    est = r.setup_s + gpu_fp64_iters / its_per_s
+    return dict(value=round(est, 3), unit="s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{r.iters} oracle iterations of the same instance ({r.solve_s:.1f} s, "
+                       f"{its_per_s:.2f} it/s) plus its setup ({r.setup_s:.1f} s); time to 1e-4 "
+                       f"extrapolated to the {gpu_fp64_iters} iterations the FP64 solve takes",
+                iters_per_s=round(its_per_s, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="medium")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sample-iters", type=int, default=640)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2510_10891_amd import hprlp, scuc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    t = time.perf_counter()
+    data, lp = scuc.make_instance(args.config, args.seed)
+    log(f"instance {data.cfg.name}: m={lp.m} n={lp.n} nnz={lp.nnz} ({time.perf_counter() - t:.1f} s)")
+
+    res = {}
+    for name, prec in (("fp32", hprlp.HPR_FP32), ("fp64", hprlp.HPR_FP64)):
+        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=200000, profile=1, stream=stream)
+        h = hprlp.hpr_create(lp, opts)
+        infos, sec = run_solves(hprlp, h, args.steps, args.warmup, torch)
+        ks = hprlp.hpr_get_kernel_stats(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+        ev = oracle.kkt(lp, x, y, z)
+        info = infos[-1]
+        res[name] = dict(sec=sec, info=info, ks=ks, kkt=ev, x=x)
+        log(f"{name}: {info.term} iters={info.iters} restarts={info.restarts} solve={sec:.4f}s "
+            f"setup={info.setup_s:.2f}s it/s={info.iters / sec:.0f} rel_kkt(oracle)={ev['rel_kkt']:.2e} "
+            f"pobj={info.pobj:.8g} primal={ks['primal_ms'] * 1e3:.1f}us dual={ks['dual_ms'] * 1e3:.1f}us")
+        hprlp.hpr_destroy(h)
+
+    f32, f64 = res["fp32"], res["fp64"]
+    pb, db = algorithmic_bytes(lp, fp32=True)
+    ks = f32["ks"]
+    if ks["dual_ms"] >= ks["primal_ms"]:
+        kname, kbytes, kms = "dual_step_fp32", db, ks["dual_ms"]
+    else:
+        kname, kbytes, kms = "primal_step_fp32", pb, ks["primal_ms"]
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
+                other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(lp, f64["info"].iters, args.cpu_sample_iters)
+        log(f"cpu baseline: {cpu}")
+
+    rel_obj = abs(f32["info"].pobj - f64["info"].pobj) / max(1.0, abs(f64["info"].pobj))
+    out = {
+        "metric": "time-to-1e-4 rel KKT (s)",
+        "value": round(f32["sec"], 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["sec"] * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 reductions",
+        "data": "synthetic",
+        "config": {"workload": data.cfg.name, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "tol": 1e-4,
+                   "seed": args.seed},
+        "iters": f32["info"].iters,
+        "iters_per_s": round(f32["info"].iters / f32["sec"], 1),
+        "setup_s": round(f32["info"].setup_s, 3),
+        "rel_kkt_fp64_eval": f32["kkt"]["rel_kkt"],
+        "fp64": {"value": round(f64["sec"], 5), "iters": f64["info"].iters,
+                 "iters_per_s": round(f64["info"].iters / f64["sec"], 1),
+                 "rel_kkt_fp64_eval": f64["kkt"]["rel_kkt"],
+                 "dual_us": round(f64["ks"]["dual_ms"] * 1e3, 2),
+                 "primal_us": round(f64["ks"]["primal_ms"] * 1e3, 2)},
+        "fp32_vs_fp64": {"speedup": round(f64["sec"] / f32["sec"], 3), "obj_rel_diff": rel_obj,
+                         "x_rel_diff": float(np.linalg.norm(f32["x"] - f64["x"]) /
+                                             max(1e-30, np.linalg.norm(f64["x"])))},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

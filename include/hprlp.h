@@ -1,0 +1,166 @@
+/*
+ * hprlp.h - C interface of the MI355X (gfx950) LP solver.
+ *
+ * Solves the linear program of the paper's eq.(lp), generalised to two-sided rows,
+ *
+ *     minimise  c^T x + obj_offset
+ *     subject to row_lo <= A x <= row_hi,   col_lo <= x <= col_hi,
+ *
+ * with the restarted Halpern-Peaceman-Rachford iteration of eq.(hpr) (Section III):
+ * diagonal scaling and vector normalisation (Section III-A), lambda = lambda_max(A A^T)
+ * by the power method, a primal projection step and a dual projection step per
+ * iteration, reflection and Halpern averaging, and periodic FP64 checks of the KKT
+ * residual map of Theorem 1 that decide termination, restarts and the penalty sigma.
+ * A row with row_hi = +inf is the paper's a_i^T x >= theta_i.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an HPR_* status (0 = HPR_OK, negative = error) and never
+ *     aborts or throws. hpr_last_error() gives a message for the calling thread's
+ *     most recent error.
+ *   - Input arrays are read during the call only; the library keeps its own copies.
+ *     Unless a call says otherwise, pointers are host pointers.
+ *   - Output arrays are owned by the caller and must hold the stated number of doubles.
+ *   - A handle is used by one thread at a time. All device work of a handle runs on
+ *     the stream given in hpr_opts.stream (a hipStream_t), or on a stream the library
+ *     creates when it is NULL.
+ *   - Results are returned in the original (unscaled) space of the problem.
+ */
+#ifndef HPRLP_H
+#define HPRLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call status */
+enum {
+    HPR_OK = 0,
+    HPR_ERR_INVALID = -1,   /* bad argument or problem data (NaN, lo > hi, bad CSR, ...) */
+    HPR_ERR_NOMEM = -2,     /* device or host allocation failed */
+    HPR_ERR_HIP = -3,       /* a HIP runtime call failed */
+    HPR_ERR_STATE = -4      /* call not valid in the handle's state (e.g. no solve yet) */
+};
+
+/* termination of a solve (hpr_info.term) */
+enum {
+    HPR_SOLVED = 1,         /* rel_kkt <= tol, verified in FP64 */
+    HPR_ITER_LIMIT = 2,
+    HPR_TIME_LIMIT = 3,
+    HPR_NUMERIC_FAIL = 4    /* NaN or Inf appeared in a check */
+};
+
+/* storage precision of A and of the iterates (hpr_opts.precision) */
+enum {
+    HPR_FP64 = 0,           /* everything FP64 */
+    HPR_FP32 = 1            /* A, iterates and matrix-vector sums in FP32; norms, inner
+                               products, sigma, restart tests and KKT residuals in FP64 */
+};
+
+/* scaling steps (hpr_opts.scaling, bit mask), applied in this order */
+enum {
+    HPR_SCALE_RUIZ = 2,     /* hpr_opts.ruiz_iters passes of max-norm equilibration */
+    HPR_SCALE_PC = 1,       /* Pock-Chambolle diagonal scaling with alpha = 1 */
+    HPR_SCALE_BC = 4        /* divide bounds by 1 + ||b|| and the cost by 1 + ||c|| */
+};
+
+/* One LP in CSR form. Host pointers. col_idx entries lie in [0, n) with no column
+ * repeated inside a row; val and c are finite; bounds may be +-INFINITY but not NaN,
+ * row_lo <= row_hi, col_lo <= col_hi, a lower bound is never +inf and an upper bound
+ * never -inf. m may be 0 (row_ptr may then be NULL); n must be >= 1. */
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    const int64_t *row_ptr;     /* [m + 1], row_ptr[0] = 0, row_ptr[m] = nnz, nondecreasing */
+    const int32_t *col_idx;     /* [nnz] */
+    const double *val;          /* [nnz] */
+    const double *row_lo;       /* [m] */
+    const double *row_hi;       /* [m] */
+    const double *col_lo;       /* [n] */
+    const double *col_hi;       /* [n] */
+    const double *c;            /* [n] */
+    double obj_offset;
+} hpr_lp;
+
+typedef struct {
+    double tol;                 /* stop when rel_kkt <= tol (default 1e-4; 0 = run to max_iter) */
+    int64_t max_iter;           /* iteration limit, >= 1 (default 1e6) */
+    double time_limit_s;        /* wall-clock limit of hpr_solve, <= 0 = none (default 0) */
+    int32_t precision;          /* HPR_FP64 (default) or HPR_FP32 */
+    int32_t scaling;            /* mask of HPR_SCALE_* (default PC | BC) */
+    int32_t ruiz_iters;         /* passes when HPR_SCALE_RUIZ is set (default 10) */
+    int32_t check_every;        /* iterations between checks (default 64); iteration 0 and the
+                                   last allowed iteration are checks too */
+    double sigma0;              /* initial penalty sigma (default 1) */
+    double lambda;              /* > 0: use as lambda and skip the power method (default 0) */
+    uint64_t seed;              /* power-method start vector (SplitMix64 stream, default 0) */
+    int32_t restart;            /* restart rule on (default 1) */
+    int32_t sigma_update;       /* sigma adaptation at restarts on (default 1) */
+    int32_t power_max_iter;     /* default 200 */
+    double power_tol;           /* relative change that stops the power method (default 1e-6) */
+    int32_t profile;            /* 1: time one primal and one dual kernel per block of
+                                   iterations with HIP events (hpr_get_kernel_stats) */
+    void *stream;               /* hipStream_t or NULL */
+} hpr_opts;
+
+typedef struct {
+    int32_t term;               /* HPR_SOLVED, ... */
+    int64_t iters;              /* iterations performed */
+    int64_t restarts;
+    double pobj, dobj;          /* primal and dual objective (original space) */
+    double rel_p, rel_d, rel_gap, rel_kkt;   /* relative KKT residuals, FP64 */
+    double lambda, sigma;       /* step constant used and final sigma */
+    double setup_s;             /* hpr_create: scaling, transfer, power method */
+    double solve_s;             /* hpr_solve wall time */
+} hpr_info;
+
+/* Kernel timings of the last hpr_solve with hpr_opts.profile = 1: average duration of
+ * the fused primal step (A^T product, box projection, Halpern averaging) and of the
+ * fused dual step (A product, row projection, Halpern averaging), measured with HIP
+ * events on the solve's stream around sampled non-check iterations. */
+typedef struct {
+    double primal_ms;
+    double dual_ms;
+    int64_t samples;
+} hpr_kernel_stats;
+
+typedef struct hpr_handle hpr_handle;
+
+/* Fills *opts with the defaults listed above. */
+void hpr_default_opts(hpr_opts *opts);
+
+/* Validates and copies the LP, scales it, uploads it to the current HIP device and
+ * computes lambda. *out receives a handle to free with hpr_destroy. */
+int hpr_create(const hpr_lp *lp, const hpr_opts *opts, hpr_handle **out);
+
+/* Replaces the column bounds (original space), e.g. to fix binaries as the paper's
+ * Fix operator does; A, rows and scaling are kept. NULL keeps that side. */
+int hpr_set_bounds(hpr_handle *h, const double *col_lo, const double *col_hi);
+
+/* Sets the start point (original space) of the next hpr_solve: x0 [n], y0 [m]; NULL for
+ * either means zero. The point is projected onto the bounds (x) and onto the sign
+ * pattern of the rows (y: >= 0 needs a finite lower side, <= 0 a finite upper side). */
+int hpr_set_start(hpr_handle *h, const double *x0, const double *y0);
+
+/* Runs the iteration from the start point until tol, max_iter or the time limit. */
+int hpr_solve(hpr_handle *h, hpr_info *info);
+
+/* Copies the last check's point (xbar [n], ybar [m], zbar [n]) in the original space
+ * to caller-owned host arrays; any may be NULL. HPR_ERR_STATE before a solve. */
+int hpr_get_solution(hpr_handle *h, double *x, double *y, double *z);
+
+/* Kernel timings of the last solve (zeros unless it ran with hpr_opts.profile = 1). */
+int hpr_get_kernel_stats(hpr_handle *h, hpr_kernel_stats *out);
+
+/* Frees the handle and its device memory. NULL is accepted. */
+int hpr_destroy(hpr_handle *h);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *hpr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPRLP_H */

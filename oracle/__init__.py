@@ -94,7 +94,7 @@ class _Pinned:
         self.v = _f64(lp.val)
         self.lo, self.hi = _f64(lp.row_lo), _f64(lp.row_hi)
         self.l, self.u, self.c = _f64(lp.col_lo), _f64(lp.col_hi), _f64(lp.c)
-        self.s = _LP(lp.m, lp.n, int(self.rp[-1]) if len(self.rp) else 0,
+        self.s = _LP(lp.m, lp.n, len(self.ci),
                      self.rp.ctypes.data, self.ci.ctypes.data, self.v.ctypes.data,
                      self.lo.ctypes.data, self.hi.ctypes.data, self.l.ctypes.data,
                      self.u.ctypes.data, self.c.ctypes.data, float(lp.obj_offset))

@@ -1,0 +1,232 @@
+"""Python binding of libhprlp.so (the C interface in include/hprlp.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.
+Loading fails with an error when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhprlp.so")
+
+HPR_OK, HPR_ERR_INVALID, HPR_ERR_NOMEM, HPR_ERR_HIP, HPR_ERR_STATE = 0, -1, -2, -3, -4
+HPR_SOLVED, HPR_ITER_LIMIT, HPR_TIME_LIMIT, HPR_NUMERIC_FAIL = 1, 2, 3, 4
+HPR_FP64, HPR_FP32 = 0, 1
+HPR_SCALE_PC, HPR_SCALE_RUIZ, HPR_SCALE_BC = 1, 2, 4
+TERM_NAMES = {HPR_SOLVED: "solved", HPR_ITER_LIMIT: "iter_limit", HPR_TIME_LIMIT: "time_limit",
+              HPR_NUMERIC_FAIL: "numeric_fail"}
+
+
+class HprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class hpr_lp(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("row_lo", C.c_void_p), ("row_hi", C.c_void_p), ("col_lo", C.c_void_p),
+                ("col_hi", C.c_void_p), ("c", C.c_void_p), ("obj_offset", C.c_double)]
+
+
+class hpr_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
+                ("precision", C.c_int32), ("scaling", C.c_int32), ("ruiz_iters", C.c_int32),
+                ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
+                ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
+                ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class hpr_kernel_stats(C.Structure):
+    _fields_ = [("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64)]
+
+
+class hpr_info(C.Structure):
+    _fields_ = [("term", C.c_int32), ("iters", C.c_int64), ("restarts", C.c_int64),
+                ("pobj", C.c_double), ("dobj", C.c_double), ("rel_p", C.c_double),
+                ("rel_d", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double),
+                ("lambda_", C.c_double), ("sigma", C.c_double), ("setup_s", C.c_double),
+                ("solve_s", C.c_double)]
+
+
+_lib = None
+EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", "hpr_solve",
+           "hpr_get_solution", "hpr_get_kernel_stats", "hpr_destroy", "hpr_last_error")
+
+
+def lib():
+    """Load libhprlp.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with python -m paper_2510_10891_amd.build")
+        L = C.CDLL(_LIB_PATH)
+        L.hpr_last_error.restype = C.c_char_p
+        for name in EXPORTS[1:-1]:
+            getattr(L, name).restype = C.c_int
+        L.hpr_default_opts.restype = None
+        _lib = L
+    return _lib
+
+
+def hpr_last_error() -> str:
+    return lib().hpr_last_error().decode()
+
+
+def _check(rc):
+    if rc != HPR_OK:
+        raise HprError(rc, hpr_last_error())
+
+
+@dataclass
+class Options:
+    """Python mirror of hpr_opts (defaults equal hpr_default_opts)."""
+    tol: float = 1e-4
+    max_iter: int = 1_000_000
+    time_limit_s: float = 0.0
+    precision: int = HPR_FP64
+    scaling: int = HPR_SCALE_PC | HPR_SCALE_BC
+    ruiz_iters: int = 10
+    check_every: int = 64
+    sigma0: float = 1.0
+    lambda_: float = 0.0
+    seed: int = 0
+    restart: int = 1
+    sigma_update: int = 1
+    power_max_iter: int = 200
+    power_tol: float = 1e-6
+    profile: int = 0
+    stream: int = 0
+
+    def to_c(self) -> hpr_opts:
+        o = hpr_opts()
+        for f in fields(self):
+            setattr(o, f.name, getattr(self, f.name))
+        o.stream = self.stream or None
+        return o
+
+
+def hpr_default_opts() -> hpr_opts:
+    o = hpr_opts()
+    lib().hpr_default_opts(C.byref(o))
+    return o
+
+
+@dataclass
+class Info:
+    term: str
+    iters: int
+    restarts: int
+    pobj: float
+    dobj: float
+    rel_p: float
+    rel_d: float
+    rel_gap: float
+    rel_kkt: float
+    lam: float
+    sigma: float
+    setup_s: float
+    solve_s: float
+
+
+class _LPArrays:
+    """Contiguous copies kept alive for the duration of a call."""
+
+    def __init__(self, lp):
+        f64 = lambda a: np.ascontiguousarray(a, np.float64)
+        self.rp = np.ascontiguousarray(lp.row_ptr, np.int64)
+        self.ci = np.ascontiguousarray(lp.col_idx, np.int32)
+        self.v = f64(lp.val)
+        self.lo, self.hi = f64(lp.row_lo), f64(lp.row_hi)
+        self.l, self.u, self.c = f64(lp.col_lo), f64(lp.col_hi), f64(lp.c)
+        if len(self.v) != len(self.ci):
+            raise ValueError("col_idx and val differ in length")
+        nnz = len(self.ci)   # the library checks row_ptr[m] == nnz
+        ptr = lambda a: a.ctypes.data if a.size else None
+        self.s = hpr_lp(lp.m, lp.n, nnz, ptr(self.rp), ptr(self.ci), ptr(self.v), ptr(self.lo),
+                        ptr(self.hi), ptr(self.l), ptr(self.u), ptr(self.c), float(lp.obj_offset))
+
+
+class Handle:
+    """Owns an hpr_handle*; freed by hpr_destroy (or when garbage collected)."""
+
+    def __init__(self, ptr, m, n):
+        self.ptr, self.m, self.n = ptr, m, n
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            try:
+                lib().hpr_destroy(self.ptr)
+            except Exception:
+                pass
+            self.ptr = None
+
+
+def hpr_create(lp, opts: Options | None = None) -> Handle:
+    a = _LPArrays(lp)
+    o = (opts or Options()).to_c()
+    out = C.c_void_p()
+    _check(lib().hpr_create(C.byref(a.s), C.byref(o), C.byref(out)))
+    return Handle(out, lp.m, lp.n)
+
+
+def hpr_destroy(h: Handle) -> None:
+    if h.ptr:
+        _check(lib().hpr_destroy(h.ptr))
+        h.ptr = None
+
+
+def hpr_set_bounds(h: Handle, col_lo=None, col_hi=None) -> None:
+    lo = None if col_lo is None else np.ascontiguousarray(col_lo, np.float64)
+    hi = None if col_hi is None else np.ascontiguousarray(col_hi, np.float64)
+    _check(lib().hpr_set_bounds(h.ptr, None if lo is None else lo.ctypes.data_as(C.c_void_p),
+                                None if hi is None else hi.ctypes.data_as(C.c_void_p)))
+
+
+def hpr_set_start(h: Handle, x0=None, y0=None) -> None:
+    xa = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+    ya = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+    _check(lib().hpr_set_start(h.ptr, None if xa is None else xa.ctypes.data_as(C.c_void_p),
+                               None if ya is None else ya.ctypes.data_as(C.c_void_p)))
+
+
+def hpr_solve(h: Handle) -> Info:
+    info = hpr_info()
+    _check(lib().hpr_solve(h.ptr, C.byref(info)))
+    return Info(TERM_NAMES.get(info.term, str(info.term)), info.iters, info.restarts, info.pobj,
+                info.dobj, info.rel_p, info.rel_d, info.rel_gap, info.rel_kkt, info.lambda_,
+                info.sigma, info.setup_s, info.solve_s)
+
+
+def hpr_get_solution(h: Handle):
+    x = np.zeros(h.n)
+    y = np.zeros(max(h.m, 1))
+    z = np.zeros(h.n)
+    _check(lib().hpr_get_solution(h.ptr, x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
+                                  z.ctypes.data_as(C.c_void_p)))
+    return x, y[:h.m], z
+
+
+def hpr_get_kernel_stats(h: Handle) -> dict:
+    s = hpr_kernel_stats()
+    _check(lib().hpr_get_kernel_stats(h.ptr, C.byref(s)))
+    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples)
+
+
+def solve(lp, opts: Options | None = None, x0=None, y0=None):
+    """Create, (optionally warm-start,) solve and fetch: returns (info, x, y, z)."""
+    h = hpr_create(lp, opts)
+    try:
+        if x0 is not None or y0 is not None:
+            hpr_set_start(h, x0, y0)
+        info = hpr_solve(h)
+        x, y, z = hpr_get_solution(h)
+    finally:
+        hpr_destroy(h)
+    return info, x, y, z

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP solver against the CPU oracle, through the C interface.
+
+Short runs (tol = 0, a fixed iteration count) must reproduce the oracle's iterates
+element by element: same scaling, lambda, iteration, check schedule, restarts and
+sigma. FP64 agrees to rounding (1e-8 relative); FP32 storage to FP32 rounding over a
+few iterations. Full solves are judged by the oracle's FP64 KKT evaluator.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_10891_amd import hprlp, scuc
+from tests.helpers import highs, rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_RTOL = 1e-8
+FP32_RTOL = 2e-5
+
+
+def ragged_lp(seed, m=400, n=900, bounded=True):
+    """Random feasible LP whose row and column lengths span every lane-group bin
+    (empty rows and columns, 1-3 entries, tens, hundreds, > 256) and a ragged tail."""
+    rng = np.random.default_rng(seed)
+    empty_cols = set(rng.choice(n, 7, replace=False).tolist())
+    usable = np.array([j for j in range(n) if j not in empty_cols])
+    lens = rng.choice([0, 1, 2, 3, 5, 9, 17, 33, 70, 140, 300, 700], size=m,
+                      p=[.04, .12, .12, .12, .1, .1, .1, .08, .08, .06, .05, .03])
+    rows, cols, vals = [], [], []
+    for i, L in enumerate(lens):
+        cs = np.sort(rng.choice(usable, size=min(L, len(usable)), replace=False))
+        rows += [i] * len(cs)
+        cols += cs.tolist()
+        vals += rng.standard_normal(len(cs)).tolist()
+    import scipy.sparse as sp
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    l = -rng.uniform(0.5, 2, n)
+    u = rng.uniform(0.5, 2, n)
+    if not bounded:
+        u[rng.random(n) < 0.2] = np.inf
+        l[rng.random(n) < 0.1] = -np.inf
+    xf = np.clip(rng.uniform(-0.5, 0.5, n), l, u)
+    ax = A @ xf
+    kind = rng.random(m)
+    lo = np.where(kind < 0.7, ax - rng.uniform(0, 1, m), -np.inf)
+    hi = np.where(kind > 0.3, ax + rng.uniform(0, 1, m), np.inf)
+    eq = kind < 0.1
+    lo[eq] = hi[eq] = ax[eq]
+    empty = np.diff(A.indptr) == 0
+    lo[empty] = np.minimum(lo[empty], 0.0)
+    hi[empty] = np.maximum(hi[empty], 0.0)
+    c = rng.standard_normal(n)
+    return scuc.LP(m, n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.copy(),
+                   lo, hi, l, u, c, 0.25)
+
+
+def run_both(lp, K, precision=hprlp.HPR_FP64, **kw):
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, **kw))
+    opts = hprlp.Options(tol=0.0, max_iter=K, precision=precision,
+                         **{("lambda_" if k == "lambda_in" else k): v for k, v in kw.items()
+                            if k not in ("use_pc", "use_bc", "ruiz_iters")})
+    if "use_pc" in kw or "use_bc" in kw or "ruiz_iters" in kw:
+        mask = (hprlp.HPR_SCALE_PC if kw.get("use_pc", True) else 0) | \
+               (hprlp.HPR_SCALE_BC if kw.get("use_bc", True) else 0) | \
+               (hprlp.HPR_SCALE_RUIZ if kw.get("ruiz_iters", 0) else 0)
+        opts.scaling = mask
+        opts.ruiz_iters = kw.get("ruiz_iters", 10)
+    info, x, y, z = hprlp.solve(lp, opts)
+    return o, info, x, y, z
+
+
+def assert_close(a, b, rtol, what):
+    scale = 1.0 + np.abs(b).max(initial=0.0)
+    err = np.abs(a - b).max(initial=0.0)
+    assert err <= rtol * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def assert_parity(o, info, x, y, z, rtol):
+    assert info.iters == o.iters
+    assert info.restarts == o.restarts
+    assert abs(info.lam - o.lam) <= 1e-12 * o.lam
+    assert_close(x, o.x, rtol, "x")
+    assert_close(y, o.y, rtol, "y")
+    assert_close(z, o.z, rtol, "z")
+    assert abs(info.pobj - o.pobj) <= rtol * (1 + abs(o.pobj))
+
+
+# ----------------------------------------------------------------------------- short-run parity
+
+@pytest.mark.parametrize("K", [1, 2, 64, 65, 66, 200, 513])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp64_iterates_match_oracle_ragged(seed, K):
+    lp = ragged_lp(seed, bounded=(seed == 0))
+    o, info, x, y, z = run_both(lp, K)
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("K", [1, 65, 1000])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fp64_iterates_match_oracle_small_scuc(seed, K):
+    _, lp = scuc.make_instance("small", seed)
+    o, info, x, y, z = run_both(lp, K)
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("variant", [dict(use_pc=False, use_bc=False), dict(ruiz_iters=10),
+                                     dict(restart=False, sigma_update=False), dict(lambda_in=0.9)])
+def test_fp64_options_match_oracle(variant):
+    _, lp = scuc.make_instance("small", 3)
+    o, info, x, y, z = run_both(lp, 300, **variant)
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("K", [1, 2, 65])
+def test_fp32_iterates_track_oracle(K):
+    lp = ragged_lp(2)
+    o, info, x, y, z = run_both(lp, K, precision=hprlp.HPR_FP32)
+    assert info.iters == o.iters
+    assert_close(x, o.x, FP32_RTOL * 10 * K, "x")
+    assert_close(y, o.y, FP32_RTOL * 10 * K, "y")
+
+
+# ----------------------------------------------------------------------------- full solves
+
+@pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
+@pytest.mark.parametrize("seed", range(10))
+def test_small_scuc_reaches_tolerance(seed, precision):
+    _, lp = scuc.make_instance("small", seed)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-4, precision=precision, max_iter=200000))
+    assert info.term == "solved"
+    ev = oracle.kkt(lp, x, y, z)
+    assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), ev
+    assert abs(ev["rel_kkt"] - info.rel_kkt) <= 1e-6 + 1e-3 * info.rel_kkt
+    ref, _, _ = highs(lp)
+    assert rel(info.pobj, ref) < 2e-3
+    if precision == hprlp.HPR_FP64:
+        o = oracle.solve(lp, oracle.Options(tol=1e-4, max_iter=200000))
+        assert o.iters == info.iters
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fp64_tight_tolerance_matches_oracle_objective(seed):
+    _, lp = scuc.make_instance("small", seed)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-8, max_iter=400000))
+    o = oracle.solve(lp, oracle.Options(tol=1e-8, max_iter=400000))
+    assert info.term == "solved" and o.term == "solved"
+    assert rel(info.pobj, o.pobj) < 1e-6
+    assert oracle.kkt(lp, x, y, z)["rel_kkt"] <= 1e-8 * 1.001
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_lps_match_brute_force(seed):
+    lp = scuc.random_lp(np.random.default_rng(seed), 5, 4)
+    obj, _ = oracle.brute_force(lp)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-9, max_iter=200000))
+    assert info.term == "solved"
+    assert rel(info.pobj, obj) < 1e-6
+
+
+def test_medium_full_size_parity_and_tolerance():
+    """The 2,000-bus instance at full size: 65 iterations element by element against the
+    oracle, then FP64 and FP32 solves to 1e-4 judged by the FP64 KKT evaluator."""
+    _, lp = scuc.make_instance("medium", 0)
+    o, info, x, y, z = run_both(lp, 65)
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+    for precision in (hprlp.HPR_FP64, hprlp.HPR_FP32):
+        info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-4, precision=precision, max_iter=100000))
+        assert info.term == "solved", info
+        ev = oracle.kkt(lp, x, y, z)
+        assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), ev
+
+
+# ----------------------------------------------------------------------------- handle semantics
+
+def test_fixing_bounds_then_resolve_matches_oracle():
+    data, lp = scuc.make_instance("small", 4)
+    G, T = data.cfg.n_gen, data.cfg.T
+    lo, hi = lp.col_lo.copy(), lp.col_hi.copy()
+    for g in range(0, G, 3):            # fix u of every third unit on for the first 8 hours
+        cols = scuc.col_index(G, np.arange(8), scuc.U, g)
+        lo[cols] = hi[cols] = 1.0
+    fixed = lp.replace(col_lo=lo, col_hi=hi)
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=300))
+    hprlp.hpr_solve(h)
+    hprlp.hpr_set_bounds(h, lo, hi)
+    info = hprlp.hpr_solve(h)
+    x, y, z = hprlp.hpr_get_solution(h)
+    o = oracle.solve(fixed, oracle.Options(tol=0.0, max_iter=300))
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+def test_warm_start_from_solution_converges_at_once():
+    _, lp = scuc.make_instance("small", 1)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-7, max_iter=200000))
+    assert info.term == "solved"
+    info2, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000), x0=x, y0=y)
+    assert info2.term == "solved" and info2.iters < info.iters / 4
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=130), x0=x, y0=y)
+    i3, x3, y3, z3 = hprlp.solve(lp, hprlp.Options(tol=0.0, max_iter=130), x0=x, y0=y)
+    assert_parity(o, i3, x3, y3, z3, FP64_RTOL)
+
+
+def test_repeat_solves_are_bitwise_identical():
+    _, lp = scuc.make_instance("small", 2)
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=1e-6))
+    a = hprlp.hpr_solve(h)
+    xa, ya, za = hprlp.hpr_get_solution(h)
+    b = hprlp.hpr_solve(h)
+    xb, yb, zb = hprlp.hpr_get_solution(h)
+    assert a.iters == b.iters and a.pobj == b.pobj
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(za, zb)
+
+
+def test_get_solution_before_solve_is_a_state_error():
+    _, lp = scuc.make_instance("small", 0)
+    h = hprlp.hpr_create(lp)
+    with pytest.raises(hprlp.HprError) as e:
+        hprlp.hpr_get_solution(h)
+    assert e.value.code == hprlp.HPR_ERR_STATE
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+def test_box_only_lp_without_rows():
+    rng = np.random.default_rng(0)
+    n = 37
+    c = rng.standard_normal(n)
+    l, u = -rng.uniform(0.5, 2, n), rng.uniform(0.5, 2, n)
+    lp = scuc.LP(0, n, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0), np.zeros(0),
+                 np.zeros(0), l, u, c, 1.5)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-10, max_iter=1000))
+    assert info.term == "solved"
+    assert np.allclose(x, np.where(c > 0, l, u), atol=1e-10)
+    o = oracle.solve(lp, oracle.Options(tol=1e-10, max_iter=1000))
+    assert o.iters == info.iters
+
+
+def test_infeasible_lp_is_not_reported_solved():
+    lp = scuc.LP(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.array([1.0, 1.0]),
+                 np.array([3.0]), np.array([np.inf]), np.zeros(2), np.ones(2), np.ones(2))
+    info, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=5000))
+    assert info.term != "solved"
+
+
+def test_single_iteration_and_short_final_block():
+    lp = ragged_lp(3)
+    for K in (1, 3, 64, 127, 129):
+        o, info, x, y, z = run_both(lp, K)
+        assert info.term == "iter_limit" and info.iters == K
+        assert_parity(o, info, x, y, z, FP64_RTOL)
