@@ -115,7 +115,8 @@ def main():
         res[name] = dict(sec=sec, info=info, ks=ks, kkt=ev, x=x)
         log(f"{name}: {info.term} iters={info.iters} restarts={info.restarts} solve={sec:.4f}s "
             f"setup={info.setup_s:.2f}s it/s={info.iters / sec:.0f} rel_kkt(oracle)={ev['rel_kkt']:.2e} "
-            f"pobj={info.pobj:.8g} primal={ks['primal_ms'] * 1e3:.1f}us dual={ks['dual_ms'] * 1e3:.1f}us")
+            f"pobj={info.pobj:.8g} primal={ks['primal_ms'] * 1e3:.1f}us dual={ks['dual_ms'] * 1e3:.1f}us "
+            f"U(A)={ks['unroll_a']} U(At)={ks['unroll_at']}")
         hprlp.hpr_destroy(h)
 
     f32, f64 = res["fp32"], res["fp64"]
@@ -129,7 +130,8 @@ def main():
     roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
-                other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2))
+                other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
+                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"]})
 
     cpu = None
     if not args.no_cpu:

@@ -101,6 +101,9 @@ typedef struct {
     double power_tol;           /* relative change that stops the power method (default 1e-6) */
     int32_t profile;            /* 1: time one primal and one dual kernel per block of
                                    iterations with HIP events (hpr_get_kernel_stats) */
+    int32_t unroll;             /* quads (4 entries) per lane and pass in the matrix products:
+                                   1, 2, 4 or 8; 0 (default) = pick per matrix by timing at
+                                   hpr_create. The choice fixes the summation order. */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 
@@ -123,6 +126,8 @@ typedef struct {
     double primal_ms;
     double dual_ms;
     int64_t samples;
+    int32_t unroll_a;           /* schedule used for A (dual step) */
+    int32_t unroll_at;          /* schedule used for A^T (primal step) */
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

@@ -12,9 +12,9 @@ constexpr int kMaxQ = 8;         // FP64 quantities reduced by one check kernel
 constexpr int kRowQ = 6;         // quantities of the row check
 constexpr int kColQ = 6;         // quantities of the column check
 
-// Rows of one matrix grouped by how many lanes work on a row. Bin b holds rows whose
-// padded length is <= 4 * 2^b (the last bin also takes every longer row); a block of
-// bin b covers kBlock / 2^b rows.
+// Rows of one matrix grouped by how many lanes work on a row. With U quads (4 entries)
+// per lane and pass, bin b holds rows of at most U * 2^b quads (the last bin also takes
+// every longer row, whose lanes then loop); a block of bin b covers kBlock / 2^b rows.
 struct Bins {
     int32_t row_off[kNumBins];       // offset of bin b in the row list
     int32_t nrows[kNumBins];
@@ -32,6 +32,7 @@ struct DevCsr {
     const int32_t* rows;    // row list ordered by bin
     Bins bins;
     int32_t nrows;
+    int32_t unroll;         // U: 1, 2, 4 or 8 quads per lane and pass
 };
 
 // Scalars the iteration reads on the device (written by the host between blocks).

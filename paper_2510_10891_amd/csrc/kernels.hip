@@ -2,9 +2,10 @@
 // dual projection steps of eq.(hpr), FP64 check reductions, and small helpers.
 //
 // Every matrix product walks one stored row per group of G lanes (G = 1..64 by row
-// length). A lane loads 4 values and 4 column indices with 16-byte loads, gathers the
-// 4 vector entries, and the G partial sums are combined with cross-lane shuffles in a
-// fixed order, so results are bitwise repeatable for a given matrix.
+// length). A lane loads quads of 4 values and 4 column indices with 16-byte loads, U
+// quads at a time, gathers the vector entries, and the G partial sums are combined with
+// cross-lane shuffles in a fixed order, so results are bitwise repeatable for a given
+// schedule (G per row and U per matrix).
 #include "internal.h"
 
 #include <math.h>
@@ -50,46 +51,43 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Dot products of stored row [b, e) with one or two gathered vectors; lane `lane` of a
-// group of G lanes takes entries b + 4*lane + 4*G*t.
-template <int G, int NV, typename Tm, typename Tx, typename Acc>
+// Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
+// group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
+// before any gather so U 16-byte loads per array are in flight per lane.
+template <int G, int U, int NV, typename Tm, typename Tx, typename Acc>
 __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int lane,
                                           const Tx* __restrict__ g0, const Tx* __restrict__ g1,
                                           Acc& s0, Acc& s1) {
     s0 = Acc(0);
     s1 = Acc(0);
-    int64_t p = b + kVec * lane;
-    // two quads in flight per lane for long rows
-    for (; p + kVec * G < e; p += 2 * kVec * G) {
-        const int4 c0 = load_idx(A.col + p);
-        const int4 c1 = load_idx(A.col + p + kVec * G);
-        const Quad<Tm> v0 = Quad<Tm>::load(A.val + p);
-        const Quad<Tm> v1 = Quad<Tm>::load(A.val + p + kVec * G);
-        s0 += Acc(v0.a[0]) * Acc(g0[c0.x]) + Acc(v0.a[1]) * Acc(g0[c0.y]) +
-              Acc(v0.a[2]) * Acc(g0[c0.z]) + Acc(v0.a[3]) * Acc(g0[c0.w]);
-        s0 += Acc(v1.a[0]) * Acc(g0[c1.x]) + Acc(v1.a[1]) * Acc(g0[c1.y]) +
-              Acc(v1.a[2]) * Acc(g0[c1.z]) + Acc(v1.a[3]) * Acc(g0[c1.w]);
-        if constexpr (NV == 2) {
-            s1 += Acc(v0.a[0]) * Acc(g1[c0.x]) + Acc(v0.a[1]) * Acc(g1[c0.y]) +
-                  Acc(v0.a[2]) * Acc(g1[c0.z]) + Acc(v0.a[3]) * Acc(g1[c0.w]);
-            s1 += Acc(v1.a[0]) * Acc(g1[c1.x]) + Acc(v1.a[1]) * Acc(g1[c1.y]) +
-                  Acc(v1.a[2]) * Acc(g1[c1.z]) + Acc(v1.a[3]) * Acc(g1[c1.w]);
+    for (int64_t p = b + kVec * lane; p < e; p += (int64_t)kVec * G * U) {
+        int4 c[U];
+        Quad<Tm> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = p + (int64_t)kVec * G * u;
+            if (q < e) {
+                c[u] = load_idx(A.col + q);
+                v[u] = Quad<Tm>::load(A.val + q);
+            }
         }
-    }
-    if (p < e) {
-        const int4 c0 = load_idx(A.col + p);
-        const Quad<Tm> v0 = Quad<Tm>::load(A.val + p);
-        s0 += Acc(v0.a[0]) * Acc(g0[c0.x]) + Acc(v0.a[1]) * Acc(g0[c0.y]) +
-              Acc(v0.a[2]) * Acc(g0[c0.z]) + Acc(v0.a[3]) * Acc(g0[c0.w]);
-        if constexpr (NV == 2) {
-            s1 += Acc(v0.a[0]) * Acc(g1[c0.x]) + Acc(v0.a[1]) * Acc(g1[c0.y]) +
-                  Acc(v0.a[2]) * Acc(g1[c0.z]) + Acc(v0.a[3]) * Acc(g1[c0.w]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = p + (int64_t)kVec * G * u;
+            if (q < e) {
+                s0 += Acc(v[u].a[0]) * Acc(g0[c[u].x]) + Acc(v[u].a[1]) * Acc(g0[c[u].y]) +
+                      Acc(v[u].a[2]) * Acc(g0[c[u].z]) + Acc(v[u].a[3]) * Acc(g0[c[u].w]);
+                if constexpr (NV == 2) {
+                    s1 += Acc(v[u].a[0]) * Acc(g1[c[u].x]) + Acc(v[u].a[1]) * Acc(g1[c[u].y]) +
+                          Acc(v[u].a[2]) * Acc(g1[c[u].z]) + Acc(v[u].a[3]) * Acc(g1[c[u].w]);
+                }
+            }
         }
     }
 }
 
 // One block of bin `bin`: each group of G lanes takes one row of the bin's row list.
-template <int G, typename Op>
+template <int G, int U, typename Op>
 __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, int bin, int lb) {
     using Acc = typename Op::Acc;
     const int lane = threadIdx.x & (G - 1);
@@ -100,7 +98,7 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     const int64_t b = active ? A.start[row] : 0;
     const int64_t e = active ? A.start[row + 1] : 0;
     Acc s0, s1;
-    group_dot<G, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
+    group_dot<G, U, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
     s0 = group_sum<G>(s0);
     if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
     if (active && lane == 0) op.epi(row, s0, s1);
@@ -124,7 +122,7 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
     }
 }
 
-template <typename Op>
+template <typename Op, int U>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
     Op op = op_in;
     op.init();
@@ -135,13 +133,13 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
         if (blk >= A.bins.block_off[b]) bin = b;
     const int lb = blk - A.bins.block_off[bin];
     switch (bin) {
-        case 0: run_bin<1>(A, op, bin, lb); break;
-        case 1: run_bin<2>(A, op, bin, lb); break;
-        case 2: run_bin<4>(A, op, bin, lb); break;
-        case 3: run_bin<8>(A, op, bin, lb); break;
-        case 4: run_bin<16>(A, op, bin, lb); break;
-        case 5: run_bin<32>(A, op, bin, lb); break;
-        default: run_bin<64>(A, op, bin, lb); break;
+        case 0: run_bin<1, U>(A, op, bin, lb); break;
+        case 1: run_bin<2, U>(A, op, bin, lb); break;
+        case 2: run_bin<4, U>(A, op, bin, lb); break;
+        case 3: run_bin<8, U>(A, op, bin, lb); break;
+        case 4: run_bin<16, U>(A, op, bin, lb); break;
+        case 5: run_bin<32, U>(A, op, bin, lb); break;
+        default: run_bin<64, U>(A, op, bin, lb); break;
     }
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
@@ -150,7 +148,12 @@ template <typename Op>
 static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st) {
     const int nb = A.bins.block_off[kNumBins];
     if (nb <= 0) return;
-    hipLaunchKernelGGL(csr_kernel<Op>, dim3(nb), dim3(kBlock), 0, st, A, op);
+    switch (A.unroll) {
+        case 1: hipLaunchKernelGGL((csr_kernel<Op, 1>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+        case 2: hipLaunchKernelGGL((csr_kernel<Op, 2>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+        case 8: hipLaunchKernelGGL((csr_kernel<Op, 8>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+        default: hipLaunchKernelGGL((csr_kernel<Op, 4>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+    }
 }
 
 template <typename T>

@@ -118,36 +118,22 @@ static HostCsr transpose(const HostCsr& a) {
     return t;
 }
 
-// Padded, binned layout of one matrix (structure on the host, ready for upload).
+// Padded layout of one matrix (structure on the host, ready for upload).
 struct Layout {
     std::vector<int64_t> start;
     std::vector<int32_t> col;
     std::vector<double> val;
-    std::vector<int32_t> rows;
-    Bins bins{};
 };
-
-static int bin_of(int64_t padded_len) {
-    int64_t groups = padded_len / kVec;   // quads in the row
-    int b = 0;
-    while (b < kNumBins - 1 && (int64_t(1) << b) < groups) ++b;
-    return b;
-}
 
 static Layout make_layout(const HostCsr& a) {
     Layout L;
     const int32_t R = a.rows;
     L.start.resize((size_t)R + 1);
     int64_t off = 0;
-    std::vector<int> bin(R);
-    std::vector<int32_t> count(kNumBins, 0);
     for (int32_t i = 0; i < R; ++i) {
         L.start[i] = off;
         const int64_t len = a.ptr[i + 1] - a.ptr[i];
-        const int64_t pad = (len + kVec - 1) / kVec * kVec;
-        off += pad;
-        bin[i] = bin_of(pad);
-        count[bin[i]]++;
+        off += (len + kVec - 1) / kVec * kVec;
     }
     L.start[R] = off;
     L.col.resize(off);
@@ -164,39 +150,67 @@ static Layout make_layout(const HostCsr& a) {
             L.val[d] = 0.0;
         }
     }
-    L.rows.resize(R);
+    return L;
+}
+
+// Lane-group bins for U quads per lane and pass: bin b takes rows of at most U * 2^b quads.
+static void make_bins(const std::vector<int64_t>& start, int U, std::vector<int32_t>& rows, Bins& bins) {
+    const int32_t R = (int32_t)start.size() - 1;
+    std::vector<uint8_t> bin((size_t)R);
+    int32_t count[kNumBins] = {0};
+    for (int32_t i = 0; i < R; ++i) {
+        const int64_t quads = (start[i + 1] - start[i]) / kVec;
+        int b = 0;
+        while (b < kNumBins - 1 && (int64_t)U * (int64_t(1) << b) < quads) ++b;
+        bin[i] = (uint8_t)b;
+        count[b]++;
+    }
     int32_t roff = 0, boff = 0;
     for (int b = 0; b < kNumBins; ++b) {
-        L.bins.row_off[b] = roff;
-        L.bins.nrows[b] = count[b];
-        L.bins.block_off[b] = boff;
+        bins.row_off[b] = roff;
+        bins.nrows[b] = count[b];
+        bins.block_off[b] = boff;
         const int per_block = kBlock >> b;
         boff += (count[b] + per_block - 1) / per_block;
         roff += count[b];
     }
-    L.bins.block_off[kNumBins] = boff;
-    std::vector<int32_t> pos(L.bins.row_off, L.bins.row_off + kNumBins);
-    for (int32_t i = 0; i < R; ++i) L.rows[pos[bin[i]]++] = i;
-    return L;
+    bins.block_off[kNumBins] = boff;
+    rows.resize((size_t)R);
+    int32_t pos[kNumBins];
+    for (int b = 0; b < kNumBins; ++b) pos[b] = bins.row_off[b];
+    for (int32_t i = 0; i < R; ++i) rows[pos[bin[i]]++] = i;
 }
 
 // Device copy of a layout: shared structure plus FP64 and (optionally) FP32 values.
 struct DevMatrix {
     DBuf start, col, rows, val64, val32;
+    std::vector<int64_t> start_h;   // host copy of the offsets (rebinning)
     Bins bins{};
     int32_t nrows = 0;
+    int32_t unroll = 4;
     int64_t padded = 0;
     void upload_from(const Layout& L, bool fp32, hipStream_t st) {
-        nrows = (int32_t)L.rows.size();
+        nrows = (int32_t)L.start.size() - 1;
         padded = (int64_t)L.col.size();
-        bins = L.bins;
+        start_h = L.start;
         upload(start, L.start, st);
         upload(col, L.col, st);
-        upload(rows, L.rows, st);
         upload(val64, L.val, st);
         if (fp32) {
             val32.alloc(L.val.size() * sizeof(float));
             launch_cast<float>(val64.as<double>(), val32.as<float>(), (int64_t)L.val.size(), st);
+        }
+        rows.alloc(sizeof(int32_t) * std::max(nrows, 1));
+        set_unroll(4, st);
+    }
+    // rebuild the bins for U quads per lane and upload the row list
+    void set_unroll(int U, hipStream_t st) {
+        std::vector<int32_t> r;
+        make_bins(start_h, U, r, bins);
+        unroll = U;
+        if (!r.empty()) {
+            HIP_OK(hipMemcpyAsync(rows.p, r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, st));
+            HIP_OK(hipStreamSynchronize(st));
         }
     }
     template <typename T>
@@ -208,6 +222,7 @@ struct DevMatrix {
         d.rows = rows.as<int32_t>();
         d.bins = bins;
         d.nrows = nrows;
+        d.unroll = unroll;
         return d;
     }
 };
@@ -261,6 +276,8 @@ static int validate_opts(const hpr_opts* o) {
     if (o->power_max_iter < 1) return fail(HPR_ERR_INVALID, "power_max_iter must be >= 1");
     if (std::isnan(o->lambda)) return fail(HPR_ERR_INVALID, "lambda is NaN");
     if ((o->scaling & HPR_SCALE_RUIZ) && o->ruiz_iters < 0) return fail(HPR_ERR_INVALID, "ruiz_iters < 0");
+    if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
+        return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
     return HPR_OK;
 }
 
@@ -350,6 +367,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->power_max_iter = 200;
     o->power_tol = 1e-6;
     o->profile = 0;
+    o->unroll = 0;
     o->stream = nullptr;
 }
 
@@ -516,10 +534,6 @@ static void alloc_iterates(hpr_handle* h) {
     const size_t n = (size_t)h->n, m = (size_t)std::max(h->m, 1);
     for (DBuf* b : {&h->x, &h->x0, &h->xh, &h->xb, &h->zb, &h->dx}) b->alloc(es * n);
     for (DBuf* b : {&h->y, &h->y0, &h->yb, &h->dy}) b->alloc(es * m);
-    const int nbr = std::max(h->A.bins.block_off[kNumBins], 1);
-    const int nbc = std::max(h->At.bins.block_off[kNumBins], 1);
-    h->part_r.alloc(sizeof(double) * kRowQ * nbr);
-    h->part_c.alloc(sizeof(double) * kColQ * nbc);
     h->sums.alloc(sizeof(double) * 2 * kMaxQ);
     h->ctrl.alloc(sizeof(Ctrl));
     h->ux.alloc(sizeof(double) * n);
@@ -527,6 +541,70 @@ static void alloc_iterates(hpr_handle* h) {
     h->uz.alloc(sizeof(double) * n);
     HIP_OK(hipHostMalloc((void**)&h->pinned, sizeof(double) * 2 * kMaxQ, hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void**)&h->ctrl_h, sizeof(Ctrl), hipHostMallocDefault));
+}
+
+// per-block partial sums of the check kernels (block counts depend on the bins)
+static void alloc_partials(hpr_handle* h) {
+    const int nbr = std::max(h->A.bins.block_off[kNumBins], 1);
+    const int nbc = std::max(h->At.bins.block_off[kNumBins], 1);
+    h->part_r.alloc(sizeof(double) * kRowQ * nbr);
+    h->part_c.alloc(sizeof(double) * kColQ * nbc);
+}
+
+// Schedule tuner: for each matrix, time the fused step kernel that streams it (dual step
+// for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass (the bins
+// follow U), and keep the fastest. A forced opts.unroll skips the timing.
+template <typename T>
+static void autotune(hpr_handle* h) {
+    hipStream_t st = h->st;
+    const size_t es = sizeof(T);
+    for (DBuf* b : {&h->x, &h->x0, &h->xh, &h->xb, &h->zb, &h->dx, &h->y, &h->y0, &h->yb, &h->dy})
+        HIP_OK(hipMemsetAsync(b->p, 0, b->bytes, st));
+    (void)es;
+    h->ctrl_h->sigma = 1.0;
+    h->ctrl_h->s = 1.0;
+    h->ctrl_h->lambda = 1.0;
+    h->ctrl_h->k_base = 0;
+    HIP_OK(hipMemcpyAsync(h->ctrl.p, h->ctrl_h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+    const int forced = h->opts.unroll;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const DevProb<T> p = h->prob<T>();
+    const DevIter<T> v = h->iter<T>();
+    for (int which = 0; which < 2; ++which) {
+        DevMatrix& M = which == 0 ? h->A : h->At;
+        if (forced) {
+            M.set_unroll(forced, st);
+            continue;
+        }
+        if (M.nrows == 0) continue;
+        int bestU = 4;
+        float best = 1e30f;
+        for (int U : {1, 2, 4, 8}) {
+            M.set_unroll(U, st);
+            const DevCsr<T> view = M.view<T>();
+            auto launch = [&]() {
+                if (which == 0) launch_dual_step<T>(view, p, v, h->ctrl.as<Ctrl>(), 0, false, st);
+                else launch_primal_step<T>(view, p, v, h->ctrl.as<Ctrl>(), 0, false, st);
+            };
+            for (int r = 0; r < 2; ++r) launch();
+            HIP_OK(hipEventRecord(e0, st));
+            for (int r = 0; r < 8; ++r) launch();
+            HIP_OK(hipEventRecord(e1, st));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bestU = U;
+            }
+        }
+        M.set_unroll(bestU, st);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_OK(hipGetLastError());
 }
 
 extern "C" int hpr_create(const hpr_lp* lp, const hpr_opts* opts_in, hpr_handle** out) {
@@ -572,6 +650,9 @@ extern "C" int hpr_create(const hpr_lp* lp, const hpr_opts* opts_in, hpr_handle*
             sync(h.get());   // host layouts are freed at scope end
         }
         alloc_iterates(h.get());
+        if (h->fp32) autotune<float>(h.get());
+        else autotune<double>(h.get());
+        alloc_partials(h.get());
         h->lambda = o.lambda > 0 ? o.lambda : power_method(h.get());
         sync(h.get());
     } catch (const HipError& e) {
@@ -852,6 +933,8 @@ extern "C" int hpr_get_kernel_stats(hpr_handle* h, hpr_kernel_stats* out) {
     g_err.clear();
     if (!h || !out) return fail(HPR_ERR_INVALID, "handle or out is NULL");
     *out = h->kstats;
+    out->unroll_a = h->A.unroll;
+    out->unroll_at = h->At.unroll;
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;

@@ -40,11 +40,12 @@ class hpr_opts(C.Structure):
                 ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("unroll", C.c_int32), ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
-    _fields_ = [("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64)]
+    _fields_ = [("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
+                ("unroll_a", C.c_int32), ("unroll_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -102,6 +103,7 @@ class Options:
     power_max_iter: int = 200
     power_tol: float = 1e-6
     profile: int = 0
+    unroll: int = 0
     stream: int = 0
 
     def to_c(self) -> hpr_opts:
@@ -216,7 +218,8 @@ def hpr_get_solution(h: Handle):
 def hpr_get_kernel_stats(h: Handle) -> dict:
     s = hpr_kernel_stats()
     _check(lib().hpr_get_kernel_stats(h.ptr, C.byref(s)))
-    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples)
+    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
+                unroll_at=s.unroll_at)
 
 
 def solve(lp, opts: Options | None = None, x0=None, y0=None):

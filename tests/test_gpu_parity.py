@@ -55,9 +55,9 @@ def ragged_lp(seed, m=400, n=900, bounded=True):
                    lo, hi, l, u, c, 0.25)
 
 
-def run_both(lp, K, precision=hprlp.HPR_FP64, **kw):
+def run_both(lp, K, precision=hprlp.HPR_FP64, unroll=0, **kw):
     o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, **kw))
-    opts = hprlp.Options(tol=0.0, max_iter=K, precision=precision,
+    opts = hprlp.Options(tol=0.0, max_iter=K, precision=precision, unroll=unroll,
                          **{("lambda_" if k == "lambda_in" else k): v for k, v in kw.items()
                             if k not in ("use_pc", "use_bc", "ruiz_iters")})
     if "use_pc" in kw or "use_bc" in kw or "ruiz_iters" in kw:
@@ -94,6 +94,21 @@ def test_fp64_iterates_match_oracle_ragged(seed, K):
     lp = ragged_lp(seed, bounded=(seed == 0))
     o, info, x, y, z = run_both(lp, K)
     assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+@pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
+def test_every_schedule_matches_oracle(unroll, precision):
+    """Each lane-group schedule (U quads per lane and pass, bins following U)."""
+    lp = ragged_lp(4, bounded=False)
+    K = 130 if precision == hprlp.HPR_FP64 else 2
+    o, info, x, y, z = run_both(lp, K, precision=precision, unroll=unroll)
+    if precision == hprlp.HPR_FP64:
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+    else:
+        assert info.iters == o.iters
+        assert_close(x, o.x, FP32_RTOL * 20, "x")
+        assert_close(y, o.y, FP32_RTOL * 20, "y")
 
 
 @pytest.mark.parametrize("K", [1, 65, 1000])
