@@ -104,6 +104,9 @@ typedef struct {
     int32_t unroll;             /* quads (4 entries) per lane and pass in the matrix products:
                                    1, 2, 4 or 8; 0 (default) = pick per matrix by timing at
                                    hpr_create. The choice fixes the summation order. */
+    int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
+                                   its check and its control step as one captured HIP graph;
+                                   0: launch every kernel directly */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 
@@ -160,6 +163,52 @@ int hpr_get_kernel_stats(hpr_handle *h, hpr_kernel_stats *out);
 
 /* Frees the handle and its device memory. NULL is accepted. */
 int hpr_destroy(hpr_handle *h);
+
+/* ---- batches: many LPs solved together (the reduced LPs of successive-fixing rounds,
+ * Algorithm 2, or of several scenarios). The LPs are pooled into one block-diagonal
+ * problem: every kernel launch covers all of them, each LP keeps its own scaling, lambda,
+ * sigma, restarts, checks and termination (decided on the device), and an LP that has
+ * finished costs nothing in later launches. Each LP follows exactly the schedule and rules
+ * of a single solve with the same options. */
+typedef struct hpr_batch hpr_batch;
+
+/* lps: array of `count` LPs (1 <= count <= 1024), same rules as hpr_create. */
+int hpr_batch_create(const hpr_lp *lps, int32_t count, const hpr_opts *opts, hpr_batch **out);
+int hpr_batch_size(hpr_batch *b, int32_t *count);
+/* As hpr_set_bounds / hpr_set_start for LP i (0-based). */
+int hpr_batch_set_bounds(hpr_batch *b, int32_t i, const double *col_lo, const double *col_hi);
+int hpr_batch_set_start(hpr_batch *b, int32_t i, const double *x0, const double *y0);
+/* Solves every LP; infos has `count` entries (solve_s is the wall time of the batch). */
+int hpr_batch_solve(hpr_batch *b, hpr_info *infos);
+/* As hpr_get_solution for LP i. */
+int hpr_batch_get_solution(hpr_batch *b, int32_t i, double *x, double *y, double *z);
+int hpr_batch_get_kernel_stats(hpr_batch *b, hpr_kernel_stats *out);
+/* Frees the batch. NULL is accepted. */
+int hpr_batch_destroy(hpr_batch *b);
+
+/* ---- warm-start network: a multilayer perceptron whose forward pass, gradients and
+ * Adam step run on the GPU (BF16 weights and activations on the matrix cores with FP32
+ * accumulation, FP32 master weights and moments). Layer i: z_i = h_i W_i + b_i with
+ * h_{i+1} = max(z_i, 0) except after the last layer; loss 0.5 * mean (out - target)^2.
+ * Parameters are one FP32 array: for each layer, W_i (sizes[i] x sizes[i+1], row-major)
+ * then b_i (sizes[i+1]). Inputs, targets and outputs are host arrays, row-major. Errors
+ * of these calls are reported by hpr_mlp_last_error(). */
+typedef struct hpr_mlp hpr_mlp;
+
+/* nlayers in [1, 8]; sizes[0..nlayers] in [1, 4096]; params may be NULL (all zero). */
+int hpr_mlp_create(int32_t nlayers, const int32_t *sizes, const float *params, void *stream, hpr_mlp **out);
+int hpr_mlp_num_params(hpr_mlp *q, int64_t *n);
+/* Replaces the parameters and resets the Adam moments and step count. */
+int hpr_mlp_set_params(hpr_mlp *q, const float *params);
+int hpr_mlp_get_params(hpr_mlp *q, float *params);
+/* Y [n][sizes[nlayers]] = network(X [n][sizes[0]]). */
+int hpr_mlp_forward(hpr_mlp *q, const float *X, int64_t n, float *Y);
+/* Loss and gradients (same layout as the parameters; grads may be NULL) for targets T. */
+int hpr_mlp_gradients(hpr_mlp *q, const float *X, const float *T, int64_t n, float *grads, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) on the mini-batch (X, T). */
+int hpr_mlp_train_step(hpr_mlp *q, const float *X, const float *T, int64_t n, float lr, float *loss);
+int hpr_mlp_destroy(hpr_mlp *q);
+const char *hpr_mlp_last_error(void);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *hpr_last_error(void);

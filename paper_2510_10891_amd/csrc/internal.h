@@ -1,4 +1,9 @@
 // Internal device data layout and kernel launchers of the gfx950 LP solver.
+//
+// One engine serves a single LP and a batch alike: the LPs of a batch are pooled into one
+// block-diagonal problem (rows and columns of LP l occupy contiguous ranges), each kernel
+// launch covers every LP, and per-LP scalars live in device arrays indexed by the LP id
+// that each thread block carries in its descriptor.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,39 +13,55 @@ namespace hpr {
 constexpr int kBlock = 256;      // threads per block: 4 wavefronts of 64 lanes
 constexpr int kNumBins = 7;      // lanes per row: 1, 2, 4, 8, 16, 32, 64
 constexpr int kVec = 4;          // every stored row is padded to a multiple of 4 entries
-constexpr int kMaxQ = 8;         // FP64 quantities reduced by one check kernel
-constexpr int kRowQ = 6;         // quantities of the row check
-constexpr int kColQ = 6;         // quantities of the column check
+constexpr int kRowQ = 6;         // FP64 quantities of the row check
+constexpr int kColQ = 6;         // FP64 quantities of the column check
+constexpr int kSumStride = 16;   // per-LP sums: [0, kRowQ) rows, [8, 8 + kColQ) columns
+constexpr int kChunk = 8192;     // entries per block of the segmented vector kernels
+constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 
-// Rows of one matrix grouped by how many lanes work on a row. With U quads (4 entries)
-// per lane and pass, bin b holds rows of at most U * 2^b quads (the last bin also takes
-// every longer row, whose lanes then loop); a block of bin b covers kBlock / 2^b rows.
-struct Bins {
-    int32_t row_off[kNumBins];       // offset of bin b in the row list
-    int32_t nrows[kNumBins];
-    int32_t block_off[kNumBins + 1]; // first block of bin b; [kNumBins] = total blocks
+// One thread block of a matrix product: rows list[first .. first + count) of bin `bin`
+// (2^bin lanes per row), all belonging to LP `lp`.
+struct BlockDesc {
+    int32_t bin;
+    int32_t lp;
+    int32_t first;
+    int32_t count;
 };
 
 // A sparse matrix on the device: CSR whose rows start at multiples of 4 entries, so a
 // lane reads 4 values and 4 column indices with 16-byte loads. Padding entries carry
-// value 0 and a column index the row already uses.
+// value 0 and a column index the row already uses. Column indices are global (pooled).
 template <typename Tm>
 struct DevCsr {
-    const int64_t* start;   // [rows + 1]
-    const int32_t* col;     // [padded nnz]
-    const Tm* val;          // [padded nnz]
-    const int32_t* rows;    // row list ordered by bin
-    Bins bins;
-    int32_t nrows;
-    int32_t unroll;         // U: 1, 2, 4 or 8 quads per lane and pass
+    const int64_t* start;      // [rows + 1]
+    const int32_t* col;        // [padded nnz]
+    const Tm* val;             // [padded nnz]
+    const int32_t* rows;       // row list in schedule order
+    const BlockDesc* sched;    // [nblocks]
+    int32_t nblocks;
+    int32_t unroll;            // U: 1, 2, 4 or 8 quads per lane and pass
 };
 
-// Scalars the iteration reads on the device (written by the host between blocks).
+// Per-LP scalars read by the iteration kernels.
 struct Ctrl {
     double sigma;       // primal step
     double s;           // dual step 1 / (lambda sigma)
     double lambda;
+    double beta_b, beta_c;
     int64_t k_base;     // Halpern counter at the first iteration of the current block
+    int32_t active;     // 0: finished, the LP's blocks return at once
+    int32_t restart;    // 1: copy the bar point into anchor and iterate (set at a check)
+};
+
+// Per-LP control state of the check logic (device-resident, read back at the end).
+struct LpState {
+    double r0, r_prev;           // merit at the last restart and at the previous check
+    double norm_b, norm_c, obj_offset;
+    double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit;
+    double p32[6];               // FP32-storage check values kept while FP64 confirms them
+    int64_t it, k, restarts;
+    int32_t term;                // 0 running, else HPR_SOLVED ...
+    int32_t candidate;           // FP32 check passed, awaiting FP64 confirmation
 };
 
 // Problem vectors of the scaled LP (type Tp) and the diagonal scaling (FP64).
@@ -58,7 +79,7 @@ struct DevIter {
     Tv *y, *y0, *yb, *dy;             // [m] iterate, anchor, bar point, y - ybar
 };
 
-// Launchers (kernels.hip). All run on `st`.
+// Launchers (kernels.hip). All run on `st` and may be captured into a graph.
 template <typename T>
 void launch_primal_step(const DevCsr<T>& At, const DevProb<T>& p, const DevIter<T>& v, const Ctrl* ctrl,
                         int j, bool check, hipStream_t st);
@@ -67,31 +88,53 @@ void launch_dual_step(const DevCsr<T>& A, const DevProb<T>& p, const DevIter<T>&
                       int j, bool check, hipStream_t st);
 // Check kernels: per-block FP64 partial sums into partials [quantity][nblocks].
 template <typename Tm, typename Tp, typename Tv>
-void launch_check_rows(const DevCsr<Tm>& A, const DevProb<Tp>& p, const DevIter<Tv>& v, double beta_b,
+void launch_check_rows(const DevCsr<Tm>& A, const DevProb<Tp>& p, const DevIter<Tv>& v, const Ctrl* ctrl,
                        double* partials, hipStream_t st);
 template <typename Tm, typename Tp, typename Tv>
-void launch_check_cols(const DevCsr<Tm>& At, const DevProb<Tp>& p, const DevIter<Tv>& v, double beta_c,
+void launch_check_cols(const DevCsr<Tm>& At, const DevProb<Tp>& p, const DevIter<Tv>& v, const Ctrl* ctrl,
                        double* partials, hipStream_t st);
-// Sums partials [nq][nblocks] in a fixed order into out[nq] (one block per quantity).
-void launch_finish_sums(const double* partials, int nq, int nblocks, double* out, hipStream_t st);
+// out[l * kSumStride + off + q] = sum of partials[q][seg[l] .. seg[l+1]) in a fixed order.
+void launch_finish_sums(const double* partials, int nq, int nblocks, const int32_t* seg, int nlp,
+                        double* out, int off, hipStream_t st);
+// Copies the bar point into anchor and iterate for the LPs whose Ctrl::restart is set.
+template <typename T>
+void launch_restart(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v, const Ctrl* ctrl,
+                    hipStream_t st);
+// The per-LP decisions of a check (one thread per LP); phase 1 after the storage-precision
+// check, phase 2 after an FP64 confirmation of candidates, phase 3 stores FP64 values
+// for reporting, phase 4 ends every running LP at the time limit.
+struct ControlArgs {
+    Ctrl* ctrl;
+    LpState* st;
+    const double* sums;      // storage-precision check sums [nlp][kSumStride]
+    const double* sums64;    // FP64 check sums (phases 2, 3)
+    int32_t* stat;           // [0] running LPs, [1] candidates
+    int nlp;
+    int nb;                  // iterations in the block just run (phase 1)
+    int fp32;
+    int phase;
+    int64_t max_iter;
+    double tol;
+    int restart_rule;
+    int sigma_update;
+};
+void launch_control(const ControlArgs& a, hipStream_t st);
 // y = A x (plain product, used by the power method).
 template <typename T>
 void launch_spmv(const DevCsr<T>& A, const T* x, T* y, hipStream_t st);
-// partials[b] = sum of v_i^2 over block b's slice (FP64); nblocks = sumsq_blocks(n).
-template <typename T>
-void launch_sumsq(const T* v, int64_t n, double* partials, hipStream_t st);
-int sumsq_blocks(int64_t n);
-template <typename T>
-void launch_scale(T* v, int64_t n, double factor, hipStream_t st);
-template <typename T>
-void launch_start_vector(T* v, int64_t n, uint64_t seed, hipStream_t st);
-// x0 = x = xb ; y0 = y = yb
-template <typename T>
-void launch_restart(const DevIter<T>& v, int n, int m, hipStream_t st);
+// Segmented vector kernels over pooled ranges seg[0..nlp] (entries of LP l in [seg[l], seg[l+1])):
+// partials[l * max_chunks + c] = sum of squares of chunk c of LP l; start vector from SplitMix64
+// with LP-local indices; scale by factor[l].
+void launch_seg_sumsq(const double* v, const int64_t* seg, int nlp, int max_chunks, double* partials,
+                      hipStream_t st);
+void launch_seg_start_vector(double* v, const int64_t* seg, int nlp, int max_chunks, uint64_t seed,
+                             hipStream_t st);
+void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, const double* factor,
+                      hipStream_t st);
 // original-space point: x = beta_b dc xb, y = beta_c dr yb, z = beta_c zb / dc (FP64 out)
 template <typename T>
-void launch_unscale(const DevIter<T>& v, const double* dr, const double* dc, int n, int m, double beta_b,
-                    double beta_c, double* x, double* y, double* z, hipStream_t st);
+void launch_unscale(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v, const double* dr,
+                    const double* dc, const Ctrl* ctrl, double* x, double* y, double* z, hipStream_t st);
 // FP64 -> T copy
 template <typename T>
 void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st);

@@ -1,5 +1,6 @@
 // gfx950 kernels of the LP iteration: binned CSR products fused with the primal and
-// dual projection steps of eq.(hpr), FP64 check reductions, and small helpers.
+// dual projection steps of eq.(hpr), FP64 check reductions, the per-LP control of the
+// checks (restart, sigma, termination), and small helpers.
 //
 // Every matrix product walks one stored row per group of G lanes (G = 1..64 by row
 // length). A lane loads quads of 4 values and 4 column indices with 16-byte loads, U
@@ -86,21 +87,22 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
     }
 }
 
-// One block of bin `bin`: each group of G lanes takes one row of the bin's row list.
+// One block: each group of G lanes takes one row of the block's slice of the row list.
 template <int G, int U, typename Op>
-__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, int bin, int lb) {
+__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d) {
     using Acc = typename Op::Acc;
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int r = lb * (kBlock / G) + grp;
-    const bool active = r < A.bins.nrows[bin];
-    const int row = active ? A.rows[A.bins.row_off[bin] + r] : 0;
-    const int64_t b = active ? A.start[row] : 0;
-    const int64_t e = active ? A.start[row + 1] : 0;
-    Acc s0, s1;
-    group_dot<G, U, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
-    s0 = group_sum<G>(s0);
-    if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
+    const bool active = grp < d.count;
+    const int row = active ? A.rows[d.first + grp] : 0;
+    Acc s0 = Acc(0), s1 = Acc(0);
+    if constexpr (Op::NV > 0) {
+        const int64_t b = active ? A.start[row] : 0;
+        const int64_t e = active ? A.start[row + 1] : 0;
+        group_dot<G, U, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
+        s0 = group_sum<G>(s0);
+        if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
+    }
     if (active && lane == 0) op.epi(row, s0, s1);
 }
 
@@ -122,31 +124,27 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
     }
 }
 
+// Ops with NQ > 0 (reductions) never skip a block: every block writes its partials.
 template <typename Op, int U>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
+    const BlockDesc d = A.sched[blockIdx.x];
     Op op = op_in;
-    op.init();
-    const int blk = blockIdx.x;
-    int bin = 0;
-#pragma unroll
-    for (int b = 1; b < kNumBins; ++b)
-        if (blk >= A.bins.block_off[b]) bin = b;
-    const int lb = blk - A.bins.block_off[bin];
-    switch (bin) {
-        case 0: run_bin<1, U>(A, op, bin, lb); break;
-        case 1: run_bin<2, U>(A, op, bin, lb); break;
-        case 2: run_bin<4, U>(A, op, bin, lb); break;
-        case 3: run_bin<8, U>(A, op, bin, lb); break;
-        case 4: run_bin<16, U>(A, op, bin, lb); break;
-        case 5: run_bin<32, U>(A, op, bin, lb); break;
-        default: run_bin<64, U>(A, op, bin, lb); break;
+    if (!op.init(d)) return;
+    switch (d.bin) {
+        case 0: run_bin<1, U>(A, op, d); break;
+        case 1: run_bin<2, U>(A, op, d); break;
+        case 2: run_bin<4, U>(A, op, d); break;
+        case 3: run_bin<8, U>(A, op, d); break;
+        case 4: run_bin<16, U>(A, op, d); break;
+        case 5: run_bin<32, U>(A, op, d); break;
+        default: run_bin<64, U>(A, op, d); break;
     }
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
 
 template <typename Op>
 static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st) {
-    const int nb = A.bins.block_off[kNumBins];
+    const int nb = A.nblocks;
     if (nb <= 0) return;
     switch (A.unroll) {
         case 1: hipLaunchKernelGGL((csr_kernel<Op, 1>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
@@ -180,11 +178,14 @@ struct PrimalOp {
     T sigma, a0, a1;
     double q[1];
     double* partials;
-    __device__ __forceinline__ void init() {
-        const int64_t k = ctrl->k_base + j;
-        sigma = T(ctrl->sigma);
+    __device__ __forceinline__ bool init(const BlockDesc& d) {
+        const Ctrl& c = ctrl[d.lp];
+        if (!c.active) return false;
+        const int64_t k = c.k_base + j;
+        sigma = T(c.sigma);
         a0 = T(1.0 / double(k + 2));
         a1 = T(double(k + 1) / double(k + 2));
+        return true;
     }
     __device__ __forceinline__ void epi(int col, T aty, T) {
         const T xk = v.x[col];
@@ -222,11 +223,14 @@ struct DualOp {
     T s, a0, a1;
     double q[1];
     double* partials;
-    __device__ __forceinline__ void init() {
-        const int64_t k = ctrl->k_base + j;
-        s = T(ctrl->s);
+    __device__ __forceinline__ bool init(const BlockDesc& d) {
+        const Ctrl& c = ctrl[d.lp];
+        if (!c.active) return false;
+        const int64_t k = c.k_base + j;
+        s = T(c.s);
         a0 = T(1.0 / double(k + 2));
         a1 = T(double(k + 1) / double(k + 2));
+        return true;
     }
     __device__ __forceinline__ void epi(int row, T ax, T) {
         const T yk = v.y[row];
@@ -260,12 +264,15 @@ struct CheckRowsOp {
     const V* g1;
     DevProb<P> p;
     DevIter<V> v;
+    const Ctrl* ctrl;
     double beta_b;
     double q[NQ];
     double* partials;
-    __device__ __forceinline__ void init() {
+    __device__ __forceinline__ bool init(const BlockDesc& d) {
+        beta_b = ctrl[d.lp].beta_b;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+        return true;
     }
     __device__ __forceinline__ void epi(int row, M ax, M adx) {
         const double a = double(ax);
@@ -301,12 +308,15 @@ struct CheckColsOp {
     const V* g1;
     DevProb<P> p;
     DevIter<V> v;
+    const Ctrl* ctrl;
     double beta_c;
     double q[NQ];
     double* partials;
-    __device__ __forceinline__ void init() {
+    __device__ __forceinline__ bool init(const BlockDesc& d) {
+        beta_c = ctrl[d.lp].beta_c;
 #pragma unroll
         for (int k = 0; k < NQ; ++k) q[k] = 0.0;
+        return true;
     }
     __device__ __forceinline__ void epi(int col, M aty, M) {
         const double c = double(p.c[col]);
@@ -326,6 +336,64 @@ struct CheckColsOp {
     }
 };
 
+// ---------------------------------------------------------------- per-row bookkeeping (no product)
+
+// restart of LP d.lp: anchor = iterate = bar point (rows: y; columns: x)
+template <typename T, bool ROWS>
+struct RestartOp {
+    using Tm = T;
+    using Acc = T;
+    static constexpr int NV = 0, NQ = 0;
+    const T* g0;
+    const T* g1;
+    DevIter<T> v;
+    const Ctrl* ctrl;
+    double q[1];
+    double* partials;
+    __device__ __forceinline__ bool init(const BlockDesc& d) { return ctrl[d.lp].restart != 0; }
+    __device__ __forceinline__ void epi(int i, T, T) {
+        if constexpr (ROWS) {
+            const T b = v.yb[i];
+            v.y0[i] = b;
+            v.y[i] = b;
+        } else {
+            const T a = v.xb[i];
+            v.x0[i] = a;
+            v.x[i] = a;
+        }
+    }
+};
+
+// original-space bar point: x = beta_b dc xbar, z = beta_c zbar / dc, y = beta_c dr ybar
+template <typename T, bool ROWS>
+struct UnscaleOp {
+    using Tm = T;
+    using Acc = T;
+    static constexpr int NV = 0, NQ = 0;
+    const T* g0;
+    const T* g1;
+    DevIter<T> v;
+    const Ctrl* ctrl;
+    const double *dr, *dc;
+    double *x, *y, *z;
+    double bb, bc;
+    double q[1];
+    double* partials;
+    __device__ __forceinline__ bool init(const BlockDesc& d) {
+        bb = ctrl[d.lp].beta_b;
+        bc = ctrl[d.lp].beta_c;
+        return true;
+    }
+    __device__ __forceinline__ void epi(int i, T, T) {
+        if constexpr (ROWS) {
+            y[i] = bc * dr[i] * double(v.yb[i]);
+        } else {
+            x[i] = bb * dc[i] * double(v.xb[i]);
+            z[i] = bc * double(v.zb[i]) / dc[i];
+        }
+    }
+};
+
 // ---------------------------------------------------------------- plain product
 
 template <typename T>
@@ -338,86 +406,234 @@ struct SpmvOp {
     T* out;
     double q[1];
     double* partials;
-    __device__ __forceinline__ void init() {}
+    __device__ __forceinline__ bool init(const BlockDesc&) { return true; }
     __device__ __forceinline__ void epi(int row, T s, T) { out[row] = s; }
 };
 
-// ---------------------------------------------------------------- small kernels
+// ---------------------------------------------------------------- sums and control
 
-// Fixed-order sum of partials[k][0..nb) for k = blockIdx.x.
-__global__ __launch_bounds__(kBlock) void finish_sums_kernel(const double* partials, int nb, double* out) {
+// block (q, l): fixed-order sum of partials[q][seg[l] .. seg[l+1])
+__global__ __launch_bounds__(kBlock) void finish_sums_kernel(const double* partials, int nb, const int32_t* seg,
+                                                             double* out, int off) {
     __shared__ double sh[kBlock];
-    const double* p = partials + (size_t)blockIdx.x * nb;
+    const int q = blockIdx.x, l = blockIdx.y;
+    const double* p = partials + (size_t)q * nb;
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) s += p[i];
+    for (int i = seg[l] + threadIdx.x; i < seg[l + 1]; i += kBlock) s += p[i];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) out[(size_t)l * kSumStride + off + q] = sh[0];
 }
 
-constexpr int kSumsqItems = 8192;   // entries per block of the sum-of-squares kernel
+struct CheckValues {
+    double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit, move_x, move_y;
+    bool bad;
+};
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void sumsq_kernel(const T* v, int64_t n, double* partials) {
-    double q[1] = {0.0};
-    const int64_t b = (int64_t)blockIdx.x * kSumsqItems;
-    const int64_t e = b + kSumsqItems < n ? b + kSumsqItems : n;
-    for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
-        const double a = double(v[i]);
-        q[0] += a * a;
+// The relative KKT residuals of the original problem and the merit from the check sums
+// (see CheckRowsOp / CheckColsOp). Written without FMA contraction so that the device
+// takes the same decisions as an IEEE host evaluation of the same formulas.
+__device__ CheckValues check_values(const double* s, const Ctrl& c, const LpState& S) {
+#pragma clang fp contract(off)
+    const double* r = s;
+    const double* k = s + 8;
+    CheckValues v;
+    const double bb = c.beta_b * c.beta_c;
+    v.rel_p = sqrt(r[0]) / (1.0 + S.norm_b);
+    v.rel_d = sqrt(k[0]) / (1.0 + S.norm_c);
+    v.pobj = bb * k[1] + S.obj_offset;
+    v.dobj = bb * (r[3] + k[2]) + S.obj_offset;
+    v.rel_gap = fabs(v.pobj - v.dobj) / (1.0 + fabs(v.pobj) + fabs(v.dobj));
+    v.rel_kkt = fmax(v.rel_p, fmax(v.rel_d, v.rel_gap));
+    const double r2 = k[3] / c.sigma + c.lambda * c.sigma * r[1] + 2.0 * r[2];
+    v.merit = sqrt(r2 > 0.0 ? r2 : 0.0);
+    v.move_x = sqrt(k[4]);
+    v.move_y = sqrt(r[4]);
+    v.bad = (r[5] + k[5]) > 0.0 || isnan(v.rel_p) || isnan(v.rel_d) || isnan(v.rel_gap) ||
+            !isfinite(v.rel_kkt) || !isfinite(v.pobj) || !isfinite(v.merit);
+    return v;
+}
+
+__device__ void store_values(LpState& S, const CheckValues& v) {
+    S.rel_p = v.rel_p;
+    S.rel_d = v.rel_d;
+    S.rel_gap = v.rel_gap;
+    S.rel_kkt = v.rel_kkt;
+    S.pobj = v.pobj;
+    S.dobj = v.dobj;
+    S.merit = v.merit;
+}
+
+// After a check that did not terminate: iteration limit, then the restart rule:
+// restart when r <= 0.2 r0, or r <= 0.8 r0 while rising (r > r_prev), or when the
+// iterations since the last restart are >= 0.2 of all iterations. At a restart
+// sigma <- sqrt(sigma sigma*), sigma* = ||dx|| / (sqrt(lambda) ||dy||) from the anchor
+// move (skipped below 1e-12), clamped to [1e-4, 1e4]; anchor = iterate = bar point, k = 0.
+__device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, double move_x, double move_y) {
+#pragma clang fp contract(off)
+    if (S.it >= a.max_iter) {
+        S.term = 2;   // HPR_ITER_LIMIT
+        c.active = 0;
+        return;
     }
-    block_reduce_store(q, partials);
+    if (S.it == 1) {
+        S.r0 = r;
+        S.r_prev = r;
+        c.k_base = S.k;
+        return;
+    }
+    bool do_restart = false;
+    if (a.restart_rule) {
+        if (r <= 0.2 * S.r0) do_restart = true;
+        else if (r <= 0.8 * S.r0 && r > S.r_prev) do_restart = true;
+        else if ((double)S.k >= 0.2 * (double)S.it) do_restart = true;
+    }
+    if (do_restart) {
+        double sigma = c.sigma;
+        if (a.sigma_update && move_x > 1e-12 && move_y > 1e-12) {
+            const double star = move_x / (sqrt(c.lambda) * move_y);
+            sigma = sqrt(sigma * star);
+            sigma = sigma < 1e-4 ? 1e-4 : (sigma > 1e4 ? 1e4 : sigma);
+        }
+        c.sigma = sigma;
+        c.s = 1.0 / (c.lambda * sigma);
+        c.restart = 1;
+        S.k = 0;
+        S.restarts += 1;
+        S.r0 = r;
+    }
+    S.r_prev = r;
+    c.k_base = S.k;
 }
 
-template <typename T>
-__global__ void scale_kernel(T* v, int64_t n, double f) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = T(double(v[i]) * f);
+__global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
+    __shared__ int n_run, n_cand;
+    if (threadIdx.x == 0) {
+        n_run = 0;
+        n_cand = 0;
+    }
+    __syncthreads();
+    const int l = threadIdx.x;
+    if (l < a.nlp) {
+        Ctrl c = a.ctrl[l];
+        LpState S = a.st[l];
+        if (a.phase == 1) {
+            c.restart = 0;
+            if (c.active) {
+                S.it += a.nb;
+                S.k += a.nb;
+                const CheckValues v = check_values(a.sums + (size_t)l * kSumStride, c, S);
+                store_values(S, v);
+                if (v.bad) {
+                    S.term = 4;   // HPR_NUMERIC_FAIL
+                    c.active = 0;
+                } else if (v.rel_kkt <= a.tol) {
+                    if (!a.fp32) {
+                        S.term = 1;   // HPR_SOLVED
+                        c.active = 0;
+                    } else {
+                        S.candidate = 1;
+                        S.p32[0] = v.merit;
+                        S.p32[1] = v.move_x;
+                        S.p32[2] = v.move_y;
+                    }
+                } else {
+                    decide(S, c, a, v.merit, v.move_x, v.move_y);
+                }
+            }
+        } else if (a.phase == 2) {
+            c.restart = 0;
+            if (c.active && S.candidate) {
+                S.candidate = 0;
+                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
+                if (!v.bad && v.rel_kkt <= a.tol) {
+                    store_values(S, v);
+                    S.term = 1;
+                    c.active = 0;
+                } else {
+                    decide(S, c, a, S.p32[0], S.p32[1], S.p32[2]);
+                }
+            }
+        } else if (a.phase == 3) {
+            if (S.term != 4) {
+                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
+                S.rel_p = v.rel_p;
+                S.rel_d = v.rel_d;
+                S.rel_gap = v.rel_gap;
+                S.rel_kkt = v.rel_kkt;
+                S.pobj = v.pobj;
+                S.dobj = v.dobj;
+            }
+        } else if (a.phase == 4) {
+            c.restart = 0;
+            if (c.active) {
+                S.term = 3;   // HPR_TIME_LIMIT
+                c.active = 0;
+                S.candidate = 0;
+            }
+        }
+        a.ctrl[l] = c;
+        a.st[l] = S;
+        if (c.active) atomicAdd(&n_run, 1);
+        if (S.candidate) atomicAdd(&n_cand, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.stat[0] = n_run;
+        a.stat[1] = n_cand;
+    }
 }
 
-// SplitMix64 (Steele, Lea and Flood 2014) as a counter-based generator: draw i is the
-// finaliser applied to seed + (i + 1) * 0x9E3779B97F4A7C15; mapped to [-1, 1) from its top 53 bits.
+// ---------------------------------------------------------------- segmented vector kernels
+
 __device__ __forceinline__ uint64_t splitmix64_draw(uint64_t seed, uint64_t i) {
+    // SplitMix64 (Steele, Lea and Flood 2014) as a counter-based generator: draw i is the
+    // finaliser applied to seed + (i + 1) * 0x9E3779B97F4A7C15.
     uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
 
-template <typename T>
-__global__ void start_vector_kernel(T* v, int64_t n, uint64_t seed) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = T(2.0 * (double(splitmix64_draw(seed, (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0);
-}
-
-template <typename T>
-__global__ void restart_kernel(T* x0, T* x, const T* xb, int n, T* y0, T* y, const T* yb, int m) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const T a = xb[i];
-        x0[i] = a;
-        x[i] = a;
-    }
-    if (i < m) {
-        const T b = yb[i];
-        y0[i] = b;
-        y[i] = b;
+// grid (max_chunks, nlp): block (c, l) covers entries seg[l] + c*kChunk .. of LP l
+__global__ __launch_bounds__(kBlock) void seg_sumsq_kernel(const double* v, const int64_t* seg, int max_chunks,
+                                                           double* partials) {
+    const int c = blockIdx.x, l = blockIdx.y;
+    const int64_t b = seg[l] + (int64_t)c * kChunk;
+    const int64_t e = b + kChunk < seg[l + 1] ? b + kChunk : seg[l + 1];
+    double s = 0.0;
+    for (int64_t i = b + threadIdx.x; i < e; i += kBlock) s += v[i] * v[i];
+    __shared__ double sh[kBlock / 64];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+        partials[(size_t)l * max_chunks + c] = t;
     }
 }
 
-template <typename T>
-__global__ void unscale_kernel(const T* xb, const T* zb, const T* yb, const double* dr, const double* dc, int n,
-                               int m, double beta_b, double beta_c, double* x, double* y, double* z) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        x[i] = beta_b * dc[i] * double(xb[i]);
-        z[i] = beta_c * double(zb[i]) / dc[i];
+__global__ __launch_bounds__(kBlock) void seg_start_kernel(double* v, const int64_t* seg, uint64_t seed) {
+    const int c = blockIdx.x, l = blockIdx.y;
+    const int64_t b = seg[l] + (int64_t)c * kChunk;
+    const int64_t e = b + kChunk < seg[l + 1] ? b + kChunk : seg[l + 1];
+    for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+        const uint64_t r = splitmix64_draw(seed, (uint64_t)(i - seg[l]));
+        v[i] = 2.0 * (double(r >> 11) * 0x1.0p-53) - 1.0;
     }
-    if (i < m) y[i] = beta_c * dr[i] * double(yb[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void seg_scale_kernel(double* v, const int64_t* seg, const double* f) {
+    const int c = blockIdx.x, l = blockIdx.y;
+    const int64_t b = seg[l] + (int64_t)c * kChunk;
+    const int64_t e = b + kChunk < seg[l + 1] ? b + kChunk : seg[l + 1];
+    const double s = f[l];
+    for (int64_t i = b + threadIdx.x; i < e; i += kBlock) v[i] *= s;
 }
 
 template <typename T>
@@ -425,8 +641,6 @@ __global__ void cast_kernel(const double* s, T* d, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = T(s[i]);
 }
-
-static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------- launchers
 
@@ -457,33 +671,51 @@ void launch_dual_step(const DevCsr<T>& A, const DevProb<T>& p, const DevIter<T>&
 }
 
 template <typename Tm, typename Tp, typename Tv>
-void launch_check_rows(const DevCsr<Tm>& A, const DevProb<Tp>& p, const DevIter<Tv>& v, double beta_b,
+void launch_check_rows(const DevCsr<Tm>& A, const DevProb<Tp>& p, const DevIter<Tv>& v, const Ctrl* ctrl,
                        double* partials, hipStream_t st) {
     CheckRowsOp<Tm, Tp, Tv> op{};
     op.g0 = v.xb;
     op.g1 = v.dx;
     op.p = p;
     op.v = v;
-    op.beta_b = beta_b;
+    op.ctrl = ctrl;
     op.partials = partials;
     launch_csr(A, op, st);
 }
 
 template <typename Tm, typename Tp, typename Tv>
-void launch_check_cols(const DevCsr<Tm>& At, const DevProb<Tp>& p, const DevIter<Tv>& v, double beta_c,
+void launch_check_cols(const DevCsr<Tm>& At, const DevProb<Tp>& p, const DevIter<Tv>& v, const Ctrl* ctrl,
                        double* partials, hipStream_t st) {
     CheckColsOp<Tm, Tp, Tv> op{};
     op.g0 = v.yb;
     op.p = p;
     op.v = v;
-    op.beta_c = beta_c;
+    op.ctrl = ctrl;
     op.partials = partials;
     launch_csr(At, op, st);
 }
 
-void launch_finish_sums(const double* partials, int nq, int nblocks, double* out, hipStream_t st) {
-    if (nq <= 0) return;
-    hipLaunchKernelGGL(finish_sums_kernel, dim3(nq), dim3(kBlock), 0, st, partials, nblocks, out);
+void launch_finish_sums(const double* partials, int nq, int nblocks, const int32_t* seg, int nlp, double* out,
+                        int off, hipStream_t st) {
+    if (nq <= 0 || nlp <= 0) return;
+    hipLaunchKernelGGL(finish_sums_kernel, dim3(nq, nlp), dim3(kBlock), 0, st, partials, nblocks, seg, out, off);
+}
+
+template <typename T>
+void launch_restart(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v, const Ctrl* ctrl,
+                    hipStream_t st) {
+    RestartOp<T, true> r{};
+    r.v = v;
+    r.ctrl = ctrl;
+    launch_csr(A, r, st);
+    RestartOp<T, false> c{};
+    c.v = v;
+    c.ctrl = ctrl;
+    launch_csr(At, c, st);
+}
+
+void launch_control(const ControlArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(control_kernel, dim3(1), dim3(kMaxBatch), 0, st, a);
 }
 
 template <typename T>
@@ -494,48 +726,49 @@ void launch_spmv(const DevCsr<T>& A, const T* x, T* y, hipStream_t st) {
     launch_csr(A, op, st);
 }
 
-int sumsq_blocks(int64_t n) { return (int)((n + kSumsqItems - 1) / kSumsqItems); }
+void launch_seg_sumsq(const double* v, const int64_t* seg, int nlp, int max_chunks, double* partials,
+                      hipStream_t st) {
+    if (nlp <= 0 || max_chunks <= 0) return;
+    hipLaunchKernelGGL(seg_sumsq_kernel, dim3(max_chunks, nlp), dim3(kBlock), 0, st, v, seg, max_chunks, partials);
+}
 
-template <typename T>
-void launch_sumsq(const T* v, int64_t n, double* partials, hipStream_t st) {
-    const int nb = sumsq_blocks(n);
-    if (nb <= 0) return;
-    hipLaunchKernelGGL(sumsq_kernel<T>, dim3(nb), dim3(kBlock), 0, st, v, n, partials);
+void launch_seg_start_vector(double* v, const int64_t* seg, int nlp, int max_chunks, uint64_t seed,
+                             hipStream_t st) {
+    if (nlp <= 0 || max_chunks <= 0) return;
+    hipLaunchKernelGGL(seg_start_kernel, dim3(max_chunks, nlp), dim3(kBlock), 0, st, v, seg, seed);
+}
+
+void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, const double* factor,
+                      hipStream_t st) {
+    if (nlp <= 0 || max_chunks <= 0) return;
+    hipLaunchKernelGGL(seg_scale_kernel, dim3(max_chunks, nlp), dim3(kBlock), 0, st, v, seg, factor);
 }
 
 template <typename T>
-void launch_scale(T* v, int64_t n, double factor, hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(scale_kernel<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, factor);
-}
-
-template <typename T>
-void launch_start_vector(T* v, int64_t n, uint64_t seed, hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(start_vector_kernel<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, seed);
-}
-
-template <typename T>
-void launch_restart(const DevIter<T>& v, int n, int m, hipStream_t st) {
-    const int len = n > m ? n : m;
-    if (len <= 0) return;
-    hipLaunchKernelGGL(restart_kernel<T>, dim3(grid_for(len)), dim3(kBlock), 0, st, v.x0, v.x, v.xb, n, v.y0,
-                       v.y, v.yb, m);
-}
-
-template <typename T>
-void launch_unscale(const DevIter<T>& v, const double* dr, const double* dc, int n, int m, double beta_b,
-                    double beta_c, double* x, double* y, double* z, hipStream_t st) {
-    const int len = n > m ? n : m;
-    if (len <= 0) return;
-    hipLaunchKernelGGL(unscale_kernel<T>, dim3(grid_for(len)), dim3(kBlock), 0, st, v.xb, v.zb, v.yb, dr, dc,
-                       n, m, beta_b, beta_c, x, y, z);
+void launch_unscale(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v, const double* dr,
+                    const double* dc, const Ctrl* ctrl, double* x, double* y, double* z, hipStream_t st) {
+    UnscaleOp<T, true> r{};
+    r.v = v;
+    r.ctrl = ctrl;
+    r.dr = dr;
+    r.dc = dc;
+    r.y = y;
+    launch_csr(A, r, st);
+    UnscaleOp<T, false> c{};
+    c.v = v;
+    c.ctrl = ctrl;
+    c.dr = dr;
+    c.dc = dc;
+    c.x = x;
+    c.z = z;
+    launch_csr(At, c, st);
 }
 
 template <typename T>
 void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(cast_kernel<T>, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n);
+    hipLaunchKernelGGL(cast_kernel<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, src,
+                       dst, n);
 }
 
 // ---------------------------------------------------------------- instantiations
@@ -546,22 +779,20 @@ void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st) {
     template void launch_dual_step<T>(const DevCsr<T>&, const DevProb<T>&, const DevIter<T>&, const Ctrl*,   \
                                       int, bool, hipStream_t);                                               \
     template void launch_spmv<T>(const DevCsr<T>&, const T*, T*, hipStream_t);                              \
-    template void launch_sumsq<T>(const T*, int64_t, double*, hipStream_t);                                  \
-    template void launch_scale<T>(T*, int64_t, double, hipStream_t);                                         \
-    template void launch_start_vector<T>(T*, int64_t, uint64_t, hipStream_t);                                \
-    template void launch_restart<T>(const DevIter<T>&, int, int, hipStream_t);                               \
-    template void launch_unscale<T>(const DevIter<T>&, const double*, const double*, int, int, double,       \
-                                    double, double*, double*, double*, hipStream_t);                         \
+    template void launch_restart<T>(const DevCsr<T>&, const DevCsr<T>&, const DevIter<T>&, const Ctrl*,      \
+                                    hipStream_t);                                                            \
+    template void launch_unscale<T>(const DevCsr<T>&, const DevCsr<T>&, const DevIter<T>&, const double*,    \
+                                    const double*, const Ctrl*, double*, double*, double*, hipStream_t);     \
     template void launch_cast<T>(const double*, T*, int64_t, hipStream_t);
 
 HPR_INST(double)
 HPR_INST(float)
 
-#define HPR_INST_CHECK(M, P, V)                                                                             \
-    template void launch_check_rows<M, P, V>(const DevCsr<M>&, const DevProb<P>&, const DevIter<V>&, double, \
-                                             double*, hipStream_t);                                         \
-    template void launch_check_cols<M, P, V>(const DevCsr<M>&, const DevProb<P>&, const DevIter<V>&, double, \
-                                             double*, hipStream_t);
+#define HPR_INST_CHECK(M, P, V)                                                                              \
+    template void launch_check_rows<M, P, V>(const DevCsr<M>&, const DevProb<P>&, const DevIter<V>&,          \
+                                             const Ctrl*, double*, hipStream_t);                             \
+    template void launch_check_cols<M, P, V>(const DevCsr<M>&, const DevProb<P>&, const DevIter<V>&,          \
+                                             const Ctrl*, double*, hipStream_t);
 
 HPR_INST_CHECK(double, double, double)
 HPR_INST_CHECK(float, float, float)

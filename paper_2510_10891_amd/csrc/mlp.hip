@@ -1,0 +1,465 @@
+// Warm-start network on the GPU: a multilayer perceptron with BF16 weights and
+// activations on the matrix cores (MFMA, FP32 accumulation), FP32 master weights,
+// and its training step (forward, backward, Adam) written as plain kernels.
+//
+// Layer i: z_i = h_i W_i + b_i, h_{i+1} = max(z_i, 0) except after the last layer.
+// Loss: 0.5 * mean over all output entries of (out - target)^2.
+// Adam (Kingma and Ba 2015) with bias correction on the FP32 master copy; the BF16 copy
+// used by the products is refreshed after every step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hprlp.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxLayers = 8;
+constexpr int kTile = 16;
+constexpr int kThreads = 256;
+
+__host__ __device__ inline uint16_t to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));  // inf/nan
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float from_bf16(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// C(i, j) = sum_k A(i, k) B(k, j) for an M x N output, BF16 operands addressed with
+// element strides (A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1]) so transposed
+// operands need no copy. One wavefront computes one 16 x 16 tile with
+// v_mfma_f32_16x16x16_bf16 over K in steps of 16; out-of-range rows/columns/depths are
+// read as zero. Epilogue: + bias (FP32, may be null), optional ReLU, FP32 and/or BF16 store.
+struct GemmArgs {
+    const uint16_t* A;
+    const uint16_t* B;
+    int64_t sa0, sa1, sb0, sb1;
+    int M, N, K;
+    const float* bias;
+    int relu;
+    float* C32;        // [M][N] or null
+    uint16_t* C16;     // [M][N] or null
+};
+
+__global__ __launch_bounds__(kThreads) void gemm_bf16_kernel(GemmArgs g) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tiles_n = (g.N + kTile - 1) / kTile;
+    const int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wave;
+    const int64_t tiles = (int64_t)((g.M + kTile - 1) / kTile) * tiles_n;
+    if (tile >= tiles) return;
+    const int i0 = (int)(tile / tiles_n) * kTile;
+    const int j0 = (int)(tile % tiles_n) * kTile;
+    const int r = lane & 15;          // A row / B column of this lane
+    const int kq = (lane >> 4) * 4;   // first of the 4 depths this lane supplies
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kTile) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + kq + t;
+            const int ia = i0 + r, jb = j0 + r;
+            a[t] = (ia < g.M && k < g.K) ? (short)g.A[(int64_t)ia * g.sa0 + (int64_t)k * g.sa1] : (short)0;
+            b[t] = (jb < g.N && k < g.K) ? (short)g.B[(int64_t)k * g.sb0 + (int64_t)jb * g.sb1] : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    const int j = j0 + r;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int i = i0 + (lane >> 4) * 4 + t;
+        if (i < g.M && j < g.N) {
+            float v = acc[t] + (g.bias ? g.bias[j] : 0.f);
+            if (g.relu) v = v > 0.f ? v : 0.f;
+            if (g.C32) g.C32[(int64_t)i * g.N + j] = v;
+            if (g.C16) g.C16[(int64_t)i * g.N + j] = to_bf16(v);
+        }
+    }
+}
+
+void gemm(const GemmArgs& g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0) return;
+    const int64_t tiles = (int64_t)((g.M + kTile - 1) / kTile) * ((g.N + kTile - 1) / kTile);
+    const int64_t blocks = (tiles + (kThreads / 64) - 1) / (kThreads / 64);
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, g);
+}
+
+__global__ void f32_to_bf16_kernel(const float* s, uint16_t* d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = to_bf16(s[i]);
+}
+
+// g = (out - target) / count as BF16 (the gradient of the loss at the output) and per-block
+// partial sums of (out - target)^2 (FP64) for the loss.
+__global__ __launch_bounds__(kThreads) void output_grad_kernel(const float* out, const float* target, int64_t n,
+                                                               float inv_count, uint16_t* g16, double* part) {
+    __shared__ double sh[kThreads];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const float d = out[i] - target[i];
+        s += (double)d * (double)d;
+        g16[i] = to_bf16(d * inv_count);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// dz = dh * (z > 0), BF16 in and out (z from the forward pass, FP32)
+__global__ void relu_back_kernel(const float* z, uint16_t* g, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(z[i] > 0.f)) g[i] = 0;
+}
+
+// db[j] = sum_i g[i][j] (column sums in a fixed order, FP32 accumulate)
+__global__ void bias_grad_kernel(const uint16_t* g, int rows, int cols, float* db) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int i = 0; i < rows; ++i) s += from_bf16(g[(int64_t)i * cols + j]);
+    db[j] = s;
+}
+
+__global__ void adam_kernel(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define MLP_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? HPR_ERR_NOMEM : HPR_ERR_HIP,       \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                \
+    } while (0)
+
+}  // namespace
+
+struct hpr_mlp {
+    int L = 0;
+    int sizes[kMaxLayers + 1] = {0};
+    int64_t woff[kMaxLayers] = {0}, boff[kMaxLayers] = {0}, nparams = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    float *w = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // FP32 params / grads / moments
+    uint16_t* w16 = nullptr;                                          // BF16 weights
+    int64_t cap = 0;                                                  // rows the buffers hold
+    uint16_t* x16 = nullptr;                                          // input, BF16
+    uint16_t* h16[kMaxLayers + 1] = {nullptr};                        // activations, BF16
+    float* z32[kMaxLayers] = {nullptr};                               // pre-activations, FP32
+    uint16_t* g16 = nullptr;                                          // gradient scratch, BF16
+    uint16_t* g16b = nullptr;
+    float* xin = nullptr;                                             // staging of X and targets
+    float* tgt = nullptr;
+    double* part = nullptr;
+    int64_t step = 0;
+    ~hpr_mlp() {
+        if (st) (void)hipStreamSynchronize(st);
+        for (void* p : {(void*)w, (void*)grad, (void*)m, (void*)v, (void*)w16}) (void)hipFree(p);
+        release_rows();
+        if (own_stream && st) (void)hipStreamDestroy(st);
+    }
+    void release_rows() {
+        (void)hipFree(x16);
+        for (int i = 0; i <= kMaxLayers; ++i) (void)hipFree(h16[i]), h16[i] = nullptr;
+        for (int i = 0; i < kMaxLayers; ++i) (void)hipFree(z32[i]), z32[i] = nullptr;
+        (void)hipFree(g16);
+        (void)hipFree(g16b);
+        (void)hipFree(xin);
+        (void)hipFree(tgt);
+        (void)hipFree(part);
+        x16 = g16 = g16b = nullptr;
+        xin = tgt = nullptr;
+        part = nullptr;
+        cap = 0;
+    }
+    int width() const {
+        int mx = 0;
+        for (int i = 0; i <= L; ++i) mx = sizes[i] > mx ? sizes[i] : mx;
+        return mx;
+    }
+    int ensure_rows(int64_t n) {
+        if (n <= cap) return HPR_OK;
+        release_rows();
+        const int64_t W = width();
+        MLP_HIP(hipMalloc(&x16, sizeof(uint16_t) * n * sizes[0]));
+        MLP_HIP(hipMalloc(&xin, sizeof(float) * n * W));
+        MLP_HIP(hipMalloc(&tgt, sizeof(float) * n * sizes[L]));
+        for (int i = 1; i <= L; ++i) MLP_HIP(hipMalloc(&h16[i], sizeof(uint16_t) * n * sizes[i]));
+        for (int i = 0; i < L; ++i) MLP_HIP(hipMalloc(&z32[i], sizeof(float) * n * sizes[i + 1]));
+        MLP_HIP(hipMalloc(&g16, sizeof(uint16_t) * n * W));
+        MLP_HIP(hipMalloc(&g16b, sizeof(uint16_t) * n * W));
+        MLP_HIP(hipMalloc(&part, sizeof(double) * 1024));
+        cap = n;
+        return HPR_OK;
+    }
+};
+
+namespace {
+
+int refresh_bf16(hpr_mlp* q) {
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(q->nparams)), dim3(kThreads), 0, q->st, q->w, q->w16,
+                       q->nparams);
+    MLP_HIP(hipGetLastError());
+    return HPR_OK;
+}
+
+// forward pass on rows already staged in q->xin (FP32 [n][sizes[0]]); leaves z32[L-1] = output
+int forward_staged(hpr_mlp* q, int64_t n) {
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(n * q->sizes[0])), dim3(kThreads), 0, q->st, q->xin,
+                       q->x16, n * q->sizes[0]);
+    const uint16_t* h = q->x16;
+    for (int i = 0; i < q->L; ++i) {
+        GemmArgs g{};
+        g.A = h;
+        g.sa0 = q->sizes[i];
+        g.sa1 = 1;
+        g.B = q->w16 + q->woff[i];
+        g.sb0 = q->sizes[i + 1];
+        g.sb1 = 1;
+        g.M = (int)n;
+        g.N = q->sizes[i + 1];
+        g.K = q->sizes[i];
+        g.bias = q->w + q->boff[i];
+        g.relu = i < q->L - 1;
+        g.C32 = q->z32[i];
+        g.C16 = i < q->L - 1 ? q->h16[i + 1] : nullptr;
+        gemm(g, q->st);
+        h = q->h16[i + 1];
+    }
+    MLP_HIP(hipGetLastError());
+    return HPR_OK;
+}
+
+// loss and gradients into q->grad for rows staged in xin / tgt
+int gradients_staged(hpr_mlp* q, int64_t n, float* loss) {
+    int rc = forward_staged(q, n);
+    if (rc) return rc;
+    const int L = q->L;
+    const int64_t nout = n * q->sizes[L];
+    const int nb = (int)std::min<int64_t>(1024, blocks_for(nout));
+    hipLaunchKernelGGL(output_grad_kernel, dim3(nb), dim3(kThreads), 0, q->st, q->z32[L - 1], q->tgt, nout,
+                       1.0f / (float)nout, q->g16, q->part);
+    uint16_t* g = q->g16;       // gradient at z_i (BF16, [n][sizes[i+1]])
+    uint16_t* other = q->g16b;
+    for (int i = L - 1; i >= 0; --i) {
+        const uint16_t* hin = i == 0 ? q->x16 : q->h16[i];
+        // dW_i = h_i^T g  (K = rows)
+        GemmArgs gw{};
+        gw.A = hin;
+        gw.sa0 = 1;
+        gw.sa1 = q->sizes[i];
+        gw.B = g;
+        gw.sb0 = q->sizes[i + 1];
+        gw.sb1 = 1;
+        gw.M = q->sizes[i];
+        gw.N = q->sizes[i + 1];
+        gw.K = (int)n;
+        gw.C32 = q->grad + q->woff[i];
+        gemm(gw, q->st);
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(q->sizes[i + 1])), dim3(kThreads), 0, q->st, g, (int)n,
+                           q->sizes[i + 1], q->grad + q->boff[i]);
+        if (i > 0) {
+            // dh_i = g W_i^T, then ReLU mask with z_{i-1}
+            GemmArgs gh{};
+            gh.A = g;
+            gh.sa0 = q->sizes[i + 1];
+            gh.sa1 = 1;
+            gh.B = q->w16 + q->woff[i];
+            gh.sb0 = 1;
+            gh.sb1 = q->sizes[i + 1];
+            gh.M = (int)n;
+            gh.N = q->sizes[i];
+            gh.K = q->sizes[i + 1];
+            gh.C16 = other;
+            gemm(gh, q->st);
+            hipLaunchKernelGGL(relu_back_kernel, dim3(blocks_for(n * q->sizes[i])), dim3(kThreads), 0, q->st,
+                               q->z32[i - 1], other, n * q->sizes[i]);
+            std::swap(g, other);
+        }
+    }
+    MLP_HIP(hipGetLastError());
+    std::vector<double> part(nb);
+    MLP_HIP(hipMemcpyAsync(part.data(), q->part, sizeof(double) * nb, hipMemcpyDeviceToHost, q->st));
+    MLP_HIP(hipStreamSynchronize(q->st));
+    double s = 0.0;
+    for (double p : part) s += p;
+    if (loss) *loss = (float)(0.5 * s / (double)nout);
+    return HPR_OK;
+}
+
+int stage(hpr_mlp* q, const float* X, const float* T, int64_t n) {
+    int rc = q->ensure_rows(n);
+    if (rc) return rc;
+    MLP_HIP(hipMemcpyAsync(q->xin, X, sizeof(float) * n * q->sizes[0], hipMemcpyHostToDevice, q->st));
+    if (T) MLP_HIP(hipMemcpyAsync(q->tgt, T, sizeof(float) * n * q->sizes[q->L], hipMemcpyHostToDevice, q->st));
+    return HPR_OK;
+}
+
+}  // namespace
+
+extern "C" int hpr_mlp_create(int32_t nlayers, const int32_t* sizes, const float* params, void* stream,
+                              hpr_mlp** out) {
+    g_err.clear();
+    if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nlayers < 1 || nlayers > kMaxLayers || !sizes) return fail(HPR_ERR_INVALID, "nlayers must be in [1, %d]", kMaxLayers);
+    for (int i = 0; i <= nlayers; ++i)
+        if (sizes[i] < 1 || sizes[i] > 4096) return fail(HPR_ERR_INVALID, "layer width %d out of [1, 4096]", sizes[i]);
+    hpr_mlp* q = new hpr_mlp();
+    q->L = nlayers;
+    int64_t off = 0;
+    for (int i = 0; i <= nlayers; ++i) q->sizes[i] = sizes[i];
+    for (int i = 0; i < nlayers; ++i) {
+        q->woff[i] = off;
+        off += (int64_t)sizes[i] * sizes[i + 1];
+        q->boff[i] = off;
+        off += sizes[i + 1];
+    }
+    q->nparams = off;
+    auto bail = [&](int rc) {
+        delete q;
+        return rc;
+    };
+    if (stream) q->st = (hipStream_t)stream;
+    else {
+        if (hipStreamCreateWithFlags(&q->st, hipStreamNonBlocking) != hipSuccess) return bail(fail(HPR_ERR_HIP, "stream"));
+        q->own_stream = true;
+    }
+    const size_t bytes = sizeof(float) * off;
+    if (hipMalloc(&q->w, bytes) != hipSuccess || hipMalloc(&q->grad, bytes) != hipSuccess ||
+        hipMalloc(&q->m, bytes) != hipSuccess || hipMalloc(&q->v, bytes) != hipSuccess ||
+        hipMalloc(&q->w16, sizeof(uint16_t) * off) != hipSuccess)
+        return bail(fail(HPR_ERR_NOMEM, "device allocation failed"));
+    if (hipMemsetAsync(q->m, 0, bytes, q->st) != hipSuccess || hipMemsetAsync(q->v, 0, bytes, q->st) != hipSuccess ||
+        hipMemsetAsync(q->w, 0, bytes, q->st) != hipSuccess)
+        return bail(fail(HPR_ERR_HIP, "memset failed"));
+    if (params && hipMemcpyAsync(q->w, params, bytes, hipMemcpyHostToDevice, q->st) != hipSuccess)
+        return bail(fail(HPR_ERR_HIP, "copy failed"));
+    int rc = refresh_bf16(q);
+    if (rc) return bail(rc);
+    if (hipStreamSynchronize(q->st) != hipSuccess) return bail(fail(HPR_ERR_HIP, "sync failed"));
+    *out = q;
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_destroy(hpr_mlp* q) {
+    delete q;
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_num_params(hpr_mlp* q, int64_t* n) {
+    g_err.clear();
+    if (!q || !n) return fail(HPR_ERR_INVALID, "NULL argument");
+    *n = q->nparams;
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_set_params(hpr_mlp* q, const float* params) {
+    g_err.clear();
+    if (!q || !params) return fail(HPR_ERR_INVALID, "NULL argument");
+    MLP_HIP(hipMemcpyAsync(q->w, params, sizeof(float) * q->nparams, hipMemcpyHostToDevice, q->st));
+    MLP_HIP(hipMemsetAsync(q->m, 0, sizeof(float) * q->nparams, q->st));
+    MLP_HIP(hipMemsetAsync(q->v, 0, sizeof(float) * q->nparams, q->st));
+    q->step = 0;
+    int rc = refresh_bf16(q);
+    if (rc) return rc;
+    MLP_HIP(hipStreamSynchronize(q->st));
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_get_params(hpr_mlp* q, float* params) {
+    g_err.clear();
+    if (!q || !params) return fail(HPR_ERR_INVALID, "NULL argument");
+    MLP_HIP(hipMemcpyAsync(params, q->w, sizeof(float) * q->nparams, hipMemcpyDeviceToHost, q->st));
+    MLP_HIP(hipStreamSynchronize(q->st));
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_forward(hpr_mlp* q, const float* X, int64_t n, float* Y) {
+    g_err.clear();
+    if (!q || !X || !Y || n < 0) return fail(HPR_ERR_INVALID, "bad argument");
+    if (n == 0) return HPR_OK;
+    int rc = stage(q, X, nullptr, n);
+    if (rc) return rc;
+    rc = forward_staged(q, n);
+    if (rc) return rc;
+    MLP_HIP(hipMemcpyAsync(Y, q->z32[q->L - 1], sizeof(float) * n * q->sizes[q->L], hipMemcpyDeviceToHost, q->st));
+    MLP_HIP(hipStreamSynchronize(q->st));
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_gradients(hpr_mlp* q, const float* X, const float* T, int64_t n, float* grads, float* loss) {
+    g_err.clear();
+    if (!q || !X || !T || n < 1) return fail(HPR_ERR_INVALID, "bad argument");
+    int rc = stage(q, X, T, n);
+    if (rc) return rc;
+    rc = gradients_staged(q, n, loss);
+    if (rc) return rc;
+    if (grads) {
+        MLP_HIP(hipMemcpyAsync(grads, q->grad, sizeof(float) * q->nparams, hipMemcpyDeviceToHost, q->st));
+        MLP_HIP(hipStreamSynchronize(q->st));
+    }
+    return HPR_OK;
+}
+
+extern "C" int hpr_mlp_train_step(hpr_mlp* q, const float* X, const float* T, int64_t n, float lr, float* loss) {
+    g_err.clear();
+    if (!q || !X || !T || n < 1 || !(lr > 0)) return fail(HPR_ERR_INVALID, "bad argument");
+    int rc = stage(q, X, T, n);
+    if (rc) return rc;
+    rc = gradients_staged(q, n, loss);
+    if (rc) return rc;
+    q->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)q->step), c2 = 1.0f - powf(b2, (float)q->step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(q->nparams)), dim3(kThreads), 0, q->st, q->w, q->grad, q->m, q->v,
+                       q->nparams, lr, b1, b2, 1e-8f, c1, c2);
+    rc = refresh_bf16(q);
+    if (rc) return rc;
+    MLP_HIP(hipStreamSynchronize(q->st));
+    return HPR_OK;
+}
+
+extern "C" const char* hpr_mlp_last_error(void) { return g_err.c_str(); }

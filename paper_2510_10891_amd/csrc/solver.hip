@@ -1,12 +1,14 @@
 // Host runtime of the gfx950 LP solver: the C interface declared in hprlp.h.
 //
-// hpr_create validates the LP, scales it (Section III-A: optional Ruiz passes,
-// Pock-Chambolle with alpha = 1, bound/cost normalisation), builds the padded and
-// binned CSR layouts of A~ and A~^T, uploads them and estimates lambda = lambda_max(A~A~^T)
-// with the power method on the device. hpr_solve runs blocks of iterations of eq.(hpr)
-// on the device; the last iteration of each block writes the bar point, two check
-// kernels reduce the KKT residuals (Theorem 1's residual map, normalised) and the merit
-// in FP64, and the host decides termination, restarts and sigma from those sums.
+// An Engine holds one LP or a batch pooled into one block-diagonal problem. Creation
+// validates each LP, scales it (Section III-A: optional Ruiz passes, Pock-Chambolle with
+// alpha = 1, bound/cost normalisation), builds the padded CSR layouts of A~ and A~^T and
+// their block schedules, tunes the schedule, and estimates every LP's
+// lambda = lambda_max(A~A~^T) with the power method on the device. A solve runs blocks of
+// iterations of eq.(hpr); the last iteration of a block writes the bar point, two check
+// kernels reduce the KKT residuals (Theorem 1's residual map, normalised) and the merit in
+// FP64, and a control kernel takes every LP's decisions (termination, restart, sigma) on
+// the device. Blocks are replayed as captured HIP graphs; the host polls once per block.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -153,80 +155,6 @@ static Layout make_layout(const HostCsr& a) {
     return L;
 }
 
-// Lane-group bins for U quads per lane and pass: bin b takes rows of at most U * 2^b quads.
-static void make_bins(const std::vector<int64_t>& start, int U, std::vector<int32_t>& rows, Bins& bins) {
-    const int32_t R = (int32_t)start.size() - 1;
-    std::vector<uint8_t> bin((size_t)R);
-    int32_t count[kNumBins] = {0};
-    for (int32_t i = 0; i < R; ++i) {
-        const int64_t quads = (start[i + 1] - start[i]) / kVec;
-        int b = 0;
-        while (b < kNumBins - 1 && (int64_t)U * (int64_t(1) << b) < quads) ++b;
-        bin[i] = (uint8_t)b;
-        count[b]++;
-    }
-    int32_t roff = 0, boff = 0;
-    for (int b = 0; b < kNumBins; ++b) {
-        bins.row_off[b] = roff;
-        bins.nrows[b] = count[b];
-        bins.block_off[b] = boff;
-        const int per_block = kBlock >> b;
-        boff += (count[b] + per_block - 1) / per_block;
-        roff += count[b];
-    }
-    bins.block_off[kNumBins] = boff;
-    rows.resize((size_t)R);
-    int32_t pos[kNumBins];
-    for (int b = 0; b < kNumBins; ++b) pos[b] = bins.row_off[b];
-    for (int32_t i = 0; i < R; ++i) rows[pos[bin[i]]++] = i;
-}
-
-// Device copy of a layout: shared structure plus FP64 and (optionally) FP32 values.
-struct DevMatrix {
-    DBuf start, col, rows, val64, val32;
-    std::vector<int64_t> start_h;   // host copy of the offsets (rebinning)
-    Bins bins{};
-    int32_t nrows = 0;
-    int32_t unroll = 4;
-    int64_t padded = 0;
-    void upload_from(const Layout& L, bool fp32, hipStream_t st) {
-        nrows = (int32_t)L.start.size() - 1;
-        padded = (int64_t)L.col.size();
-        start_h = L.start;
-        upload(start, L.start, st);
-        upload(col, L.col, st);
-        upload(val64, L.val, st);
-        if (fp32) {
-            val32.alloc(L.val.size() * sizeof(float));
-            launch_cast<float>(val64.as<double>(), val32.as<float>(), (int64_t)L.val.size(), st);
-        }
-        rows.alloc(sizeof(int32_t) * std::max(nrows, 1));
-        set_unroll(4, st);
-    }
-    // rebuild the bins for U quads per lane and upload the row list
-    void set_unroll(int U, hipStream_t st) {
-        std::vector<int32_t> r;
-        make_bins(start_h, U, r, bins);
-        unroll = U;
-        if (!r.empty()) {
-            HIP_OK(hipMemcpyAsync(rows.p, r.data(), sizeof(int32_t) * r.size(), hipMemcpyHostToDevice, st));
-            HIP_OK(hipStreamSynchronize(st));
-        }
-    }
-    template <typename T>
-    DevCsr<T> view() const {
-        DevCsr<T> d;
-        d.start = start.as<int64_t>();
-        d.col = col.as<int32_t>();
-        d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
-        d.rows = rows.as<int32_t>();
-        d.bins = bins;
-        d.nrows = nrows;
-        d.unroll = unroll;
-        return d;
-    }
-};
-
 // ---------------------------------------------------------------- validation
 
 static int validate(const hpr_lp* lp) {
@@ -289,42 +217,232 @@ static double finite_side(double lo, double hi) {
     return 0.0;
 }
 
-// ---------------------------------------------------------------- the handle
+// ---------------------------------------------------------------- per-LP host data and scaling
 
-struct hpr_handle {
+struct LpHost {
     int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    int64_t row_off = 0, col_off = 0;            // position in the pooled numbering
+    double beta_b = 1, beta_c = 1, lambda = 1, norm_b = 0, norm_c = 0, obj_offset = 0;
+    std::vector<double> dr, dc;                 // diagonal scaling
+    std::vector<double> lo_s, hi_s, l_s, u_s, c_s;   // scaled rows, bounds and cost
+    std::vector<double> x_start, y_start;       // start point in the original space (empty = zero)
+};
+
+// Section III-A: optional Ruiz passes (rows/columns divided by the square root of their
+// largest magnitude), Pock-Chambolle with alpha = 1 (divided by the square root of the
+// absolute row/column sums; empty ones keep 1), then the bounds are divided by
+// beta_b = 1 + ||b~|| (b~ the finite sides of the scaled rows) and the cost by
+// beta_c = 1 + ||c~||. Scales `a` in place and fills the LP's scaled vectors.
+static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& h) {
+    const int32_t m = lp->m, n = lp->n;
+    h.dr.assign((size_t)m, 1.0);
+    h.dc.assign((size_t)n, 1.0);
+    std::vector<double> er((size_t)m), ec((size_t)n);
+    auto apply = [&]() {
+        for (int32_t i = 0; i < m; ++i)
+            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) a.val[k] *= er[i] * ec[a.idx[k]];
+        for (int32_t i = 0; i < m; ++i) h.dr[i] *= er[i];
+        for (int32_t j = 0; j < n; ++j) h.dc[j] *= ec[j];
+    };
+    if (o.scaling & HPR_SCALE_RUIZ) {
+        for (int32_t it = 0; it < o.ruiz_iters; ++it) {
+            std::fill(ec.begin(), ec.end(), 0.0);
+            for (int32_t i = 0; i < m; ++i) {
+                double r = 0.0;
+                for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
+                    const double v = std::fabs(a.val[k]);
+                    r = std::max(r, v);
+                    ec[a.idx[k]] = std::max(ec[a.idx[k]], v);
+                }
+                er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
+            }
+            for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
+            apply();
+        }
+    }
+    if (o.scaling & HPR_SCALE_PC) {
+        std::fill(ec.begin(), ec.end(), 0.0);
+        for (int32_t i = 0; i < m; ++i) {
+            double r = 0.0;
+            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
+                r += std::fabs(a.val[k]);
+                ec[a.idx[k]] += std::fabs(a.val[k]);
+            }
+            er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
+        }
+        for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
+        apply();
+    }
+    h.lo_s.resize(m);
+    h.hi_s.resize(m);
+    for (int32_t i = 0; i < m; ++i) {
+        h.lo_s[i] = lp->row_lo[i] * h.dr[i];
+        h.hi_s[i] = lp->row_hi[i] * h.dr[i];
+    }
+    h.l_s.resize(n);
+    h.u_s.resize(n);
+    h.c_s.resize(n);
+    for (int32_t j = 0; j < n; ++j) {
+        h.l_s[j] = lp->col_lo[j] / h.dc[j];
+        h.u_s[j] = lp->col_hi[j] / h.dc[j];
+        h.c_s[j] = lp->c[j] * h.dc[j];
+    }
+    h.beta_b = h.beta_c = 1.0;
+    if (o.scaling & HPR_SCALE_BC) {
+        double b2 = 0.0, c2 = 0.0;
+        for (int32_t i = 0; i < m; ++i) {
+            const double b = finite_side(h.lo_s[i], h.hi_s[i]);
+            b2 += b * b;
+        }
+        for (int32_t j = 0; j < n; ++j) c2 += h.c_s[j] * h.c_s[j];
+        h.beta_b = 1.0 + std::sqrt(b2);
+        h.beta_c = 1.0 + std::sqrt(c2);
+        for (int32_t i = 0; i < m; ++i) {
+            h.lo_s[i] /= h.beta_b;
+            h.hi_s[i] /= h.beta_b;
+        }
+        for (int32_t j = 0; j < n; ++j) {
+            h.l_s[j] /= h.beta_b;
+            h.u_s[j] /= h.beta_b;
+            h.c_s[j] /= h.beta_c;
+        }
+    }
+    double b2 = 0.0, c2 = 0.0;   // norms of the original rhs and cost (relative residuals)
+    for (int32_t i = 0; i < m; ++i) {
+        const double b = finite_side(lp->row_lo[i], lp->row_hi[i]);
+        b2 += b * b;
+    }
+    for (int32_t j = 0; j < n; ++j) c2 += lp->c[j] * lp->c[j];
+    h.norm_b = std::sqrt(b2);
+    h.norm_c = std::sqrt(c2);
+    h.obj_offset = lp->obj_offset;
+}
+
+// ---------------------------------------------------------------- pooled matrices and schedules
+
+// The work list of one pooled matrix for U quads per lane and pass: per LP, per bin (bin b:
+// rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
+// rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
+static void make_schedule(const std::vector<int64_t>& start, const std::vector<int64_t>& lp_rows, int U,
+                          std::vector<int32_t>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
+    const int L = (int)lp_rows.size() - 1;
+    rows.clear();
+    sched.clear();
+    seg.assign((size_t)L + 1, 0);
+    std::vector<int32_t> by_bin[kNumBins];
+    for (int l = 0; l < L; ++l) {
+        seg[l] = (int32_t)sched.size();
+        for (auto& v : by_bin) v.clear();
+        for (int64_t i = lp_rows[l]; i < lp_rows[l + 1]; ++i) {
+            const int64_t quads = (start[i + 1] - start[i]) / kVec;
+            int b = 0;
+            while (b < kNumBins - 1 && (int64_t)U * (int64_t(1) << b) < quads) ++b;
+            by_bin[b].push_back((int32_t)i);
+        }
+        for (int b = 0; b < kNumBins; ++b) {
+            const int per_block = kBlock >> b;
+            for (size_t k = 0; k < by_bin[b].size(); k += per_block) {
+                BlockDesc d;
+                d.bin = b;
+                d.lp = l;
+                d.first = (int32_t)rows.size();
+                d.count = (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k);
+                sched.push_back(d);
+                rows.insert(rows.end(), by_bin[b].begin() + k, by_bin[b].begin() + k + d.count);
+            }
+        }
+    }
+    seg[L] = (int32_t)sched.size();
+}
+
+struct DevMatrix {
+    DBuf start, col, rows, sched, seg, val64, val32;
+    std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
+    int32_t nrows = 0, nblocks = 0, unroll = 4;
+    int64_t padded = 0;
+    void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, bool fp32, hipStream_t st) {
+        nrows = (int32_t)L.start.size() - 1;
+        padded = (int64_t)L.col.size();
+        start_h = L.start;
+        lp_rows = lp_rows_in;
+        upload(start, L.start, st);
+        upload(col, L.col, st);
+        upload(val64, L.val, st);
+        if (fp32) {
+            val32.alloc(L.val.size() * sizeof(float));
+            launch_cast<float>(val64.as<double>(), val32.as<float>(), (int64_t)L.val.size(), st);
+        }
+        set_unroll(4, st);
+    }
+    void set_unroll(int U, hipStream_t st) {
+        std::vector<int32_t> r, sg;
+        std::vector<BlockDesc> sc;
+        make_schedule(start_h, lp_rows, U, r, sc, sg);
+        unroll = U;
+        nblocks = (int32_t)sc.size();
+        upload(rows, r, st);
+        upload(sched, sc, st);
+        upload(seg, sg, st);
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    template <typename T>
+    DevCsr<T> view() const {
+        DevCsr<T> d;
+        d.start = start.as<int64_t>();
+        d.col = col.as<int32_t>();
+        d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
+        d.rows = rows.as<int32_t>();
+        d.sched = sched.as<BlockDesc>();
+        d.nblocks = nblocks;
+        d.unroll = unroll;
+        return d;
+    }
+};
+
+// ---------------------------------------------------------------- the engine (one LP or a batch)
+
+struct Engine {
+    int L = 0;
+    int64_t M = 0, N = 0;                       // pooled rows and columns
     hpr_opts opts{};
     bool fp32 = false;
     hipStream_t st = nullptr;
     bool own_stream = false;
     int device = 0;
-
-    double beta_b = 1, beta_c = 1, lambda = 1, norm_b = 0, norm_c = 0, obj_offset = 0;
-    std::vector<double> dr, dc;                 // diagonal scaling
-    std::vector<double> lo_s, hi_s, l_s, u_s;   // scaled bounds (host copies)
-    std::vector<double> x_start, y_start;       // start point in the original space (empty = zero)
+    std::vector<LpHost> lps;
 
     DevMatrix A, At;
     DBuf c64, l64, u64, lo64, hi64, c32, l32, u32, lo32, hi32, dr_d, dc_d;
     DBuf x, x0, xh, xb, zb, dx, y, y0, yb, dy;
-    DBuf part_r, part_c, sums, ctrl;
-    DBuf ux, uy, uz;                            // unscaled FP64 output
-    double* pinned = nullptr;                   // host-visible sums
-    Ctrl* ctrl_h = nullptr;
+    DBuf part_r, part_c, sums, sums64, ctrl, state, stat;
+    DBuf ux, uy, uz;
+    int32_t* stat_h = nullptr;                  // pinned
+    std::vector<Ctrl> ctrl_h;
+    std::vector<LpState> state_h;
 
-    bool solved_once = false;
-    double setup_s = 0;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // profiling marks
+    hipGraphExec_t g_first = nullptr, g_block = nullptr;
+    bool graphs_built = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     hpr_kernel_stats kstats{};
+    bool solved_once = false;
+    double setup_s = 0, solve_s = 0;
 
-    ~hpr_handle() {
+    ~Engine() {
         if (st) (void)hipStreamSynchronize(st);
+        drop_graphs();
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
-        if (pinned) (void)hipHostFree(pinned);
-        if (ctrl_h) (void)hipHostFree(ctrl_h);
+        if (stat_h) (void)hipHostFree(stat_h);
         if (own_stream && st) (void)hipStreamDestroy(st);
     }
+    void drop_graphs() {
+        if (g_first) (void)hipGraphExecDestroy(g_first);
+        if (g_block) (void)hipGraphExecDestroy(g_block);
+        g_first = g_block = nullptr;
+        graphs_built = false;
+    }
+    void sync() { HIP_OK(hipStreamSynchronize(st)); }
 
     template <typename T>
     DevProb<T> prob() const {
@@ -368,225 +486,116 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->power_tol = 1e-6;
     o->profile = 0;
     o->unroll = 0;
+    o->use_graph = 1;
     o->stream = nullptr;
 }
 
 extern "C" const char* hpr_last_error(void) { return g_err.c_str(); }
 
-// ---------------------------------------------------------------- setup
-
-static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, hpr_handle* h) {
-    const int32_t m = lp->m, n = lp->n;
-    h->dr.assign((size_t)m, 1.0);
-    h->dc.assign((size_t)n, 1.0);
-    std::vector<double> er((size_t)m), ec((size_t)n);
-    auto apply = [&]() {
-        for (int32_t i = 0; i < m; ++i)
-            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) a.val[k] *= er[i] * ec[a.idx[k]];
-        for (int32_t i = 0; i < m; ++i) h->dr[i] *= er[i];
-        for (int32_t j = 0; j < n; ++j) h->dc[j] *= ec[j];
-    };
-    if (o.scaling & HPR_SCALE_RUIZ) {
-        for (int32_t it = 0; it < o.ruiz_iters; ++it) {
-            std::fill(ec.begin(), ec.end(), 0.0);
-            for (int32_t i = 0; i < m; ++i) {
-                double r = 0.0;
-                for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-                    const double v = std::fabs(a.val[k]);
-                    r = std::max(r, v);
-                    ec[a.idx[k]] = std::max(ec[a.idx[k]], v);
-                }
-                er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
-            }
-            for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
-            apply();
-        }
+// upload the pooled scaled vectors (and their FP32 copies)
+static void upload_vectors(Engine* e) {
+    std::vector<double> c(e->N), l(e->N), u(e->N), dc(e->N), lo(e->M), hi(e->M), dr(e->M);
+    for (const LpHost& h : e->lps) {
+        std::copy(h.c_s.begin(), h.c_s.end(), c.begin() + h.col_off);
+        std::copy(h.l_s.begin(), h.l_s.end(), l.begin() + h.col_off);
+        std::copy(h.u_s.begin(), h.u_s.end(), u.begin() + h.col_off);
+        std::copy(h.dc.begin(), h.dc.end(), dc.begin() + h.col_off);
+        std::copy(h.lo_s.begin(), h.lo_s.end(), lo.begin() + h.row_off);
+        std::copy(h.hi_s.begin(), h.hi_s.end(), hi.begin() + h.row_off);
+        std::copy(h.dr.begin(), h.dr.end(), dr.begin() + h.row_off);
     }
-    if (o.scaling & HPR_SCALE_PC) {
-        std::fill(ec.begin(), ec.end(), 0.0);
-        for (int32_t i = 0; i < m; ++i) {
-            double r = 0.0;
-            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-                r += std::fabs(a.val[k]);
-                ec[a.idx[k]] += std::fabs(a.val[k]);
-            }
-            er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
-        }
-        for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
-        apply();
+    hipStream_t st = e->st;
+    upload(e->c64, c, st);
+    upload(e->l64, l, st);
+    upload(e->u64, u, st);
+    upload(e->lo64, lo, st);
+    upload(e->hi64, hi, st);
+    upload(e->dr_d, dr, st);
+    upload(e->dc_d, dc, st);
+    if (e->fp32) {
+        const int64_t n = e->N, m = std::max<int64_t>(e->M, 1);
+        e->c32.alloc(sizeof(float) * n);
+        e->l32.alloc(sizeof(float) * n);
+        e->u32.alloc(sizeof(float) * n);
+        e->lo32.alloc(sizeof(float) * m);
+        e->hi32.alloc(sizeof(float) * m);
+        launch_cast<float>(e->c64.as<double>(), e->c32.as<float>(), e->N, st);
+        launch_cast<float>(e->l64.as<double>(), e->l32.as<float>(), e->N, st);
+        launch_cast<float>(e->u64.as<double>(), e->u32.as<float>(), e->N, st);
+        launch_cast<float>(e->lo64.as<double>(), e->lo32.as<float>(), e->M, st);
+        launch_cast<float>(e->hi64.as<double>(), e->hi32.as<float>(), e->M, st);
     }
-    h->lo_s.resize(m);
-    h->hi_s.resize(m);
-    for (int32_t i = 0; i < m; ++i) {
-        h->lo_s[i] = lp->row_lo[i] * h->dr[i];
-        h->hi_s[i] = lp->row_hi[i] * h->dr[i];
-    }
-    h->l_s.resize(n);
-    h->u_s.resize(n);
-    std::vector<double> cs(n);
-    for (int32_t j = 0; j < n; ++j) {
-        h->l_s[j] = lp->col_lo[j] / h->dc[j];
-        h->u_s[j] = lp->col_hi[j] / h->dc[j];
-        cs[j] = lp->c[j] * h->dc[j];
-    }
-    h->beta_b = h->beta_c = 1.0;
-    if (o.scaling & HPR_SCALE_BC) {
-        double b2 = 0.0, c2 = 0.0;
-        for (int32_t i = 0; i < m; ++i) {
-            const double b = finite_side(h->lo_s[i], h->hi_s[i]);
-            b2 += b * b;
-        }
-        for (int32_t j = 0; j < n; ++j) c2 += cs[j] * cs[j];
-        h->beta_b = 1.0 + std::sqrt(b2);
-        h->beta_c = 1.0 + std::sqrt(c2);
-        for (int32_t i = 0; i < m; ++i) {
-            h->lo_s[i] /= h->beta_b;
-            h->hi_s[i] /= h->beta_b;
-        }
-        for (int32_t j = 0; j < n; ++j) {
-            h->l_s[j] /= h->beta_b;
-            h->u_s[j] /= h->beta_b;
-            cs[j] /= h->beta_c;
-        }
-    }
-    // norms of the original rhs and cost for the relative residuals
-    double b2 = 0.0, c2 = 0.0;
-    for (int32_t i = 0; i < m; ++i) {
-        const double b = finite_side(lp->row_lo[i], lp->row_hi[i]);
-        b2 += b * b;
-    }
-    for (int32_t j = 0; j < n; ++j) c2 += lp->c[j] * lp->c[j];
-    h->norm_b = std::sqrt(b2);
-    h->norm_c = std::sqrt(c2);
-
-    hipStream_t st = h->st;
-    upload(h->c64, cs, st);
-    upload(h->l64, h->l_s, st);
-    upload(h->u64, h->u_s, st);
-    upload(h->lo64, h->lo_s, st);
-    upload(h->hi64, h->hi_s, st);
-    upload(h->dr_d, h->dr, st);
-    upload(h->dc_d, h->dc, st);
-    if (h->fp32) {
-        h->c32.alloc(sizeof(float) * n);
-        h->l32.alloc(sizeof(float) * n);
-        h->u32.alloc(sizeof(float) * n);
-        h->lo32.alloc(sizeof(float) * std::max(m, 1));
-        h->hi32.alloc(sizeof(float) * std::max(m, 1));
-        launch_cast<float>(h->c64.as<double>(), h->c32.as<float>(), n, st);
-        launch_cast<float>(h->l64.as<double>(), h->l32.as<float>(), n, st);
-        launch_cast<float>(h->u64.as<double>(), h->u32.as<float>(), n, st);
-        launch_cast<float>(h->lo64.as<double>(), h->lo32.as<float>(), m, st);
-        launch_cast<float>(h->hi64.as<double>(), h->hi32.as<float>(), m, st);
-    }
-    HIP_OK(hipStreamSynchronize(st));   // `cs` is a local host vector
+    e->sync();   // the host vectors above are locals
 }
 
-static void sync(hpr_handle* h) { HIP_OK(hipStreamSynchronize(h->st)); }
-
-// lambda_max(A~ A~^T) by the power method in FP64 on the device: v <- A~(A~^T v)/||.||,
-// estimate ||A~ A~^T v|| for unit v; stop at relative change <= power_tol or after
-// power_max_iter products; lambda = 1.01 * estimate, capped at 1 when the Pock-Chambolle
-// scaling is on (it bounds ||A~|| by 1), and 1 when the estimate is 0.
-static double power_method(hpr_handle* h) {
-    const int32_t m = h->m, n = h->n;
-    if (m == 0 || h->A.padded == 0) return 1.0;
-    DBuf v, t, w, part;
-    v.alloc(sizeof(double) * m);
-    w.alloc(sizeof(double) * m);
-    t.alloc(sizeof(double) * n);
-    const int nb = sumsq_blocks(m);
-    part.alloc(sizeof(double) * nb);
-    DBuf tot;
-    tot.alloc(sizeof(double));
-    hipStream_t st = h->st;
-    DevCsr<double> A = h->A.view<double>(), At = h->At.view<double>();
-    auto norm = [&](const double* p) {
-        launch_sumsq<double>(p, m, part.as<double>(), st);
-        launch_finish_sums(part.as<double>(), 1, nb, tot.as<double>(), st);
-        double s = 0;
-        HIP_OK(hipMemcpyAsync(&s, tot.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        sync(h);
-        return std::sqrt(s);
-    };
-    launch_start_vector<double>(v.as<double>(), m, h->opts.seed, st);
-    const double nv = norm(v.as<double>());
-    launch_scale<double>(v.as<double>(), m, 1.0 / nv, st);
-    double est = 0.0, prev = 0.0;
-    for (int it = 1; it <= h->opts.power_max_iter; ++it) {
-        launch_spmv<double>(At, v.as<double>(), t.as<double>(), st);
-        launch_spmv<double>(A, t.as<double>(), w.as<double>(), st);
-        est = norm(w.as<double>());
-        if (est == 0.0) break;
-        launch_scale<double>(w.as<double>(), m, 1.0 / est, st);
-        std::swap(v.p, w.p);
-        if (it > 1 && std::fabs(est - prev) <= h->opts.power_tol * est) break;
-        prev = est;
-    }
-    if (est == 0.0) return 1.0;
-    double lam = 1.01 * est;
-    if ((h->opts.scaling & HPR_SCALE_PC) && lam > 1.0) lam = 1.0;
-    return lam;
+static void alloc_iterates(Engine* e) {
+    const size_t es = e->fp32 ? sizeof(float) : sizeof(double);
+    const size_t n = (size_t)e->N, m = (size_t)std::max<int64_t>(e->M, 1);
+    for (DBuf* b : {&e->x, &e->x0, &e->xh, &e->xb, &e->zb, &e->dx}) b->alloc(es * n);
+    for (DBuf* b : {&e->y, &e->y0, &e->yb, &e->dy}) b->alloc(es * m);
+    e->sums.alloc(sizeof(double) * kSumStride * e->L);
+    e->sums64.alloc(sizeof(double) * kSumStride * e->L);
+    e->ctrl.alloc(sizeof(Ctrl) * e->L);
+    e->state.alloc(sizeof(LpState) * e->L);
+    e->stat.alloc(sizeof(int32_t) * 2);
+    e->ux.alloc(sizeof(double) * n);
+    e->uy.alloc(sizeof(double) * m);
+    e->uz.alloc(sizeof(double) * n);
+    HIP_OK(hipHostMalloc((void**)&e->stat_h, sizeof(int32_t) * 2, hipHostMallocDefault));
+    e->ctrl_h.assign(e->L, Ctrl{});
+    e->state_h.assign(e->L, LpState{});
 }
 
-static void alloc_iterates(hpr_handle* h) {
-    const size_t es = h->fp32 ? sizeof(float) : sizeof(double);
-    const size_t n = (size_t)h->n, m = (size_t)std::max(h->m, 1);
-    for (DBuf* b : {&h->x, &h->x0, &h->xh, &h->xb, &h->zb, &h->dx}) b->alloc(es * n);
-    for (DBuf* b : {&h->y, &h->y0, &h->yb, &h->dy}) b->alloc(es * m);
-    h->sums.alloc(sizeof(double) * 2 * kMaxQ);
-    h->ctrl.alloc(sizeof(Ctrl));
-    h->ux.alloc(sizeof(double) * n);
-    h->uy.alloc(sizeof(double) * m);
-    h->uz.alloc(sizeof(double) * n);
-    HIP_OK(hipHostMalloc((void**)&h->pinned, sizeof(double) * 2 * kMaxQ, hipHostMallocDefault));
-    HIP_OK(hipHostMalloc((void**)&h->ctrl_h, sizeof(Ctrl), hipHostMallocDefault));
+static void alloc_partials(Engine* e) {
+    e->part_r.alloc(sizeof(double) * kRowQ * std::max(e->A.nblocks, 1));
+    e->part_c.alloc(sizeof(double) * kColQ * std::max(e->At.nblocks, 1));
 }
 
-// per-block partial sums of the check kernels (block counts depend on the bins)
-static void alloc_partials(hpr_handle* h) {
-    const int nbr = std::max(h->A.bins.block_off[kNumBins], 1);
-    const int nbc = std::max(h->At.bins.block_off[kNumBins], 1);
-    h->part_r.alloc(sizeof(double) * kRowQ * nbr);
-    h->part_c.alloc(sizeof(double) * kColQ * nbc);
+static void put_ctrl(Engine* e) {
+    HIP_OK(hipMemcpyAsync(e->ctrl.p, e->ctrl_h.data(), sizeof(Ctrl) * e->L, hipMemcpyHostToDevice, e->st));
+    e->sync();
 }
 
-// Schedule tuner: for each matrix, time the fused step kernel that streams it (dual step
-// for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass (the bins
-// follow U), and keep the fastest. A forced opts.unroll skips the timing.
+// Schedule tuner: for each pooled matrix, time the fused step kernel that streams it (dual
+// step for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass, and keep
+// the fastest. A forced opts.unroll skips the timing.
 template <typename T>
-static void autotune(hpr_handle* h) {
-    hipStream_t st = h->st;
-    const size_t es = sizeof(T);
-    for (DBuf* b : {&h->x, &h->x0, &h->xh, &h->xb, &h->zb, &h->dx, &h->y, &h->y0, &h->yb, &h->dy})
+static void autotune(Engine* e) {
+    hipStream_t st = e->st;
+    for (DBuf* b : {&e->x, &e->x0, &e->xh, &e->xb, &e->zb, &e->dx, &e->y, &e->y0, &e->yb, &e->dy})
         HIP_OK(hipMemsetAsync(b->p, 0, b->bytes, st));
-    (void)es;
-    h->ctrl_h->sigma = 1.0;
-    h->ctrl_h->s = 1.0;
-    h->ctrl_h->lambda = 1.0;
-    h->ctrl_h->k_base = 0;
-    HIP_OK(hipMemcpyAsync(h->ctrl.p, h->ctrl_h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
-    const int forced = h->opts.unroll;
+    for (int l = 0; l < e->L; ++l) {
+        Ctrl& c = e->ctrl_h[l];
+        c = Ctrl{};
+        c.sigma = 1.0;
+        c.s = 1.0;
+        c.lambda = 1.0;
+        c.beta_b = e->lps[l].beta_b;
+        c.beta_c = e->lps[l].beta_c;
+        c.active = 1;
+    }
+    put_ctrl(e);
+    const int forced = e->opts.unroll;
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    const DevProb<T> p = h->prob<T>();
-    const DevIter<T> v = h->iter<T>();
+    const DevProb<T> p = e->prob<T>();
+    const DevIter<T> v = e->iter<T>();
     for (int which = 0; which < 2; ++which) {
-        DevMatrix& M = which == 0 ? h->A : h->At;
+        DevMatrix& Mx = which == 0 ? e->A : e->At;
         if (forced) {
-            M.set_unroll(forced, st);
+            Mx.set_unroll(forced, st);
             continue;
         }
-        if (M.nrows == 0) continue;
+        if (Mx.nrows == 0) continue;
         int bestU = 4;
         float best = 1e30f;
         for (int U : {1, 2, 4, 8}) {
-            M.set_unroll(U, st);
-            const DevCsr<T> view = M.view<T>();
+            Mx.set_unroll(U, st);
+            const DevCsr<T> view = Mx.view<T>();
             auto launch = [&]() {
-                if (which == 0) launch_dual_step<T>(view, p, v, h->ctrl.as<Ctrl>(), 0, false, st);
-                else launch_primal_step<T>(view, p, v, h->ctrl.as<Ctrl>(), 0, false, st);
+                if (which == 0) launch_dual_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
+                else launch_primal_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
             };
             for (int r = 0; r < 2; ++r) launch();
             HIP_OK(hipEventRecord(e0, st));
@@ -600,121 +609,244 @@ static void autotune(hpr_handle* h) {
                 bestU = U;
             }
         }
-        M.set_unroll(bestU, st);
+        Mx.set_unroll(bestU, st);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_OK(hipGetLastError());
 }
 
-extern "C" int hpr_create(const hpr_lp* lp, const hpr_opts* opts_in, hpr_handle** out) {
+// lambda_l = lambda_max(A~_l A~_l^T) for every LP by the power method in FP64 on the pooled
+// matrix: v <- A~(A~^T v), normalised per LP; estimate ||A~ A~^T v|| for unit v; an LP stops
+// at relative change <= power_tol or after power_max_iter products; lambda = 1.01 * estimate,
+// capped at 1 when the Pock-Chambolle scaling is on (it bounds ||A~|| by 1), and 1 when the
+// estimate is 0. Start vectors: SplitMix64 with LP-local indices.
+static void power_method(Engine* e) {
+    const int L = e->L;
+    hipStream_t st = e->st;
+    std::vector<int64_t> seg(L + 1);
+    int max_chunks = 1;
+    for (int l = 0; l < L; ++l) {
+        seg[l] = e->lps[l].row_off;
+        max_chunks = std::max<int>(max_chunks, (int)((e->lps[l].m + kChunk - 1) / kChunk));
+    }
+    seg[L] = e->M;
+    std::vector<int32_t> bseg(L + 1);
+    for (int l = 0; l <= L; ++l) bseg[l] = l * max_chunks;
+    std::vector<char> done(L, 0);
+    std::vector<double> est(L, 0.0), prev(L, 0.0);
+    for (int l = 0; l < L; ++l)
+        if (e->lps[l].m == 0 || e->lps[l].nnz == 0) done[l] = 1;
+    const bool any = std::find(done.begin(), done.end(), 0) != done.end();
+    if (any) {
+        DBuf v, t, w, part, segd, bsegd, fac;
+        v.alloc(sizeof(double) * std::max<int64_t>(e->M, 1));
+        w.alloc(sizeof(double) * std::max<int64_t>(e->M, 1));
+        t.alloc(sizeof(double) * std::max<int64_t>(e->N, 1));
+        part.alloc(sizeof(double) * L * max_chunks);
+        upload(segd, seg, st);
+        upload(bsegd, bseg, st);
+        fac.alloc(sizeof(double) * L);
+        std::vector<double> sums_h((size_t)L * kSumStride), f(L);
+        const DevCsr<double> A = e->A.view<double>(), At = e->At.view<double>();
+        auto norms = [&](const double* p) {
+            launch_seg_sumsq(p, segd.as<int64_t>(), L, max_chunks, part.as<double>(), st);
+            launch_finish_sums(part.as<double>(), 1, L * max_chunks, bsegd.as<int32_t>(), L, e->sums.as<double>(), 0,
+                               st);
+            HIP_OK(hipMemcpyAsync(sums_h.data(), e->sums.p, sizeof(double) * L * kSumStride, hipMemcpyDeviceToHost,
+                                  st));
+            e->sync();
+        };
+        auto scale = [&](double* p) {
+            HIP_OK(hipMemcpyAsync(fac.p, f.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+            launch_seg_scale(p, segd.as<int64_t>(), L, max_chunks, fac.as<double>(), st);
+            e->sync();
+        };
+        launch_seg_start_vector(v.as<double>(), segd.as<int64_t>(), L, max_chunks, e->opts.seed, st);
+        norms(v.as<double>());
+        for (int l = 0; l < L; ++l) {
+            const double nv = std::sqrt(sums_h[(size_t)l * kSumStride]);
+            f[l] = nv > 0 ? 1.0 / nv : 1.0;
+        }
+        scale(v.as<double>());
+        for (int it = 1; it <= e->opts.power_max_iter; ++it) {
+            launch_spmv<double>(At, v.as<double>(), t.as<double>(), st);
+            launch_spmv<double>(A, t.as<double>(), w.as<double>(), st);
+            norms(w.as<double>());
+            bool all = true;
+            for (int l = 0; l < L; ++l) {
+                const double s = std::sqrt(sums_h[(size_t)l * kSumStride]);
+                f[l] = s > 0 ? 1.0 / s : 1.0;
+                if (done[l]) continue;
+                est[l] = s;
+                if (s == 0.0) done[l] = 1;
+                else if (it > 1 && std::fabs(s - prev[l]) <= e->opts.power_tol * s) done[l] = 1;
+                else prev[l] = s;
+                all = all && done[l];
+            }
+            scale(w.as<double>());
+            std::swap(v.p, w.p);
+            if (all) break;
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        LpHost& h = e->lps[l];
+        if (h.m == 0 || h.nnz == 0 || est[l] == 0.0) {
+            h.lambda = 1.0;
+            continue;
+        }
+        double lam = 1.01 * est[l];
+        if ((e->opts.scaling & HPR_SCALE_PC) && lam > 1.0) lam = 1.0;
+        h.lambda = lam;
+    }
+}
+
+static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, Engine** out) {
     g_err.clear();
     if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
     *out = nullptr;
+    if (count < 1 || count > kMaxBatch) return fail(HPR_ERR_INVALID, "count must be in [1, %d]", kMaxBatch);
+    if (!lps) return fail(HPR_ERR_INVALID, "lp is NULL");
     hpr_opts o;
-    if (opts_in) o = *opts_in; else hpr_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    else hpr_default_opts(&o);
     int rc = validate_opts(&o);
     if (rc) return rc;
-    rc = validate(lp);
-    if (rc) return rc;
+    for (int l = 0; l < count; ++l) {
+        rc = validate(&lps[l]);
+        if (rc) {
+            if (count > 1) {
+                std::string msg = g_err;
+                return fail(rc, "LP %d: %s", l, msg.c_str());
+            }
+            return rc;
+        }
+    }
     const double t0 = now_s();
-    std::unique_ptr<hpr_handle> h;
+    std::unique_ptr<Engine> e;
     try {
-        h.reset(new hpr_handle());
-        h->m = lp->m;
-        h->n = lp->n;
-        h->opts = o;
-        h->fp32 = o.precision == HPR_FP32;
-        h->obj_offset = lp->obj_offset;
-        HIP_OK(hipGetDevice(&h->device));
+        e.reset(new Engine());
+        e->L = count;
+        e->opts = o;
+        e->fp32 = o.precision == HPR_FP32;
+        e->lps.resize(count);
+        HIP_OK(hipGetDevice(&e->device));
         if (o.stream) {
-            h->st = (hipStream_t)o.stream;
+            e->st = (hipStream_t)o.stream;
         } else {
-            HIP_OK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
-            h->own_stream = true;
+            HIP_OK(hipStreamCreateWithFlags(&e->st, hipStreamNonBlocking));
+            e->own_stream = true;
         }
-        HostCsr a;
-        a.rows = lp->m;
-        a.cols = lp->n;
-        if (lp->m > 0) a.ptr.assign(lp->row_ptr, lp->row_ptr + lp->m + 1);
-        else a.ptr.assign(1, 0);
-        a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
-        a.val.assign(lp->val, lp->val + lp->nnz);
-        scale_host(lp, o, a, h.get());
-        HostCsr at = transpose(a);
-        {
-            Layout la = make_layout(a);
-            h->A.upload_from(la, h->fp32, h->st);
-            Layout lt = make_layout(at);
-            h->At.upload_from(lt, h->fp32, h->st);
-            sync(h.get());   // host layouts are freed at scope end
+        Layout PA, PAt;
+        PA.start.assign(1, 0);
+        PAt.start.assign(1, 0);
+        std::vector<int64_t> rows_a(1, 0), rows_at(1, 0);
+        for (int l = 0; l < count; ++l) {
+            const hpr_lp* lp = &lps[l];
+            LpHost& h = e->lps[l];
+            h.m = lp->m;
+            h.n = lp->n;
+            h.nnz = lp->nnz;
+            h.row_off = e->M;
+            h.col_off = e->N;
+            HostCsr a;
+            a.rows = lp->m;
+            a.cols = lp->n;
+            if (lp->m > 0) a.ptr.assign(lp->row_ptr, lp->row_ptr + lp->m + 1);
+            else a.ptr.assign(1, 0);
+            a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
+            a.val.assign(lp->val, lp->val + lp->nnz);
+            scale_host(lp, o, a, h);
+            const HostCsr at = transpose(a);
+            const Layout la = make_layout(a), lt = make_layout(at);
+            // append to the pools with global column indices
+            const int64_t base_a = PA.start.back(), base_t = PAt.start.back();
+            for (size_t i = 1; i < la.start.size(); ++i) PA.start.push_back(base_a + la.start[i]);
+            for (int32_t c : la.col) PA.col.push_back(c + (int32_t)h.col_off);
+            PA.val.insert(PA.val.end(), la.val.begin(), la.val.end());
+            for (size_t i = 1; i < lt.start.size(); ++i) PAt.start.push_back(base_t + lt.start[i]);
+            for (int32_t c : lt.col) PAt.col.push_back(c + (int32_t)h.row_off);
+            PAt.val.insert(PAt.val.end(), lt.val.begin(), lt.val.end());
+            e->M += lp->m;
+            e->N += lp->n;
+            rows_a.push_back(e->M);
+            rows_at.push_back(e->N);
+            if (e->M > INT32_MAX || e->N > INT32_MAX) {
+                fail(HPR_ERR_INVALID, "pooled rows or columns exceed 2^31");
+                throw HipError{HPR_ERR_INVALID};
+            }
         }
-        alloc_iterates(h.get());
-        if (h->fp32) autotune<float>(h.get());
-        else autotune<double>(h.get());
-        alloc_partials(h.get());
-        h->lambda = o.lambda > 0 ? o.lambda : power_method(h.get());
-        sync(h.get());
-    } catch (const HipError& e) {
-        return e.code;
+        e->A.upload_from(PA, rows_a, e->fp32, e->st);
+        e->At.upload_from(PAt, rows_at, e->fp32, e->st);
+        e->sync();
+        upload_vectors(e.get());
+        alloc_iterates(e.get());
+        if (e->fp32) autotune<float>(e.get());
+        else autotune<double>(e.get());
+        alloc_partials(e.get());
+        if (o.lambda > 0) {
+            for (LpHost& h : e->lps) h.lambda = o.lambda;
+        } else {
+            power_method(e.get());
+        }
+        e->sync();
+    } catch (const HipError& err) {
+        return err.code;
     } catch (const std::bad_alloc&) {
         return fail(HPR_ERR_NOMEM, "host allocation failed");
     }
-    h->setup_s = now_s() - t0;
-    *out = h.release();
+    e->setup_s = now_s() - t0;
+    *out = e.release();
     return HPR_OK;
 }
 
-extern "C" int hpr_destroy(hpr_handle* h) {
-    delete h;
-    return HPR_OK;
-}
-
-extern "C" int hpr_set_bounds(hpr_handle* h, const double* col_lo, const double* col_hi) {
-    g_err.clear();
-    if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
-    const int32_t n = h->n;
-    std::vector<double> lo(h->l_s), hi(h->u_s);
+static int engine_set_bounds(Engine* e, int i, const double* col_lo, const double* col_hi) {
+    if (i < 0 || i >= e->L) return fail(HPR_ERR_INVALID, "LP index %d out of range", i);
+    LpHost& h = e->lps[i];
+    const int32_t n = h.n;
+    std::vector<double> lo(h.l_s), hi(h.u_s);
     for (int32_t j = 0; j < n; ++j) {
-        const double a = col_lo ? col_lo[j] : h->l_s[j] * h->beta_b * h->dc[j];
-        const double b = col_hi ? col_hi[j] : h->u_s[j] * h->beta_b * h->dc[j];
+        const double a = col_lo ? col_lo[j] : h.l_s[j] * h.beta_b * h.dc[j];
+        const double b = col_hi ? col_hi[j] : h.u_s[j] * h.beta_b * h.dc[j];
         if (std::isnan(a) || std::isnan(b) || a > b || a == INFINITY || b == -INFINITY)
             return fail(HPR_ERR_INVALID, "bad column bounds at %d", j);
-        if (col_lo) lo[j] = a / (h->beta_b * h->dc[j]);
-        if (col_hi) hi[j] = b / (h->beta_b * h->dc[j]);
+        if (col_lo) lo[j] = a / (h.beta_b * h.dc[j]);
+        if (col_hi) hi[j] = b / (h.beta_b * h.dc[j]);
     }
     try {
-        h->l_s = lo;
-        h->u_s = hi;
-        HIP_OK(hipMemcpyAsync(h->l64.p, lo.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->st));
-        HIP_OK(hipMemcpyAsync(h->u64.p, hi.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->st));
-        if (h->fp32) {
-            launch_cast<float>(h->l64.as<double>(), h->l32.as<float>(), n, h->st);
-            launch_cast<float>(h->u64.as<double>(), h->u32.as<float>(), n, h->st);
+        h.l_s = lo;
+        h.u_s = hi;
+        double* l64 = e->l64.as<double>() + h.col_off;
+        double* u64 = e->u64.as<double>() + h.col_off;
+        HIP_OK(hipMemcpyAsync(l64, h.l_s.data(), sizeof(double) * n, hipMemcpyHostToDevice, e->st));
+        HIP_OK(hipMemcpyAsync(u64, h.u_s.data(), sizeof(double) * n, hipMemcpyHostToDevice, e->st));
+        if (e->fp32) {
+            launch_cast<float>(l64, e->l32.as<float>() + h.col_off, n, e->st);
+            launch_cast<float>(u64, e->u32.as<float>() + h.col_off, n, e->st);
         }
-        sync(h);
-    } catch (const HipError& e) {
-        return e.code;
+        e->sync();
+    } catch (const HipError& err) {
+        return err.code;
     }
     return HPR_OK;
 }
 
-extern "C" int hpr_set_start(hpr_handle* h, const double* x0, const double* y0) {
-    g_err.clear();
-    if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
+static int engine_set_start(Engine* e, int i, const double* x0, const double* y0) {
+    if (i < 0 || i >= e->L) return fail(HPR_ERR_INVALID, "LP index %d out of range", i);
+    LpHost& h = e->lps[i];
     if (x0) {
-        for (int32_t j = 0; j < h->n; ++j)
+        for (int32_t j = 0; j < h.n; ++j)
             if (!std::isfinite(x0[j])) return fail(HPR_ERR_INVALID, "non-finite x0 at %d", j);
-        h->x_start.assign(x0, x0 + h->n);
+        h.x_start.assign(x0, x0 + h.n);
     } else {
-        h->x_start.clear();
+        h.x_start.clear();
     }
     if (y0) {
-        for (int32_t i = 0; i < h->m; ++i)
-            if (!std::isfinite(y0[i])) return fail(HPR_ERR_INVALID, "non-finite y0 at %d", i);
-        h->y_start.assign(y0, y0 + h->m);
+        for (int32_t r = 0; r < h.m; ++r)
+            if (!std::isfinite(y0[r])) return fail(HPR_ERR_INVALID, "non-finite y0 at %d", r);
+        h.y_start.assign(y0, y0 + h.m);
     } else {
-        h->y_start.clear();
+        h.y_start.clear();
     }
     return HPR_OK;
 }
@@ -723,244 +855,375 @@ extern "C" int hpr_set_start(hpr_handle* h, const double* x0, const double* y0) 
 
 namespace {
 
-struct CheckVals {
-    double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit, move_x, move_y;
-    bool bad;
-};
-
-// Launches both check kernels and the fixed-order finish; returns the host-side values.
-template <typename Tm, typename Tp, typename Tv>
-CheckVals run_check(hpr_handle* h, double sigma) {
-    hipStream_t st = h->st;
-    const DevCsr<Tm> A = h->A.view<Tm>();
-    const DevCsr<Tm> At = h->At.view<Tm>();
-    const DevProb<Tp> p = h->prob<Tp>();
-    const DevIter<Tv> v = h->iter<Tv>();
-    const int nbr = A.bins.block_off[kNumBins], nbc = At.bins.block_off[kNumBins];
-    double* sums = h->sums.as<double>();
-    if (nbr > 0) {
-        launch_check_rows<Tm, Tp, Tv>(A, p, v, h->beta_b, h->part_r.as<double>(), st);
-        launch_finish_sums(h->part_r.as<double>(), kRowQ, nbr, sums, st);
-    } else {
-        HIP_OK(hipMemsetAsync(sums, 0, sizeof(double) * kMaxQ, st));
-    }
-    launch_check_cols<Tm, Tp, Tv>(At, p, v, h->beta_c, h->part_c.as<double>(), st);
-    launch_finish_sums(h->part_c.as<double>(), kColQ, nbc, sums + kMaxQ, st);
-    HIP_OK(hipMemcpyAsync(h->pinned, sums, sizeof(double) * 2 * kMaxQ, hipMemcpyDeviceToHost, st));
-    sync(h);
-    const double* r = h->pinned;
-    const double* c = h->pinned + kMaxQ;
-    CheckVals cv;
-    const double bb = h->beta_b * h->beta_c;
-    cv.rel_p = std::sqrt(r[0]) / (1.0 + h->norm_b);
-    cv.rel_d = std::sqrt(c[0]) / (1.0 + h->norm_c);
-    cv.pobj = bb * c[1] + h->obj_offset;
-    cv.dobj = bb * (r[3] + c[2]) + h->obj_offset;
-    cv.rel_gap = std::fabs(cv.pobj - cv.dobj) / (1.0 + std::fabs(cv.pobj) + std::fabs(cv.dobj));
-    cv.rel_kkt = std::max(cv.rel_p, std::max(cv.rel_d, cv.rel_gap));
-    const double r2 = c[3] / sigma + h->lambda * sigma * r[1] + 2.0 * r[2];
-    cv.merit = std::sqrt(r2 > 0 ? r2 : 0.0);
-    cv.move_x = std::sqrt(c[4]);
-    cv.move_y = std::sqrt(r[4]);
-    cv.bad = (r[5] + c[5]) > 0 || !std::isfinite(cv.rel_kkt) || !std::isfinite(cv.pobj) ||
-             !std::isfinite(cv.merit);
-    return cv;
-}
-
+// start point: projection of the scaled warm start (or of zero) onto the bounds and onto the
+// sign pattern of the rows (y_i > 0 needs a finite lower side, y_i < 0 a finite upper side)
 template <typename T>
-void upload_start(hpr_handle* h) {
-    const int32_t n = h->n, m = h->m;
-    std::vector<T> xs(n), ys(std::max(m, 1));
-    for (int32_t j = 0; j < n; ++j) {
-        double v = h->x_start.empty() ? 0.0 : h->x_start[j] / (h->beta_b * h->dc[j]);
-        v = v < h->l_s[j] ? h->l_s[j] : (v > h->u_s[j] ? h->u_s[j] : v);
-        xs[j] = T(v);
-    }
-    for (int32_t i = 0; i < m; ++i) {
-        double v = h->y_start.empty() ? 0.0 : h->y_start[i] / (h->beta_c * h->dr[i]);
-        if (!std::isfinite(h->lo_s[i]) && v > 0) v = 0.0;
-        if (!std::isfinite(h->hi_s[i]) && v < 0) v = 0.0;
-        ys[i] = T(v);
+void upload_start(Engine* e) {
+    std::vector<T> xs(e->N), ys(std::max<int64_t>(e->M, 1));
+    for (const LpHost& h : e->lps) {
+        for (int32_t j = 0; j < h.n; ++j) {
+            double v = h.x_start.empty() ? 0.0 : h.x_start[j] / (h.beta_b * h.dc[j]);
+            v = v < h.l_s[j] ? h.l_s[j] : (v > h.u_s[j] ? h.u_s[j] : v);
+            xs[h.col_off + j] = T(v);
+        }
+        for (int32_t r = 0; r < h.m; ++r) {
+            double v = h.y_start.empty() ? 0.0 : h.y_start[r] / (h.beta_c * h.dr[r]);
+            if (!std::isfinite(h.lo_s[r]) && v > 0) v = 0.0;
+            if (!std::isfinite(h.hi_s[r]) && v < 0) v = 0.0;
+            ys[h.row_off + r] = T(v);
+        }
     }
     const size_t es = sizeof(T);
-    HIP_OK(hipMemcpyAsync(h->x0.p, xs.data(), es * n, hipMemcpyHostToDevice, h->st));
-    HIP_OK(hipMemcpyAsync(h->x.p, xs.data(), es * n, hipMemcpyHostToDevice, h->st));
-    if (m > 0) {
-        HIP_OK(hipMemcpyAsync(h->y0.p, ys.data(), es * m, hipMemcpyHostToDevice, h->st));
-        HIP_OK(hipMemcpyAsync(h->y.p, ys.data(), es * m, hipMemcpyHostToDevice, h->st));
+    HIP_OK(hipMemcpyAsync(e->x0.p, xs.data(), es * e->N, hipMemcpyHostToDevice, e->st));
+    HIP_OK(hipMemcpyAsync(e->x.p, xs.data(), es * e->N, hipMemcpyHostToDevice, e->st));
+    if (e->M > 0) {
+        HIP_OK(hipMemcpyAsync(e->y0.p, ys.data(), es * e->M, hipMemcpyHostToDevice, e->st));
+        HIP_OK(hipMemcpyAsync(e->y.p, ys.data(), es * e->M, hipMemcpyHostToDevice, e->st));
     }
-    sync(h);
+    e->sync();
 }
 
-void put_ctrl(hpr_handle* h, double sigma, int64_t k_base) {
-    h->ctrl_h->sigma = sigma;
-    h->ctrl_h->s = 1.0 / (h->lambda * sigma);
-    h->ctrl_h->lambda = h->lambda;
-    h->ctrl_h->k_base = k_base;
-    HIP_OK(hipMemcpyAsync(h->ctrl.p, h->ctrl_h, sizeof(Ctrl), hipMemcpyHostToDevice, h->st));
+ControlArgs control_args(Engine* e, int phase, int nb) {
+    ControlArgs a;
+    a.ctrl = e->ctrl.as<Ctrl>();
+    a.st = e->state.as<LpState>();
+    a.sums = e->sums.as<double>();
+    a.sums64 = e->sums64.as<double>();
+    a.stat = e->stat.as<int32_t>();
+    a.nlp = e->L;
+    a.nb = nb;
+    a.fp32 = e->fp32 ? 1 : 0;
+    a.phase = phase;
+    a.max_iter = e->opts.max_iter;
+    a.tol = e->opts.tol;
+    a.restart_rule = e->opts.restart;
+    a.sigma_update = e->opts.sigma_update;
+    return a;
 }
 
-// The solve loop. Iteration `it` (0-based) is a check when it % check_every == 0 or it is
-// the last allowed one. At a check: stop if rel_kkt <= tol (in FP32 storage, confirmed by an
-// FP64 re-evaluation); otherwise restart when the merit r = ||(x - xbar, y - ybar)||_M fell
-// to 0.2 r0, or to 0.8 r0 while rising, or when the iterations since the last restart reach
-// 0.2 of all iterations; at a restart sigma <- sqrt(sigma sigma*), sigma* = ||dx|| /
-// (sqrt(lambda) ||dy||) from the anchor move (skipped below 1e-12), clamped to [1e-4, 1e4],
-// and the anchor and iterate become the bar point.
+// Check kernels in precision (Tm, Tp, Tv) and the per-LP finish into `out`.
+template <typename Tm, typename Tp, typename Tv>
+void enqueue_check(Engine* e, double* out) {
+    const DevCsr<Tm> A = e->A.view<Tm>(), At = e->At.view<Tm>();
+    const DevProb<Tp> p = e->prob<Tp>();
+    const DevIter<Tv> v = e->iter<Tv>();
+    launch_check_rows<Tm, Tp, Tv>(A, p, v, e->ctrl.as<Ctrl>(), e->part_r.as<double>(), e->st);
+    launch_check_cols<Tm, Tp, Tv>(At, p, v, e->ctrl.as<Ctrl>(), e->part_c.as<double>(), e->st);
+    launch_finish_sums(e->part_r.as<double>(), kRowQ, A.nblocks, e->A.seg.as<int32_t>(), e->L, out, 0, e->st);
+    launch_finish_sums(e->part_c.as<double>(), kColQ, At.nblocks, e->At.seg.as<int32_t>(), e->L, out, 8, e->st);
+}
+
+// One block of nb iterations, the storage-precision check, the control (phase 1) and the
+// restarts. With `sample`, HIP events bracket the first iteration's two kernels.
 template <typename T>
-void solve_loop(hpr_handle* h, hpr_info* info, double t0) {
-    const hpr_opts& o = h->opts;
-    hipStream_t st = h->st;
-    upload_start<T>(h);
-    const DevCsr<T> A = h->A.view<T>(), At = h->At.view<T>();
-    const DevProb<T> p = h->prob<T>();
-    const DevIter<T> v = h->iter<T>();
-    double sigma = o.sigma0;
-    int64_t it = 0, k = 0, restarts = 0;
-    double r0 = 0.0, r_prev = 0.0;
-    int term = HPR_ITER_LIMIT;
-    CheckVals cv{};
-    put_ctrl(h, sigma, 0);
-    h->kstats = hpr_kernel_stats{};
-    if (o.profile && !h->ev[0])
-        for (hipEvent_t& e : h->ev) HIP_OK(hipEventCreate(&e));
+void enqueue_block(Engine* e, int nb, bool sample) {
+    const DevCsr<T> A = e->A.view<T>(), At = e->At.view<T>();
+    const DevProb<T> p = e->prob<T>();
+    const DevIter<T> v = e->iter<T>();
+    for (int j = 0; j < nb; ++j) {
+        const bool chk = (j == nb - 1);
+        if (sample && j == 0) HIP_OK(hipEventRecord(e->ev[0], e->st));
+        launch_primal_step<T>(At, p, v, e->ctrl.as<Ctrl>(), j, chk, e->st);
+        if (sample && j == 0) HIP_OK(hipEventRecord(e->ev[1], e->st));
+        launch_dual_step<T>(A, p, v, e->ctrl.as<Ctrl>(), j, chk, e->st);
+        if (sample && j == 0) HIP_OK(hipEventRecord(e->ev[2], e->st));
+    }
+    enqueue_check<T, T, T>(e, e->sums.as<double>());
+    launch_control(control_args(e, 1, nb), e->st);
+    launch_restart<T>(A, At, v, e->ctrl.as<Ctrl>(), e->st);
+}
+
+template <typename T>
+hipGraphExec_t capture_block(Engine* e, int nb) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    bool ok = true;
+    try {
+        enqueue_block<T>(e, nb, false);
+    } catch (const HipError&) {
+        ok = false;
+    }
+    if (hipStreamEndCapture(e->st, &g) != hipSuccess || !ok || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+    (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return exec;
+}
+
+int32_t read_stat(Engine* e, int which) {
+    HIP_OK(hipMemcpyAsync(e->stat_h, e->stat.p, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, e->st));
+    e->sync();
+    return e->stat_h[which];
+}
+
+// The solve: blocks of iterations (the first of one iteration, then check_every, the last
+// cut at max_iter), each ending with a check of every running LP; the device takes every
+// decision (control_kernel), the host only polls how many LPs are still running, confirms
+// FP32-storage candidates in FP64 and applies the time limit.
+template <typename T>
+void solve_loop(Engine* e, double t0) {
+    const hpr_opts& o = e->opts;
+    upload_start<T>(e);
+    for (int l = 0; l < e->L; ++l) {
+        const LpHost& h = e->lps[l];
+        Ctrl& c = e->ctrl_h[l];
+        c = Ctrl{};
+        c.sigma = o.sigma0;
+        c.lambda = h.lambda;
+        c.s = 1.0 / (h.lambda * o.sigma0);
+        c.beta_b = h.beta_b;
+        c.beta_c = h.beta_c;
+        c.k_base = 0;
+        c.active = 1;
+        c.restart = 0;
+        LpState& S = e->state_h[l];
+        S = LpState{};
+        S.norm_b = h.norm_b;
+        S.norm_c = h.norm_c;
+        S.obj_offset = h.obj_offset;
+    }
+    HIP_OK(hipMemcpyAsync(e->state.p, e->state_h.data(), sizeof(LpState) * e->L, hipMemcpyHostToDevice, e->st));
+    put_ctrl(e);
+    e->kstats = hpr_kernel_stats{};
+    if (o.profile && !e->ev[0])
+        for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
+    if (o.use_graph && !e->graphs_built) {
+        e->g_first = capture_block<T>(e, 1);
+        e->g_block = capture_block<T>(e, o.check_every);
+        e->graphs_built = true;
+    }
+    int64_t it = 0, blocks = 0;
     while (true) {
-        const int64_t nb = (it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it);
-        const bool sample = o.profile && nb >= 2;
-        for (int64_t j = 0; j < nb; ++j) {
-            const bool chk = (j == nb - 1);
-            if (sample && j == 0) HIP_OK(hipEventRecord(h->ev[0], st));
-            launch_primal_step<T>(At, p, v, h->ctrl.as<Ctrl>(), (int)j, chk, st);
-            if (sample && j == 0) HIP_OK(hipEventRecord(h->ev[1], st));
-            launch_dual_step<T>(A, p, v, h->ctrl.as<Ctrl>(), (int)j, chk, st);
-            if (sample && j == 0) HIP_OK(hipEventRecord(h->ev[2], st));
-        }
+        const int nb = (int)((it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it));
+        const bool sample = o.profile && nb >= 2 && (blocks % 4 == 1);
+        hipGraphExec_t g = (nb == 1 && it == 0) ? e->g_first : (nb == o.check_every ? e->g_block : nullptr);
+        if (g && !sample) HIP_OK(hipGraphLaunch(g, e->st));
+        else enqueue_block<T>(e, nb, sample);
         HIP_OK(hipGetLastError());
         it += nb;
-        k += nb;
-        cv = run_check<T, T, T>(h, sigma);
+        blocks += 1;
+        int32_t running = read_stat(e, 0);
         if (sample) {
             float a = 0.f, b = 0.f;
-            HIP_OK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
-            HIP_OK(hipEventElapsedTime(&b, h->ev[1], h->ev[2]));
-            h->kstats.primal_ms += a;
-            h->kstats.dual_ms += b;
-            h->kstats.samples += 1;
+            HIP_OK(hipEventElapsedTime(&a, e->ev[0], e->ev[1]));
+            HIP_OK(hipEventElapsedTime(&b, e->ev[1], e->ev[2]));
+            e->kstats.primal_ms += a;
+            e->kstats.dual_ms += b;
+            e->kstats.samples += 1;
         }
-        const bool last = it >= o.max_iter;
-        const bool timed_out = o.time_limit_s > 0 && now_s() - t0 > o.time_limit_s;
-        if (cv.bad) { term = HPR_NUMERIC_FAIL; break; }
-        if (cv.rel_kkt <= o.tol) {
-            if (!h->fp32) { term = HPR_SOLVED; break; }
-            const CheckVals v64 = run_check<double, double, float>(h, sigma);
-            if (v64.rel_kkt <= o.tol) { term = HPR_SOLVED; break; }
+        if (e->fp32 && e->stat_h[1] > 0) {
+            enqueue_check<double, double, float>(e, e->sums64.as<double>());
+            launch_control(control_args(e, 2, 0), e->st);
+            launch_restart<T>(e->A.view<T>(), e->At.view<T>(), e->iter<T>(), e->ctrl.as<Ctrl>(), e->st);
+            running = read_stat(e, 0);
         }
-        if (last) { term = HPR_ITER_LIMIT; break; }
-        if (timed_out) { term = HPR_TIME_LIMIT; break; }
-        const double r = cv.merit;
-        if (it == 1) {
-            r0 = r;
-            r_prev = r;
-            put_ctrl(h, sigma, k);
-            continue;
+        if (running > 0 && o.time_limit_s > 0 && now_s() - t0 > o.time_limit_s) {
+            launch_control(control_args(e, 4, 0), e->st);
+            running = read_stat(e, 0);
         }
-        bool do_restart = false;
-        if (o.restart) {
-            if (r <= 0.2 * r0) do_restart = true;
-            else if (r <= 0.8 * r0 && r > r_prev) do_restart = true;
-            else if ((double)k >= 0.2 * (double)it) do_restart = true;
-        }
-        if (do_restart) {
-            if (o.sigma_update && cv.move_x > 1e-12 && cv.move_y > 1e-12) {
-                const double star = cv.move_x / (std::sqrt(h->lambda) * cv.move_y);
-                sigma = std::sqrt(sigma * star);
-                sigma = sigma < 1e-4 ? 1e-4 : (sigma > 1e4 ? 1e4 : sigma);
-            }
-            launch_restart<T>(v, h->n, h->m, st);
-            k = 0;
-            restarts += 1;
-            r0 = r;
-        }
-        r_prev = r;
-        put_ctrl(h, sigma, k);
+        if (running == 0 || it >= o.max_iter) break;
     }
-    if (h->fp32 && term != HPR_NUMERIC_FAIL) {
-        // report the residuals of the returned point in FP64
-        const CheckVals v64 = run_check<double, double, float>(h, sigma);
-        cv.rel_p = v64.rel_p; cv.rel_d = v64.rel_d; cv.rel_gap = v64.rel_gap; cv.rel_kkt = v64.rel_kkt;
-        cv.pobj = v64.pobj; cv.dobj = v64.dobj;
+    if (e->fp32) {
+        // report the residuals of the returned points in FP64
+        enqueue_check<double, double, float>(e, e->sums64.as<double>());
+        launch_control(control_args(e, 3, 0), e->st);
     }
-    sync(h);
-    info->term = term;
-    info->iters = it;
-    info->restarts = restarts;
-    info->pobj = cv.pobj;
-    info->dobj = cv.dobj;
-    info->rel_p = cv.rel_p;
-    info->rel_d = cv.rel_d;
-    info->rel_gap = cv.rel_gap;
-    info->rel_kkt = cv.rel_kkt;
-    info->lambda = h->lambda;
-    info->sigma = sigma;
+    HIP_OK(hipMemcpyAsync(e->state_h.data(), e->state.p, sizeof(LpState) * e->L, hipMemcpyDeviceToHost, e->st));
+    HIP_OK(hipMemcpyAsync(e->ctrl_h.data(), e->ctrl.p, sizeof(Ctrl) * e->L, hipMemcpyDeviceToHost, e->st));
+    e->sync();
 }
 
 }  // namespace
 
-extern "C" int hpr_solve(hpr_handle* h, hpr_info* info) {
-    g_err.clear();
-    if (!h || !info) return fail(HPR_ERR_INVALID, "handle or info is NULL");
-    std::memset(info, 0, sizeof(*info));
+static int engine_solve(Engine* e, hpr_info* infos) {
     const double t0 = now_s();
     try {
         int dev = 0;
         HIP_OK(hipGetDevice(&dev));
-        if (dev != h->device) HIP_OK(hipSetDevice(h->device));
-        if (h->fp32) solve_loop<float>(h, info, t0);
-        else solve_loop<double>(h, info, t0);
-        if (dev != h->device) HIP_OK(hipSetDevice(dev));
-    } catch (const HipError& e) {
-        return e.code;
+        if (dev != e->device) HIP_OK(hipSetDevice(e->device));
+        if (e->fp32) solve_loop<float>(e, t0);
+        else solve_loop<double>(e, t0);
+        if (dev != e->device) HIP_OK(hipSetDevice(dev));
+    } catch (const HipError& err) {
+        return err.code;
     } catch (const std::bad_alloc&) {
         return fail(HPR_ERR_NOMEM, "host allocation failed");
     }
-    info->setup_s = h->setup_s;
-    info->solve_s = now_s() - t0;
-    h->solved_once = true;
+    e->solve_s = now_s() - t0;
+    e->solved_once = true;
+    for (int l = 0; l < e->L; ++l) {
+        const LpState& S = e->state_h[l];
+        hpr_info& info = infos[l];
+        std::memset(&info, 0, sizeof(info));
+        info.term = S.term ? S.term : HPR_ITER_LIMIT;
+        info.iters = S.it;
+        info.restarts = S.restarts;
+        info.pobj = S.pobj;
+        info.dobj = S.dobj;
+        info.rel_p = S.rel_p;
+        info.rel_d = S.rel_d;
+        info.rel_gap = S.rel_gap;
+        info.rel_kkt = S.rel_kkt;
+        info.lambda = e->lps[l].lambda;
+        info.sigma = e->ctrl_h[l].sigma;
+        info.setup_s = e->setup_s;
+        info.solve_s = e->solve_s;
+    }
     return HPR_OK;
 }
 
-extern "C" int hpr_get_kernel_stats(hpr_handle* h, hpr_kernel_stats* out) {
-    g_err.clear();
-    if (!h || !out) return fail(HPR_ERR_INVALID, "handle or out is NULL");
-    *out = h->kstats;
-    out->unroll_a = h->A.unroll;
-    out->unroll_at = h->At.unroll;
+static int engine_get_solution(Engine* e, int i, double* x, double* y, double* z) {
+    if (i < 0 || i >= e->L) return fail(HPR_ERR_INVALID, "LP index %d out of range", i);
+    if (!e->solved_once) return fail(HPR_ERR_STATE, "no solve has run on this handle");
+    const LpHost& h = e->lps[i];
+    try {
+        if (e->fp32)
+            launch_unscale<float>(e->A.view<float>(), e->At.view<float>(), e->iter<float>(), e->dr_d.as<double>(),
+                                  e->dc_d.as<double>(), e->ctrl.as<Ctrl>(), e->ux.as<double>(), e->uy.as<double>(),
+                                  e->uz.as<double>(), e->st);
+        else
+            launch_unscale<double>(e->A.view<double>(), e->At.view<double>(), e->iter<double>(),
+                                   e->dr_d.as<double>(), e->dc_d.as<double>(), e->ctrl.as<Ctrl>(),
+                                   e->ux.as<double>(), e->uy.as<double>(), e->uz.as<double>(), e->st);
+        if (x) HIP_OK(hipMemcpyAsync(x, e->ux.as<double>() + h.col_off, sizeof(double) * h.n, hipMemcpyDeviceToHost,
+                                     e->st));
+        if (y && h.m)
+            HIP_OK(hipMemcpyAsync(y, e->uy.as<double>() + h.row_off, sizeof(double) * h.m, hipMemcpyDeviceToHost,
+                                  e->st));
+        if (z) HIP_OK(hipMemcpyAsync(z, e->uz.as<double>() + h.col_off, sizeof(double) * h.n, hipMemcpyDeviceToHost,
+                                     e->st));
+        e->sync();
+    } catch (const HipError& err) {
+        return err.code;
+    }
+    return HPR_OK;
+}
+
+static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
+    *out = e->kstats;
+    out->unroll_a = e->A.unroll;
+    out->unroll_at = e->At.unroll;
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;
     }
+}
+
+// ---------------------------------------------------------------- C interface
+
+struct hpr_handle {
+    Engine* e;
+};
+struct hpr_batch {
+    Engine* e;
+};
+
+extern "C" int hpr_create(const hpr_lp* lp, const hpr_opts* opts, hpr_handle** out) {
+    if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Engine* e = nullptr;
+    const int rc = engine_create(lp, 1, opts, &e);
+    if (rc) return rc;
+    *out = new hpr_handle{e};
     return HPR_OK;
+}
+
+extern "C" int hpr_destroy(hpr_handle* h) {
+    if (h) {
+        delete h->e;
+        delete h;
+    }
+    return HPR_OK;
+}
+
+extern "C" int hpr_set_bounds(hpr_handle* h, const double* col_lo, const double* col_hi) {
+    g_err.clear();
+    if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
+    return engine_set_bounds(h->e, 0, col_lo, col_hi);
+}
+
+extern "C" int hpr_set_start(hpr_handle* h, const double* x0, const double* y0) {
+    g_err.clear();
+    if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
+    return engine_set_start(h->e, 0, x0, y0);
+}
+
+extern "C" int hpr_solve(hpr_handle* h, hpr_info* info) {
+    g_err.clear();
+    if (!h || !info) return fail(HPR_ERR_INVALID, "handle or info is NULL");
+    return engine_solve(h->e, info);
 }
 
 extern "C" int hpr_get_solution(hpr_handle* h, double* x, double* y, double* z) {
     g_err.clear();
     if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
-    if (!h->solved_once) return fail(HPR_ERR_STATE, "no solve has run on this handle");
-    try {
-        if (h->fp32)
-            launch_unscale<float>(h->iter<float>(), h->dr_d.as<double>(), h->dc_d.as<double>(), h->n, h->m,
-                                  h->beta_b, h->beta_c, h->ux.as<double>(), h->uy.as<double>(),
-                                  h->uz.as<double>(), h->st);
-        else
-            launch_unscale<double>(h->iter<double>(), h->dr_d.as<double>(), h->dc_d.as<double>(), h->n, h->m,
-                                   h->beta_b, h->beta_c, h->ux.as<double>(), h->uy.as<double>(),
-                                   h->uz.as<double>(), h->st);
-        if (x) HIP_OK(hipMemcpyAsync(x, h->ux.p, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->st));
-        if (y && h->m) HIP_OK(hipMemcpyAsync(y, h->uy.p, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->st));
-        if (z) HIP_OK(hipMemcpyAsync(z, h->uz.p, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->st));
-        sync(h);
-    } catch (const HipError& e) {
-        return e.code;
+    return engine_get_solution(h->e, 0, x, y, z);
+}
+
+extern "C" int hpr_get_kernel_stats(hpr_handle* h, hpr_kernel_stats* out) {
+    g_err.clear();
+    if (!h || !out) return fail(HPR_ERR_INVALID, "handle or out is NULL");
+    engine_kernel_stats(h->e, out);
+    return HPR_OK;
+}
+
+extern "C" int hpr_batch_create(const hpr_lp* lps, int32_t count, const hpr_opts* opts, hpr_batch** out) {
+    if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Engine* e = nullptr;
+    const int rc = engine_create(lps, count, opts, &e);
+    if (rc) return rc;
+    *out = new hpr_batch{e};
+    return HPR_OK;
+}
+
+extern "C" int hpr_batch_destroy(hpr_batch* b) {
+    if (b) {
+        delete b->e;
+        delete b;
     }
+    return HPR_OK;
+}
+
+extern "C" int hpr_batch_size(hpr_batch* b, int32_t* count) {
+    g_err.clear();
+    if (!b || !count) return fail(HPR_ERR_INVALID, "batch or count is NULL");
+    *count = b->e->L;
+    return HPR_OK;
+}
+
+extern "C" int hpr_batch_set_bounds(hpr_batch* b, int32_t i, const double* col_lo, const double* col_hi) {
+    g_err.clear();
+    if (!b) return fail(HPR_ERR_INVALID, "batch is NULL");
+    return engine_set_bounds(b->e, i, col_lo, col_hi);
+}
+
+extern "C" int hpr_batch_set_start(hpr_batch* b, int32_t i, const double* x0, const double* y0) {
+    g_err.clear();
+    if (!b) return fail(HPR_ERR_INVALID, "batch is NULL");
+    return engine_set_start(b->e, i, x0, y0);
+}
+
+extern "C" int hpr_batch_solve(hpr_batch* b, hpr_info* infos) {
+    g_err.clear();
+    if (!b || !infos) return fail(HPR_ERR_INVALID, "batch or infos is NULL");
+    return engine_solve(b->e, infos);
+}
+
+extern "C" int hpr_batch_get_solution(hpr_batch* b, int32_t i, double* x, double* y, double* z) {
+    g_err.clear();
+    if (!b) return fail(HPR_ERR_INVALID, "batch is NULL");
+    return engine_get_solution(b->e, i, x, y, z);
+}
+
+extern "C" int hpr_batch_get_kernel_stats(hpr_batch* b, hpr_kernel_stats* out) {
+    g_err.clear();
+    if (!b || !out) return fail(HPR_ERR_INVALID, "batch or out is NULL");
+    engine_kernel_stats(b->e, out);
     return HPR_OK;
 }

@@ -40,7 +40,7 @@ class hpr_opts(C.Structure):
                 ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
-                ("unroll", C.c_int32), ("stream", C.c_void_p)]
+                ("unroll", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
@@ -58,7 +58,9 @@ class hpr_info(C.Structure):
 
 _lib = None
 EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", "hpr_solve",
-           "hpr_get_solution", "hpr_get_kernel_stats", "hpr_destroy", "hpr_last_error")
+           "hpr_get_solution", "hpr_get_kernel_stats", "hpr_destroy", "hpr_batch_create", "hpr_batch_size",
+           "hpr_batch_set_bounds", "hpr_batch_set_start", "hpr_batch_solve", "hpr_batch_get_solution",
+           "hpr_batch_get_kernel_stats", "hpr_batch_destroy", "hpr_last_error")
 
 
 def lib():
@@ -104,6 +106,7 @@ class Options:
     power_tol: float = 1e-6
     profile: int = 0
     unroll: int = 0
+    use_graph: int = 1
     stream: int = 0
 
     def to_c(self) -> hpr_opts:
@@ -233,3 +236,95 @@ def solve(lp, opts: Options | None = None, x0=None, y0=None):
     finally:
         hpr_destroy(h)
     return info, x, y, z
+
+
+# ----------------------------------------------------------------------------- batches
+
+class Batch:
+    """Owns an hpr_batch*; freed by hpr_batch_destroy (or when garbage collected)."""
+
+    def __init__(self, ptr, sizes):
+        self.ptr, self.sizes = ptr, sizes   # sizes: [(m, n)] per LP
+
+    def __len__(self):
+        return len(self.sizes)
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            try:
+                lib().hpr_batch_destroy(self.ptr)
+            except Exception:
+                pass
+            self.ptr = None
+
+
+def _info(i: hpr_info) -> Info:
+    return Info(TERM_NAMES.get(i.term, str(i.term)), i.iters, i.restarts, i.pobj, i.dobj, i.rel_p,
+                i.rel_d, i.rel_gap, i.rel_kkt, i.lambda_, i.sigma, i.setup_s, i.solve_s)
+
+
+def hpr_batch_create(lps, opts: Options | None = None) -> Batch:
+    arrs = [_LPArrays(lp) for lp in lps]
+    structs = (hpr_lp * len(arrs))(*[a.s for a in arrs])
+    o = (opts or Options()).to_c()
+    out = C.c_void_p()
+    _check(lib().hpr_batch_create(structs, len(arrs), C.byref(o), C.byref(out)))
+    return Batch(out, [(lp.m, lp.n) for lp in lps])
+
+
+def hpr_batch_destroy(b: Batch) -> None:
+    if b.ptr:
+        _check(lib().hpr_batch_destroy(b.ptr))
+        b.ptr = None
+
+
+def hpr_batch_set_bounds(b: Batch, i: int, col_lo=None, col_hi=None) -> None:
+    lo = None if col_lo is None else np.ascontiguousarray(col_lo, np.float64)
+    hi = None if col_hi is None else np.ascontiguousarray(col_hi, np.float64)
+    _check(lib().hpr_batch_set_bounds(b.ptr, C.c_int32(i),
+                                      None if lo is None else lo.ctypes.data_as(C.c_void_p),
+                                      None if hi is None else hi.ctypes.data_as(C.c_void_p)))
+
+
+def hpr_batch_set_start(b: Batch, i: int, x0=None, y0=None) -> None:
+    xa = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+    ya = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+    _check(lib().hpr_batch_set_start(b.ptr, C.c_int32(i),
+                                     None if xa is None else xa.ctypes.data_as(C.c_void_p),
+                                     None if ya is None else ya.ctypes.data_as(C.c_void_p)))
+
+
+def hpr_batch_solve(b: Batch):
+    infos = (hpr_info * len(b))()
+    _check(lib().hpr_batch_solve(b.ptr, infos))
+    return [_info(i) for i in infos]
+
+
+def hpr_batch_get_solution(b: Batch, i: int):
+    m, n = b.sizes[i]
+    x, y, z = np.zeros(n), np.zeros(max(m, 1)), np.zeros(n)
+    _check(lib().hpr_batch_get_solution(b.ptr, C.c_int32(i), x.ctypes.data_as(C.c_void_p),
+                                        y.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p)))
+    return x, y[:m], z
+
+
+def hpr_batch_get_kernel_stats(b: Batch) -> dict:
+    s = hpr_kernel_stats()
+    _check(lib().hpr_batch_get_kernel_stats(b.ptr, C.byref(s)))
+    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
+                unroll_at=s.unroll_at)
+
+
+def batch_solve(lps, opts: Options | None = None, starts=None):
+    """Create, (optionally warm-start,) solve and fetch a batch: returns [(info, x, y, z)]."""
+    b = hpr_batch_create(lps, opts)
+    try:
+        if starts is not None:
+            for i, (x0, y0) in enumerate(starts):
+                if x0 is not None or y0 is not None:
+                    hpr_batch_set_start(b, i, x0, y0)
+        infos = hpr_batch_solve(b)
+        out = [(infos[i], *hpr_batch_get_solution(b, i)) for i in range(len(b))]
+    finally:
+        hpr_batch_destroy(b)
+    return out

@@ -95,3 +95,20 @@ def test_null_handles_are_rejected():
     assert L.hpr_create(None, None, None) == hprlp.HPR_ERR_INVALID
     out = C.c_void_p()
     assert L.hpr_create(None, None, C.byref(out)) == hprlp.HPR_ERR_INVALID
+
+
+def test_batch_create_rejects_bad_member_and_counts():
+    good = _good()
+    bad = BAD["nan value"](good)
+    with pytest.raises(hprlp.HprError) as e:
+        hprlp.hpr_batch_create([good, good, bad])
+    assert e.value.code == hprlp.HPR_ERR_INVALID
+    assert "LP 2" in hprlp.hpr_last_error()
+    L = hprlp.lib()
+    out = C.c_void_p()
+    arr = (hprlp.hpr_lp * 1)(hprlp._LPArrays(good).s)
+    assert L.hpr_batch_create(arr, 0, None, C.byref(out)) == hprlp.HPR_ERR_INVALID
+    assert L.hpr_batch_create(arr, 2000, None, C.byref(out)) == hprlp.HPR_ERR_INVALID
+    assert L.hpr_batch_solve(None, None) == hprlp.HPR_ERR_INVALID
+    assert L.hpr_batch_get_solution(None, 0, None, None, None) == hprlp.HPR_ERR_INVALID
+    assert L.hpr_batch_destroy(None) == hprlp.HPR_OK

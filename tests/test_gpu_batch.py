@@ -1,0 +1,118 @@
+"""Batched solves: many uneven LPs in one pooled problem (one launch per half-iteration
+for all of them, per-LP control on the device, graph-captured iteration blocks).
+
+Each LP of a batch must follow the single-LP schedule exactly, so short runs are compared
+element by element with the CPU oracle run on that LP alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_10891_amd import hprlp, scuc
+from tests.test_gpu_parity import FP64_RTOL, assert_close, assert_parity, ragged_lp
+
+pytestmark = pytest.mark.gpu
+
+
+def uneven_batch():
+    lps = [scuc.make_instance("small", s)[1] for s in range(3)]
+    lps += [ragged_lp(s, m=150 + 60 * s, n=300 + 50 * s) for s in range(3)]
+    lps += [scuc.random_lp(np.random.default_rng(s), 5, 4) for s in range(2)]
+    return lps
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+@pytest.mark.parametrize("K", [1, 65, 300])
+def test_batch_iterates_match_oracle_per_lp(K, use_graph):
+    lps = uneven_batch()
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=0.0, max_iter=K, use_graph=use_graph))
+    for lp, (info, x, y, z) in zip(lps, out):
+        o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K))
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+def test_batch_full_solves_match_single_solves():
+    """With the same schedule (U fixed) a batch member is bitwise the single solve."""
+    lps = [scuc.make_instance("small", s)[1] for s in range(8)]
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=1e-4, max_iter=200000, unroll=4))
+    for lp, (info, x, y, z) in zip(lps, out):
+        assert info.term == "solved"
+        assert oracle.kkt(lp, x, y, z)["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+        single, xs, ys, zs = hprlp.solve(lp, hprlp.Options(tol=1e-4, max_iter=200000, unroll=4))
+        assert single.iters == info.iters and single.restarts == info.restarts
+        assert np.array_equal(xs, x) and np.array_equal(ys, y)
+
+
+def test_graph_and_direct_launches_are_bitwise_identical():
+    lps = uneven_batch()
+    a = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=1))
+    b = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=0))
+    for (ia, xa, ya, za), (ib, xb, yb, zb) in zip(a, b):
+        assert ia.iters == ib.iters and ia.term == ib.term
+        assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(za, zb)
+
+
+def test_unsolvable_member_does_not_hold_back_the_others():
+    bad = scuc.LP(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.array([1.0, 1.0]),
+                  np.array([3.0]), np.array([np.inf]), np.zeros(2), np.ones(2), np.ones(2))
+    lps = [scuc.make_instance("small", 0)[1], bad, scuc.make_instance("small", 1)[1]]
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=1e-4, max_iter=6000))
+    assert out[0][0].term == "solved" and out[2][0].term == "solved"
+    assert out[1][0].term == "iter_limit" and out[1][0].iters == 6000
+    for lp, (info, x, y, z) in zip(lps, out):
+        if info.term == "solved":
+            assert oracle.kkt(lp, x, y, z)["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_fp32_batch_reaches_tolerance_in_fp64():
+    lps = [scuc.make_instance("small", s)[1] for s in range(4, 10)]
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=200000))
+    for lp, (info, x, y, z) in zip(lps, out):
+        assert info.term == "solved"
+        ev = oracle.kkt(lp, x, y, z)
+        assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+        assert abs(ev["rel_kkt"] - info.rel_kkt) <= 1e-6 + 1e-3 * info.rel_kkt
+
+
+def test_batch_bounds_and_starts_per_lp():
+    datas = [scuc.make_instance("small", s) for s in (2, 3)]
+    lps = [lp for _, lp in datas]
+    b = hprlp.hpr_batch_create(lps, hprlp.Options(tol=0.0, max_iter=130))
+    data, lp = datas[1]
+    G = data.cfg.n_gen
+    lo, hi = lp.col_lo.copy(), lp.col_hi.copy()
+    cols = scuc.col_index(G, np.arange(6), scuc.U, 1)
+    lo[cols] = hi[cols] = 1.0
+    hprlp.hpr_batch_set_bounds(b, 1, lo, hi)
+    rng = np.random.default_rng(0)
+    x0 = rng.uniform(0, 1, lps[0].n)
+    hprlp.hpr_batch_set_start(b, 0, x0, None)
+    infos = hprlp.hpr_batch_solve(b)
+    o0 = oracle.solve(lps[0], oracle.Options(tol=0.0, max_iter=130), x0=x0)
+    assert_parity(o0, infos[0], *hprlp.hpr_batch_get_solution(b, 0), FP64_RTOL)
+    o1 = oracle.solve(lp.replace(col_lo=lo, col_hi=hi), oracle.Options(tol=0.0, max_iter=130))
+    assert_parity(o1, infos[1], *hprlp.hpr_batch_get_solution(b, 1), FP64_RTOL)
+    hprlp.hpr_batch_destroy(b)
+
+
+def _reduced(count=12, classes=3):
+    from paper_2510_10891_amd import fixing
+    return [p.lp for p in fixing.make_reduced_batch(count=count, seed0=100, classes=classes)]
+
+
+def test_reduced_batch_iterates_match_oracle_per_lp():
+    """Reduced LPs of successive-fixing rounds (uneven sizes), 65 iterations."""
+    lps = _reduced()
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=0.0, max_iter=65))
+    for lp, (info, x, y, z) in zip(lps, out):
+        o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=65))
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
+def test_reduced_batch_reaches_tolerance(precision):
+    lps = _reduced(count=16, classes=4)
+    out = hprlp.batch_solve(lps, hprlp.Options(tol=1e-4, precision=precision, max_iter=100000))
+    for lp, (info, x, y, z) in zip(lps, out):
+        assert info.term == "solved", (lp.meta["parent"], info)
+        ev = oracle.kkt(lp, x, y, z)
+        assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6)
