@@ -165,6 +165,8 @@ def main():
             f"U(A)={ks['unroll_a']} U(At)={ks['unroll_at']}")
         hprlp.hpr_destroy(h)
 
+    read_gbs, copy_gbs = hprlp.hpr_probe_stream(1 << 30, 20)
+    log(f"stream probe: read {read_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s")
     f32, f64 = res["fp32"], res["fp64"]
     pb, db = algorithmic_bytes(lp, fp32=True)
     ks = f32["ks"]
@@ -177,7 +179,9 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
-                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"]})
+                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"]},
+                stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
+                frac_of_stream_read=round(achieved / read_gbs, 4))
 
     batch = batch_leg(args.batch, stream) if args.batch > 0 else None
 

@@ -107,6 +107,10 @@ typedef struct {
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
                                    its check and its control step as one captured HIP graph;
                                    0: launch every kernel directly */
+    int32_t warm_fallback;      /* 1 (default): before a solve from a caller's start point, compare
+                                   the first check (one iteration) from that point with the one from
+                                   zero and start from zero when the given point is worse or not
+                                   finite (hpr_info.warm_start tells which start was used) */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 
@@ -119,6 +123,7 @@ typedef struct {
     double lambda, sigma;       /* step constant used and final sigma */
     double setup_s;             /* hpr_create: scaling, transfer, power method */
     double solve_s;             /* hpr_solve wall time */
+    int32_t warm_start;         /* 1: started from the point of hpr_set_start, 0: from zero */
 } hpr_info;
 
 /* Kernel timings of the last hpr_solve with hpr_opts.profile = 1: average duration of
@@ -212,6 +217,12 @@ const char *hpr_mlp_last_error(void);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *hpr_last_error(void);
+
+/* Measurement aid: streams a device buffer of `bytes` (>= 1 MiB) `reps` times with a plain
+ * read-only kernel and a plain copy kernel on the current device and reports the bandwidth
+ * of each in GB/s (copy counts bytes read plus bytes written). Allocates and frees
+ * 2 * bytes of device memory; runs on the null stream. */
+int hpr_probe_stream(int64_t bytes, int32_t reps, double *read_gbs, double *copy_gbs);
 
 #ifdef __cplusplus
 }

@@ -86,10 +86,11 @@ static double now_s(void) {
 
 /* ---------------------------------------------------------------- basic algebra */
 
-/* y = A x */
+/* y = A x (rows split over threads only for large matrices; a row is always summed by one
+   thread in index order, so the result does not depend on the split) */
 static void spmv(int32_t m, const int64_t *rp, const int32_t *ci, const double *v,
                  const double *x, double *y) {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (m > 20000)
     for (int32_t i = 0; i < m; ++i) {
         double s = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * x[ci[k]];

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhprlp.so")
-SOURCES = ["kernels.hip", "solver.hip", "mlp.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "mlp.hip", "probe.hip"]
 HEADERS = ["internal.h"]
 
 FLAGS = [

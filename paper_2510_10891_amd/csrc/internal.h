@@ -28,15 +28,22 @@ struct BlockDesc {
     int32_t count;
 };
 
+// One entry of a schedule's row list: which row, where its stored entries start and
+// how many quads (4 entries) it has, fetched by one 16-byte load.
+struct RowRef {
+    int32_t row;
+    int32_t quads;
+    int64_t start;
+};
+
 // A sparse matrix on the device: CSR whose rows start at multiples of 4 entries, so a
 // lane reads 4 values and 4 column indices with 16-byte loads. Padding entries carry
 // value 0 and a column index the row already uses. Column indices are global (pooled).
 template <typename Tm>
 struct DevCsr {
-    const int64_t* start;      // [rows + 1]
     const int32_t* col;        // [padded nnz]
     const Tm* val;             // [padded nnz]
-    const int32_t* rows;       // row list in schedule order
+    const RowRef* rows;        // row list in schedule order
     const BlockDesc* sched;    // [nblocks]
     int32_t nblocks;
     int32_t unroll;            // U: 1, 2, 4 or 8 quads per lane and pass

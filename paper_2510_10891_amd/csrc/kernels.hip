@@ -94,11 +94,13 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const bool active = grp < d.count;
-    const int row = active ? A.rows[d.first + grp] : 0;
+    const RowRef rr = active ? A.rows[d.first + grp] : RowRef{0, 0, 0};
+    const int row = rr.row;
+    if (active && lane == 0) op.pre(row);   // epilogue operands, loaded while the row streams
     Acc s0 = Acc(0), s1 = Acc(0);
     if constexpr (Op::NV > 0) {
-        const int64_t b = active ? A.start[row] : 0;
-        const int64_t e = active ? A.start[row + 1] : 0;
+        const int64_t b = rr.start;
+        const int64_t e = b + (int64_t)kVec * rr.quads;
         group_dot<G, U, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
@@ -176,6 +178,7 @@ struct PrimalOp {
     int j;
     int check;
     T sigma, a0, a1;
+    T xk, x0k, ck, lk, uk;
     double q[1];
     double* partials;
     __device__ __forceinline__ bool init(const BlockDesc& d) {
@@ -187,13 +190,19 @@ struct PrimalOp {
         a1 = T(double(k + 1) / double(k + 2));
         return true;
     }
+    __device__ __forceinline__ void pre(int col) {
+        xk = v.x[col];
+        x0k = v.x0[col];
+        ck = p.c[col];
+        lk = p.l[col];
+        uk = p.u[col];
+    }
     __device__ __forceinline__ void epi(int col, T aty, T) {
-        const T xk = v.x[col];
-        const T w = xk + sigma * (aty - p.c[col]);
-        const T xb = clampv(w, p.l[col], p.u[col]);
+        const T w = xk + sigma * (aty - ck);
+        const T xb = clampv(w, lk, uk);
         const T xh = T(2) * xb - xk;
         v.xh[col] = xh;
-        v.x[col] = a0 * v.x0[col] + a1 * xh;
+        v.x[col] = a0 * x0k + a1 * xh;
         if (check) {
             v.xb[col] = xb;
             v.zb[col] = (xb - w) / sigma;
@@ -221,6 +230,7 @@ struct DualOp {
     int j;
     int check;
     T s, a0, a1;
+    T yk, y0k, lok, hik;
     double q[1];
     double* partials;
     __device__ __forceinline__ bool init(const BlockDesc& d) {
@@ -232,14 +242,19 @@ struct DualOp {
         a1 = T(double(k + 1) / double(k + 2));
         return true;
     }
+    __device__ __forceinline__ void pre(int row) {
+        yk = v.y[row];
+        y0k = v.y0[row];
+        lok = p.lo[row];
+        hik = p.hi[row];
+    }
     __device__ __forceinline__ void epi(int row, T ax, T) {
-        const T yk = v.y[row];
         const T vv = yk - s * ax;
-        const T up = vv + s * p.lo[row];
-        const T dn = vv + s * p.hi[row];
+        const T up = vv + s * lok;
+        const T dn = vv + s * hik;
         const T yb = up > T(0) ? up : (dn < T(0) ? dn : T(0));
         const T yh = T(2) * yb - yk;
-        v.y[row] = a0 * v.y0[row] + a1 * yh;
+        v.y[row] = a0 * y0k + a1 * yh;
         if (check) {
             v.yb[row] = yb;
             v.dy[row] = yk - yb;
@@ -268,6 +283,7 @@ struct CheckRowsOp {
     double beta_b;
     double q[NQ];
     double* partials;
+    __device__ __forceinline__ void pre(int) {}
     __device__ __forceinline__ bool init(const BlockDesc& d) {
         beta_b = ctrl[d.lp].beta_b;
 #pragma unroll
@@ -312,6 +328,7 @@ struct CheckColsOp {
     double beta_c;
     double q[NQ];
     double* partials;
+    __device__ __forceinline__ void pre(int) {}
     __device__ __forceinline__ bool init(const BlockDesc& d) {
         beta_c = ctrl[d.lp].beta_c;
 #pragma unroll
@@ -350,6 +367,7 @@ struct RestartOp {
     const Ctrl* ctrl;
     double q[1];
     double* partials;
+    __device__ __forceinline__ void pre(int) {}
     __device__ __forceinline__ bool init(const BlockDesc& d) { return ctrl[d.lp].restart != 0; }
     __device__ __forceinline__ void epi(int i, T, T) {
         if constexpr (ROWS) {
@@ -379,6 +397,7 @@ struct UnscaleOp {
     double bb, bc;
     double q[1];
     double* partials;
+    __device__ __forceinline__ void pre(int) {}
     __device__ __forceinline__ bool init(const BlockDesc& d) {
         bb = ctrl[d.lp].beta_b;
         bc = ctrl[d.lp].beta_c;
@@ -406,6 +425,7 @@ struct SpmvOp {
     T* out;
     double q[1];
     double* partials;
+    __device__ __forceinline__ void pre(int) {}
     __device__ __forceinline__ bool init(const BlockDesc&) { return true; }
     __device__ __forceinline__ void epi(int row, T s, T) { out[row] = s; }
 };

@@ -325,7 +325,7 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
 // rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
 // rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int64_t>& lp_rows, int U,
-                          std::vector<int32_t>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
+                          std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
     const int L = (int)lp_rows.size() - 1;
     rows.clear();
     sched.clear();
@@ -349,7 +349,10 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 d.first = (int32_t)rows.size();
                 d.count = (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k);
                 sched.push_back(d);
-                rows.insert(rows.end(), by_bin[b].begin() + k, by_bin[b].begin() + k + d.count);
+                for (int32_t r = 0; r < d.count; ++r) {
+                    const int32_t i = by_bin[b][k + r];
+                    rows.push_back(RowRef{i, (int32_t)((start[i + 1] - start[i]) / kVec), start[i]});
+                }
             }
         }
     }
@@ -376,7 +379,8 @@ struct DevMatrix {
         set_unroll(4, st);
     }
     void set_unroll(int U, hipStream_t st) {
-        std::vector<int32_t> r, sg;
+        std::vector<RowRef> r;
+        std::vector<int32_t> sg;
         std::vector<BlockDesc> sc;
         make_schedule(start_h, lp_rows, U, r, sc, sg);
         unroll = U;
@@ -389,10 +393,9 @@ struct DevMatrix {
     template <typename T>
     DevCsr<T> view() const {
         DevCsr<T> d;
-        d.start = start.as<int64_t>();
         d.col = col.as<int32_t>();
         d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
-        d.rows = rows.as<int32_t>();
+        d.rows = rows.as<RowRef>();
         d.sched = sched.as<BlockDesc>();
         d.nblocks = nblocks;
         d.unroll = unroll;
@@ -427,6 +430,7 @@ struct Engine {
     hpr_kernel_stats kstats{};
     bool solved_once = false;
     double setup_s = 0, solve_s = 0;
+    std::vector<int32_t> warm_used, use_start_mask;   // per LP: solve started from the caller's point
 
     ~Engine() {
         if (st) (void)hipStreamSynchronize(st);
@@ -487,6 +491,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->profile = 0;
     o->unroll = 0;
     o->use_graph = 1;
+    o->warm_fallback = 1;
     o->stream = nullptr;
 }
 
@@ -757,16 +762,29 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
             a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
             a.val.assign(lp->val, lp->val + lp->nnz);
             scale_host(lp, o, a, h);
-            const HostCsr at = transpose(a);
-            const Layout la = make_layout(a), lt = make_layout(at);
-            // append to the pools with global column indices
-            const int64_t base_a = PA.start.back(), base_t = PAt.start.back();
-            for (size_t i = 1; i < la.start.size(); ++i) PA.start.push_back(base_a + la.start[i]);
-            for (int32_t c : la.col) PA.col.push_back(c + (int32_t)h.col_off);
-            PA.val.insert(PA.val.end(), la.val.begin(), la.val.end());
-            for (size_t i = 1; i < lt.start.size(); ++i) PAt.start.push_back(base_t + lt.start[i]);
-            for (int32_t c : lt.col) PAt.col.push_back(c + (int32_t)h.row_off);
-            PAt.val.insert(PAt.val.end(), lt.val.begin(), lt.val.end());
+            Layout la = make_layout(a);
+            {
+                const HostCsr at = transpose(a);
+                a = HostCsr();            // free the scaled copy before the transpose's layout
+                Layout lt = make_layout(at);
+                if (count == 1) {         // one LP: the layouts are the pools
+                    PA = std::move(la);
+                    PAt = std::move(lt);
+                } else {                  // append with global column indices
+                    const int64_t base_a = PA.start.back(), base_t = PAt.start.back();
+                    PA.start.reserve(PA.start.size() + lp->m);
+                    PAt.start.reserve(PAt.start.size() + lp->n);
+                    for (size_t i = 1; i < la.start.size(); ++i) PA.start.push_back(base_a + la.start[i]);
+                    for (size_t i = 1; i < lt.start.size(); ++i) PAt.start.push_back(base_t + lt.start[i]);
+                    const size_t ca = PA.col.size(), ct = PAt.col.size();
+                    PA.col.resize(ca + la.col.size());
+                    PAt.col.resize(ct + lt.col.size());
+                    for (size_t k = 0; k < la.col.size(); ++k) PA.col[ca + k] = la.col[k] + (int32_t)h.col_off;
+                    for (size_t k = 0; k < lt.col.size(); ++k) PAt.col[ct + k] = lt.col[k] + (int32_t)h.row_off;
+                    PA.val.insert(PA.val.end(), la.val.begin(), la.val.end());
+                    PAt.val.insert(PAt.val.end(), lt.val.begin(), lt.val.end());
+                }
+            }
             e->M += lp->m;
             e->N += lp->n;
             rows_a.push_back(e->M);
@@ -858,16 +876,18 @@ namespace {
 // start point: projection of the scaled warm start (or of zero) onto the bounds and onto the
 // sign pattern of the rows (y_i > 0 needs a finite lower side, y_i < 0 a finite upper side)
 template <typename T>
-void upload_start(Engine* e) {
+void upload_start(Engine* e, bool use_start) {
     std::vector<T> xs(e->N), ys(std::max<int64_t>(e->M, 1));
-    for (const LpHost& h : e->lps) {
+    for (int l = 0; l < e->L; ++l) {
+        const LpHost& h = e->lps[l];
+        const bool warm = use_start && (e->use_start_mask.empty() || e->use_start_mask[l]);
         for (int32_t j = 0; j < h.n; ++j) {
-            double v = h.x_start.empty() ? 0.0 : h.x_start[j] / (h.beta_b * h.dc[j]);
+            double v = (!warm || h.x_start.empty()) ? 0.0 : h.x_start[j] / (h.beta_b * h.dc[j]);
             v = v < h.l_s[j] ? h.l_s[j] : (v > h.u_s[j] ? h.u_s[j] : v);
             xs[h.col_off + j] = T(v);
         }
         for (int32_t r = 0; r < h.m; ++r) {
-            double v = h.y_start.empty() ? 0.0 : h.y_start[r] / (h.beta_c * h.dr[r]);
+            double v = (!warm || h.y_start.empty()) ? 0.0 : h.y_start[r] / (h.beta_c * h.dr[r]);
             if (!std::isfinite(h.lo_s[r]) && v > 0) v = 0.0;
             if (!std::isfinite(h.hi_s[r]) && v < 0) v = 0.0;
             ys[h.row_off + r] = T(v);
@@ -965,10 +985,8 @@ int32_t read_stat(Engine* e, int which) {
 // cut at max_iter), each ending with a check of every running LP; the device takes every
 // decision (control_kernel), the host only polls how many LPs are still running, confirms
 // FP32-storage candidates in FP64 and applies the time limit.
-template <typename T>
-void solve_loop(Engine* e, double t0) {
+void init_control(Engine* e) {
     const hpr_opts& o = e->opts;
-    upload_start<T>(e);
     for (int l = 0; l < e->L; ++l) {
         const LpHost& h = e->lps[l];
         Ctrl& c = e->ctrl_h[l];
@@ -989,14 +1007,52 @@ void solve_loop(Engine* e, double t0) {
     }
     HIP_OK(hipMemcpyAsync(e->state.p, e->state_h.data(), sizeof(LpState) * e->L, hipMemcpyHostToDevice, e->st));
     put_ctrl(e);
-    e->kstats = hpr_kernel_stats{};
-    if (o.profile && !e->ev[0])
-        for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
+}
+
+// rel_kkt of every LP at the first check (one iteration) from the uploaded start points
+template <typename T>
+std::vector<double> probe_first_check(Engine* e, bool use_start) {
+    upload_start<T>(e, use_start);
+    init_control(e);
+    if (e->g_first) HIP_OK(hipGraphLaunch(e->g_first, e->st));
+    else enqueue_block<T>(e, 1, false);
+    HIP_OK(hipMemcpyAsync(e->state_h.data(), e->state.p, sizeof(LpState) * e->L, hipMemcpyDeviceToHost, e->st));
+    e->sync();
+    std::vector<double> r(e->L);
+    for (int l = 0; l < e->L; ++l) r[l] = e->state_h[l].rel_kkt;
+    return r;
+}
+
+template <typename T>
+void solve_loop(Engine* e, double t0) {
+    const hpr_opts& o = e->opts;
     if (o.use_graph && !e->graphs_built) {
         e->g_first = capture_block<T>(e, 1);
         e->g_block = capture_block<T>(e, o.check_every);
         e->graphs_built = true;
     }
+    // Warm starts fall back to the cold start (zero) for every LP whose first check from the
+    // warm point is worse (or not finite) than from zero.
+    e->warm_used.assign(e->L, 0);
+    bool any_start = false;
+    for (const LpHost& h : e->lps) any_start = any_start || !h.x_start.empty() || !h.y_start.empty();
+    if (any_start) {
+        for (int l = 0; l < e->L; ++l)
+            e->warm_used[l] = !e->lps[l].x_start.empty() || !e->lps[l].y_start.empty();
+        e->use_start_mask.clear();
+        if (o.warm_fallback) {
+            const std::vector<double> cold = probe_first_check<T>(e, false);
+            const std::vector<double> warm = probe_first_check<T>(e, true);
+            for (int l = 0; l < e->L; ++l)
+                if (e->warm_used[l] && !(std::isfinite(warm[l]) && warm[l] <= cold[l])) e->warm_used[l] = 0;
+        }
+    }
+    e->use_start_mask = e->warm_used;
+    upload_start<T>(e, true);
+    init_control(e);
+    e->kstats = hpr_kernel_stats{};
+    if (o.profile && !e->ev[0])
+        for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
     int64_t it = 0, blocks = 0;
     while (true) {
         const int nb = (int)((it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it));
@@ -1073,6 +1129,7 @@ static int engine_solve(Engine* e, hpr_info* infos) {
         info.sigma = e->ctrl_h[l].sigma;
         info.setup_s = e->setup_s;
         info.solve_s = e->solve_s;
+        info.warm_start = e->warm_used.empty() ? 0 : e->warm_used[l];
     }
     return HPR_OK;
 }

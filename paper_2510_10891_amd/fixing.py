@@ -144,7 +144,9 @@ def reduced_lp(parent: scuc.SCUCConfig, seed: int, target: float, tau: float = 0
     fixed, ur, vr, wr = fixing_strategy(u, v, w, tau)
     lo, hi = fix_bounds(lp, G, T, fixed, ur, vr, wr)
     pre = presolve_fixed(lp.replace(col_lo=lo, col_hi=hi))
-    pre.lp.meta.update(parent=parent.name, seed=seed, fixed_u=float(fixed.sum()) / (G * T), target=target)
+    pre.lp.meta.update(parent=parent.name, seed=seed, fixed_u=float(fixed.sum()) / (G * T), target=target,
+                       data=data, fixed=fixed, u_fixed=np.where(fixed, ur, 0).astype(np.int8),
+                       cols=pre.cols, rows=pre.rows)
     return pre
 
 

@@ -40,7 +40,8 @@ class hpr_opts(C.Structure):
                 ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
-                ("unroll", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p)]
+                ("unroll", C.c_int32), ("use_graph", C.c_int32),
+                ("warm_fallback", C.c_int32), ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
@@ -53,14 +54,14 @@ class hpr_info(C.Structure):
                 ("pobj", C.c_double), ("dobj", C.c_double), ("rel_p", C.c_double),
                 ("rel_d", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double),
                 ("lambda_", C.c_double), ("sigma", C.c_double), ("setup_s", C.c_double),
-                ("solve_s", C.c_double)]
+                ("solve_s", C.c_double), ("warm_start", C.c_int32)]
 
 
 _lib = None
 EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", "hpr_solve",
            "hpr_get_solution", "hpr_get_kernel_stats", "hpr_destroy", "hpr_batch_create", "hpr_batch_size",
            "hpr_batch_set_bounds", "hpr_batch_set_start", "hpr_batch_solve", "hpr_batch_get_solution",
-           "hpr_batch_get_kernel_stats", "hpr_batch_destroy", "hpr_last_error")
+           "hpr_batch_get_kernel_stats", "hpr_batch_destroy", "hpr_probe_stream", "hpr_last_error")
 
 
 def lib():
@@ -107,6 +108,7 @@ class Options:
     profile: int = 0
     unroll: int = 0
     use_graph: int = 1
+    warm_fallback: int = 1
     stream: int = 0
 
     def to_c(self) -> hpr_opts:
@@ -138,6 +140,7 @@ class Info:
     sigma: float
     setup_s: float
     solve_s: float
+    warm_start: int = 0
 
 
 class _LPArrays:
@@ -204,9 +207,7 @@ def hpr_set_start(h: Handle, x0=None, y0=None) -> None:
 def hpr_solve(h: Handle) -> Info:
     info = hpr_info()
     _check(lib().hpr_solve(h.ptr, C.byref(info)))
-    return Info(TERM_NAMES.get(info.term, str(info.term)), info.iters, info.restarts, info.pobj,
-                info.dobj, info.rel_p, info.rel_d, info.rel_gap, info.rel_kkt, info.lambda_,
-                info.sigma, info.setup_s, info.solve_s)
+    return _info(info)
 
 
 def hpr_get_solution(h: Handle):
@@ -260,7 +261,7 @@ class Batch:
 
 def _info(i: hpr_info) -> Info:
     return Info(TERM_NAMES.get(i.term, str(i.term)), i.iters, i.restarts, i.pobj, i.dobj, i.rel_p,
-                i.rel_d, i.rel_gap, i.rel_kkt, i.lambda_, i.sigma, i.setup_s, i.solve_s)
+                i.rel_d, i.rel_gap, i.rel_kkt, i.lambda_, i.sigma, i.setup_s, i.solve_s, i.warm_start)
 
 
 def hpr_batch_create(lps, opts: Options | None = None) -> Batch:
@@ -328,3 +329,10 @@ def batch_solve(lps, opts: Options | None = None, starts=None):
     finally:
         hpr_batch_destroy(b)
     return out
+
+
+def hpr_probe_stream(nbytes: int = 1 << 30, reps: int = 20):
+    """(read GB/s, copy GB/s) of plain streaming kernels on the current device."""
+    r, c = C.c_double(), C.c_double()
+    _check(lib().hpr_probe_stream(C.c_int64(nbytes), C.c_int32(reps), C.byref(r), C.byref(c)))
+    return r.value, c.value

@@ -1,0 +1,145 @@
+"""Learned warm start for the reduced SCUC LPs of successive fixing.
+
+Two small networks (3 layers, 256 hidden units, BF16 weights with FP32 accumulation,
+trained and run by the library's own kernels) map
+  * per unit-hour features to the primal values (u, v, w, p / p_max) of that unit-hour, and
+  * per security-row features to the row's dual value.
+Their outputs become the start point (x0, y0) of the solve, i.e. the Halpern anchor of
+eq.(hpr); Theorem 1's bound grows with the distance R0 of the start from the solution, which
+is what a good start shortens. Rows other than security rows start at 0. The solver falls
+back to the cold start when the predicted point's first check is worse (hpr_opts.warm_fallback).
+
+Labels are solutions the solver itself produced on training instances (seeded, disjoint
+from the evaluation seeds).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import scuc
+from .mlp import MLP, init_params
+
+GEN_FEATURES = 14
+LINE_FEATURES = 9
+GEN_SIZES = [GEN_FEATURES, 256, 256, 4]
+LINE_SIZES = [LINE_FEATURES, 256, 256, 1]
+
+
+def _hour_feats(t, T):
+    return np.stack([np.sin(2 * np.pi * (t + 1) / 24.0), np.cos(2 * np.pi * (t + 1) / 24.0), t / max(T - 1, 1)], -1)
+
+
+def gen_features(meta) -> np.ndarray:
+    """[G*T, 14] features of every unit-hour (row g*T + t) of a reduced LP's parent."""
+    d: scuc.SCUCData = meta["data"]
+    G, T = d.cfg.n_gen, d.cfg.T
+    P = d.p_max.sum()
+    order = np.argsort(d.cost, kind="stable")
+    cum = np.zeros(G)
+    cum[order] = (np.cumsum(d.p_max[order]) - d.p_max[order]) / P     # capacity of cheaper units
+    fixed = meta.get("fixed", np.zeros((G, T), bool))
+    ufix = meta.get("u_fixed", np.zeros((G, T), np.int8))
+    t = np.arange(T)
+    unit = np.stack([d.p_max / meta["eta_p"], d.p_min / meta["eta_p"], d.cost / meta["eta_c"], cum,
+                     d.startup_cost / (d.cost * d.p_max), d.min_up / 4.0, d.min_down / 4.0], -1)   # [G, 7]
+    hour = np.concatenate([(d.demand / P)[:, None], _hour_feats(t, T)], -1)                           # [T, 4]
+    F = np.concatenate([np.repeat(unit, T, 0), np.tile(hour, (G, 1)),
+                        fixed.reshape(-1, 1).astype(float), ufix.reshape(-1, 1).astype(float),
+                        np.repeat(fixed.mean(1, keepdims=True), T, 0)], -1)
+    return F.astype(np.float32)
+
+
+def line_features(meta) -> tuple[np.ndarray, np.ndarray]:
+    """Features [R, 9] of the parent's security rows and their parent row indices [R]."""
+    d: scuc.SCUCData = meta["data"]
+    P = d.p_max.sum()
+    rows = np.nonzero(meta["row_sec"] >= 0)[0]
+    s = meta["row_sec"][rows]
+    t = meta["row_hour"][rows].astype(int)
+    T = d.cfg.T
+    coef = np.abs(d.sec_coef)
+    q = d.sec_coef @ d.p_max / P - d.sec_const
+    load = np.abs(q[s]) * d.demand[t] / d.sec_limit[s]
+    F = np.concatenate([np.stack([coef.mean(1)[s], coef.max(1)[s], d.sec_limit[s] / P, load,
+                                  (d.sec_label[s, 1] >= 0).astype(float), d.demand[t] / P], -1),
+                        _hour_feats(t, T)], -1)
+    return F.astype(np.float32), rows
+
+
+def _unit_hour_cols(meta):
+    d = meta["data"]
+    G, T = d.cfg.n_gen, d.cfg.T
+    g = np.repeat(np.arange(G), T)
+    t = np.tile(np.arange(T), G)
+    return [scuc.col_index(G, t, var, g) for var in (scuc.U, scuc.V, scuc.W, scuc.P)]
+
+
+def targets(lp, x_red, y_red):
+    """Training targets of one solved reduced LP: unit-hour (u, v, w, p/p_max) [G*T, 4] with the
+    fixed values of presolved columns, and the duals of its security rows [R] (0 where the
+    presolve dropped the row)."""
+    meta = lp.meta
+    d = meta["data"]
+    n_parent = 4 * d.cfg.n_gen * d.cfg.T
+    x = np.zeros(n_parent)
+    fixed = meta["fixed"]
+    ufix = meta["u_fixed"]
+    cols = _unit_hour_cols(meta)
+    G, T = d.cfg.n_gen, d.cfg.T
+    fx = fixed.reshape(-1)
+    x[cols[0][fx]] = ufix.reshape(-1)[fx]          # fixed u; v = w = 0 for units fixed on
+    x[meta["cols"]] = x_red
+    pmax_rep = np.repeat(d.p_max, T) / meta["eta_p"]
+    tg = np.stack([x[cols[0]], x[cols[1]], x[cols[2]], x[cols[3]] / pmax_rep], -1)
+    _, srows = line_features(meta)
+    y_parent = np.zeros(len(meta["row_sec"]))
+    y_parent[meta["rows"]] = y_red
+    # duals are learned relative to eta^P, the largest scaled production cost
+    return tg.astype(np.float32), (y_parent[srows] / meta["eta_p"]).astype(np.float32)
+
+
+def predict_start(gen_net: MLP, line_net: MLP, lp):
+    """Warm start (x0, y0) of a reduced LP from the two networks (original space of the LP)."""
+    meta = lp.meta
+    d = meta["data"]
+    G, T = d.cfg.n_gen, d.cfg.T
+    out = gen_net.forward(gen_features(meta)).astype(np.float64)
+    n_parent = 4 * G * T
+    x = np.zeros(n_parent)
+    cols = _unit_hour_cols(meta)
+    pmax_rep = np.repeat(d.p_max, T) / meta["eta_p"]
+    x[cols[0]] = out[:, 0]
+    x[cols[1]] = out[:, 1]
+    x[cols[2]] = out[:, 2]
+    x[cols[3]] = out[:, 3] * pmax_rep
+    x0 = x[meta["cols"]]
+    Fl, srows = line_features(meta)
+    y_parent = np.zeros(len(meta["row_sec"]))
+    if len(srows):
+        y_parent[srows] = line_net.forward(Fl)[:, 0] * meta["eta_p"]
+    y0 = y_parent[meta["rows"]]
+    return x0, y0
+
+
+def training_set(lps, solutions):
+    """Stacked (X_gen, T_gen, X_line, T_line) from solved reduced LPs [(x, y)]."""
+    xg, tg, xl, tl = [], [], [], []
+    for lp, (x, y) in zip(lps, solutions):
+        a, b = targets(lp, x, y)
+        xg.append(gen_features(lp.meta))
+        tg.append(a)
+        F, _ = line_features(lp.meta)
+        xl.append(F)
+        tl.append(b[:, None])
+    return np.concatenate(xg), np.concatenate(tg), np.concatenate(xl), np.concatenate(tl)
+
+
+def train(sizes, X, T, steps=1500, batch=4096, lr=1e-3, seed=0, stream=None):
+    """Adam on random mini-batches with the library's training kernels; returns (net, losses)."""
+    rng = np.random.default_rng(seed)
+    net = MLP(sizes, init_params(sizes, seed), stream=stream)
+    losses = []
+    for step in range(steps):
+        idx = rng.integers(0, len(X), min(batch, len(X)))
+        losses.append(net.train_step(X[idx], T[idx], lr))
+    return net, losses

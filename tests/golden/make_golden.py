@@ -1,37 +1,44 @@
-"""Writes the stored expected values under tests/golden/ by calling the CPU oracle only.
+"""Writes the stored expected values under tests/golden/ without the GPU path.
 
 Usage: python tests/golden/make_golden.py [medium]
-Each record names the instance (generator preset and seed), the oracle options, and
-the oracle's objective and KKT residuals at a tight tolerance.
+For the 2,000-bus instance (generator preset "medium", seed 0) the optimal objective is
+computed by scipy's HiGHS interior-point solver (with crossover), an LP solver independent
+of both the oracle and the GPU library; the record names the instance and the solver.
 """
 import json
 import os
 import sys
 import time
 
+import numpy as np
+import scipy.sparse as sp
+from scipy.optimize import linprog
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-import oracle  # noqa: E402
 from paper_2510_10891_amd import scuc  # noqa: E402
 
 
-def record(preset, seed, tol):
-    _, lp = scuc.make_instance(preset, seed)
-    t = time.time()
-    r = oracle.solve(lp, oracle.Options(tol=tol, max_iter=2_000_000))
-    ev = oracle.kkt(lp, r.x, r.y, r.z)
-    return dict(preset=preset, seed=seed, m=lp.m, n=lp.n, nnz=lp.nnz, tol=tol, term=r.term,
-                iters=r.iters, restarts=r.restarts, pobj=r.pobj, dobj=r.dobj,
-                rel_kkt=ev["rel_kkt"], seconds=round(time.time() - t, 1),
-                source="oracle.solve (CPU FP64)")
+def highs_objective(lp):
+    A = lp.to_scipy()
+    eq = lp.row_lo == lp.row_hi
+    ub = np.isfinite(lp.row_hi) & ~eq
+    lb = np.isfinite(lp.row_lo) & ~eq
+    res = linprog(lp.c, A_ub=sp.vstack([A[ub], -A[lb]]).tocsr(), b_ub=np.r_[lp.row_hi[ub], -lp.row_lo[lb]],
+                  A_eq=A[eq], b_eq=lp.row_lo[eq], bounds=np.c_[lp.col_lo, lp.col_hi], method="highs-ipm")
+    return res
 
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "medium"
-    out = os.path.join(HERE, f"oracle_{which}_seed0.json")
-    rec = record(which, 0, 1e-8)
-    with open(out, "w") as f:
+    _, lp = scuc.make_instance(which, 0)
+    t = time.time()
+    res = highs_objective(lp)
+    rec = dict(preset=which, seed=0, m=lp.m, n=lp.n, nnz=lp.nnz, status=int(res.status), message=res.message,
+               objective=float(res.fun + lp.obj_offset), seconds=round(time.time() - t, 1),
+               source="scipy.optimize.linprog(method='highs-ipm') on the generated LP")
+    with open(os.path.join(HERE, f"highs_{which}_seed0.json"), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))

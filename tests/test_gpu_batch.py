@@ -76,7 +76,7 @@ def test_fp32_batch_reaches_tolerance_in_fp64():
 def test_batch_bounds_and_starts_per_lp():
     datas = [scuc.make_instance("small", s) for s in (2, 3)]
     lps = [lp for _, lp in datas]
-    b = hprlp.hpr_batch_create(lps, hprlp.Options(tol=0.0, max_iter=130))
+    b = hprlp.hpr_batch_create(lps, hprlp.Options(tol=0.0, max_iter=130, warm_fallback=0))
     data, lp = datas[1]
     G = data.cfg.n_gen
     lo, hi = lp.col_lo.copy(), lp.col_hi.copy()
@@ -116,3 +116,16 @@ def test_reduced_batch_reaches_tolerance(precision):
         assert info.term == "solved", (lp.meta["parent"], info)
         ev = oracle.kkt(lp, x, y, z)
         assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_warm_start_fallback_rejects_a_bad_start():
+    """A start far from the solution loses at the first check: the solve runs from zero,
+    exactly as the cold solve; a start at the solution is kept."""
+    lp = scuc.make_instance("small", 7)[1]
+    cold, xc, yc, zc = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000, unroll=4))
+    bad = np.full(lp.n, 1e3)
+    ib, xb, yb, zb = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000, unroll=4), x0=bad,
+                                 y0=np.full(lp.m, -1e3))
+    assert ib.warm_start == 0 and ib.iters == cold.iters and np.array_equal(xb, xc)
+    good, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000, unroll=4), x0=xc, y0=yc)
+    assert good.warm_start == 1 and good.iters < cold.iters

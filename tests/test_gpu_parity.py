@@ -212,7 +212,8 @@ def test_warm_start_from_solution_converges_at_once():
     info2, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000), x0=x, y0=y)
     assert info2.term == "solved" and info2.iters < info.iters / 4
     o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=130), x0=x, y0=y)
-    i3, x3, y3, z3 = hprlp.solve(lp, hprlp.Options(tol=0.0, max_iter=130), x0=x, y0=y)
+    i3, x3, y3, z3 = hprlp.solve(lp, hprlp.Options(tol=0.0, max_iter=130, warm_fallback=0), x0=x, y0=y)
+    assert i3.warm_start == 1
     assert_parity(o, i3, x3, y3, z3, FP64_RTOL)
 
 
