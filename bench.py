@@ -121,6 +121,66 @@ def batch_leg(count, stream):
     return out
 
 
+def warmstart_leg(n_train, n_eval, stream):
+    """Learned warm start: train the two networks on the GPU on solver-produced solutions of
+    `n_train` training LPs, then solve the evaluation batch (the batch leg's reduced LPs)
+    cold and warm-started, FP32 storage, to 1e-4; inference time counts on the warm side."""
+    import numpy as np
+    import torch
+
+    from paper_2510_10891_amd import fixing, hprlp, warmstart
+
+    t0 = time.perf_counter()
+    lps = warmstart.training_lps(n_train, workers=min(16, os.cpu_count() or 1))
+    t_gen = time.perf_counter() - t0
+    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream)
+    t0 = time.perf_counter()
+    sols, ok = warmstart.label(lps, opts)
+    t_label = time.perf_counter() - t0
+    keep = [i for i in range(len(lps)) if ok[i]]
+    Xg, Tg, Xl, Tl = warmstart.training_set([lps[i] for i in keep], [sols[i] for i in keep])
+    t0 = time.perf_counter()
+    gen_net, lg = warmstart.train(warmstart.GEN_SIZES, Xg, Tg, steps=1500, batch=8192, lr=1e-3, stream=stream)
+    line_net, ll = warmstart.train(warmstart.LINE_SIZES, Xl, Tl, steps=1500, batch=8192, lr=1e-3, stream=stream)
+    t_train = time.perf_counter() - t0
+    log(f"warm start: {len(keep)} labelled LPs ({t_gen:.1f} s gen, {t_label:.1f} s solves), "
+        f"train {t_train:.1f} s, gen loss {np.mean(lg[:5]):.3g}->{np.mean(lg[-50:]):.3g}, "
+        f"line loss {np.mean(ll[:5]):.3g}->{np.mean(ll[-50:]):.3g}")
+    ev = [p.lp for p in fixing.make_reduced_batch(count=n_eval, seed0=100)]
+    b = hprlp.hpr_batch_create(ev, opts)
+    hprlp.hpr_batch_solve(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cold = hprlp.hpr_batch_solve(b)
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    starts = [warmstart.predict_start(gen_net, line_net, lp) for lp in ev]
+    t_inf = time.perf_counter() - t0
+    for i, (x0, y0) in enumerate(starts):
+        hprlp.hpr_batch_set_start(b, i, x0, y0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    warm = hprlp.hpr_batch_solve(b)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    hprlp.hpr_batch_destroy(b)
+    ci = np.array([i.iters for i in cold])
+    wi = np.array([i.iters for i in warm])
+    out = dict(train_lps=len(keep), eval_lps=len(ev), train_s=round(t_train, 2),
+               gen_loss=[float(np.mean(lg[:5])), float(np.mean(lg[-50:]))],
+               line_loss=[float(np.mean(ll[:5])), float(np.mean(ll[-50:]))],
+               cold_iters_total=int(ci.sum()), warm_iters_total=int(wi.sum()),
+               iters_ratio=round(float(wi.sum() / ci.sum()), 4),
+               median_lp_ratio=round(float(np.median(wi / ci)), 4),
+               warm_used=int(sum(i.warm_start for i in warm)),
+               cold_batch_s=round(t_cold, 3), warm_batch_s=round(t_warm + t_inf, 3), inference_s=round(t_inf, 3),
+               all_solved=bool(all(i.term == "solved" for i in cold + warm)),
+               worst_rel_kkt_fp64_eval=float(max(i.rel_kkt for i in warm)))
+    log(f"warm start: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +191,11 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="LPs in the batch leg (0: skip)")
+    ap.add_argument("--warmstart", type=int, default=0,
+                    help="training LPs of the learned warm-start leg (0: skip)")
+    ap.add_argument("--max-iter", type=int, default=200000,
+                    help="iteration cap (lower it only for profiler runs; the line is then not a tolerance time)")
+    ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
@@ -151,8 +216,11 @@ def main():
     log(f"instance {data.cfg.name}: m={lp.m} n={lp.n} nnz={lp.nnz} ({time.perf_counter() - t:.1f} s)")
 
     res = {}
-    for name, prec in (("fp32", hprlp.HPR_FP32), ("fp64", hprlp.HPR_FP64)):
-        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=200000, profile=1, stream=stream)
+    legs = [("fp32", hprlp.HPR_FP32), ("fp64", hprlp.HPR_FP64)]
+    if args.precision != "both":
+        legs = [l for l in legs if l[0] == args.precision]
+    for name, prec in legs:
+        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=args.max_iter, profile=1, stream=stream)
         h = hprlp.hpr_create(lp, opts)
         infos, sec = run_solves(hprlp, h, args.steps, args.warmup, torch)
         ks = hprlp.hpr_get_kernel_stats(h)
@@ -167,6 +235,9 @@ def main():
 
     read_gbs, copy_gbs = hprlp.hpr_probe_stream(1 << 30, 20)
     log(f"stream probe: read {read_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s")
+    if args.precision != "both":
+        log("single-precision leg only (profiler run): no JSON line")
+        return
     f32, f64 = res["fp32"], res["fp64"]
     pb, db = algorithmic_bytes(lp, fp32=True)
     ks = f32["ks"]
@@ -179,11 +250,13 @@ def main():
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
-                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"]},
+                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
+                          "nontemporal_A": ks["nt_a"], "nontemporal_At": ks["nt_at"]},
                 stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
                 frac_of_stream_read=round(achieved / read_gbs, 4))
 
     batch = batch_leg(args.batch, stream) if args.batch > 0 else None
+    warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
 
     cpu = None
     if not args.no_cpu:
@@ -221,6 +294,7 @@ def main():
                                              max(1e-30, np.linalg.norm(f64["x"])))},
         "roofline": roof,
         "batch": batch,
+        "warm_start": warm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

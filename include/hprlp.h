@@ -109,8 +109,12 @@ typedef struct {
                                    0: launch every kernel directly */
     int32_t warm_fallback;      /* 1 (default): before a solve from a caller's start point, compare
                                    the first check (one iteration) from that point with the one from
-                                   zero and start from zero when the given point is worse or not
-                                   finite (hpr_info.warm_start tells which start was used) */
+                                   zero and start from zero when the given point's rel_kkt is not
+                                   finite or above warm_fallback_ratio times the cold one
+                                   (hpr_info.warm_start tells which start was used) */
+    double warm_fallback_ratio; /* default 1000: a guard against broken predictions; an early check
+                                   does not predict the iteration count, so a tighter race would
+                                   reject useful starts */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 
@@ -136,6 +140,8 @@ typedef struct {
     int64_t samples;
     int32_t unroll_a;           /* schedule used for A (dual step) */
     int32_t unroll_at;          /* schedule used for A^T (primal step) */
+    int32_t nontemporal_a;      /* 1: A streamed with non-temporal loads */
+    int32_t nontemporal_at;
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

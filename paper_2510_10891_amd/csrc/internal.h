@@ -47,6 +47,7 @@ struct DevCsr {
     const BlockDesc* sched;    // [nblocks]
     int32_t nblocks;
     int32_t unroll;            // U: 1, 2, 4 or 8 quads per lane and pass
+    int32_t nontemporal;       // 1: stream the matrix with non-temporal loads
 };
 
 // Per-LP scalars read by the iteration kernels.

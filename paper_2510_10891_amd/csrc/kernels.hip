@@ -15,14 +15,27 @@ namespace hpr {
 
 // ---------------------------------------------------------------- loads
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte loads of the matrix stream; NT = non-temporal (the stream is read once per
+// iteration and is larger than the caches, so it need not displace the gathered vectors)
+template <bool NT, typename V>
+__device__ __forceinline__ V ld16(const V* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 template <typename T>
 struct Quad;
 
 template <>
 struct Quad<float> {
     float a[4];
+    template <bool NT>
     __device__ __forceinline__ static Quad load(const float* p) {
-        float4 v = *reinterpret_cast<const float4*>(p);
+        const f32x4 v = ld16<NT>(reinterpret_cast<const f32x4*>(p));
         return Quad{{v.x, v.y, v.z, v.w}};
     }
 };
@@ -30,14 +43,19 @@ struct Quad<float> {
 template <>
 struct Quad<double> {
     double a[4];
+    template <bool NT>
     __device__ __forceinline__ static Quad load(const double* p) {
-        double2 v0 = *reinterpret_cast<const double2*>(p);
-        double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+        const f64x2 v0 = ld16<NT>(reinterpret_cast<const f64x2*>(p));
+        const f64x2 v1 = ld16<NT>(reinterpret_cast<const f64x2*>(p + 2));
         return Quad{{v0.x, v0.y, v1.x, v1.y}};
     }
 };
 
-__device__ __forceinline__ int4 load_idx(const int32_t* p) { return *reinterpret_cast<const int4*>(p); }
+template <bool NT>
+__device__ __forceinline__ int4 load_idx(const int32_t* p) {
+    const i32x4 v = ld16<NT>(reinterpret_cast<const i32x4*>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
 
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
@@ -55,7 +73,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
 // group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
 // before any gather so U 16-byte loads per array are in flight per lane.
-template <int G, int U, int NV, typename Tm, typename Tx, typename Acc>
+template <int G, int U, bool NT, int NV, typename Tm, typename Tx, typename Acc>
 __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int lane,
                                           const Tx* __restrict__ g0, const Tx* __restrict__ g1,
                                           Acc& s0, Acc& s1) {
@@ -68,8 +86,8 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
         for (int u = 0; u < U; ++u) {
             const int64_t q = p + (int64_t)kVec * G * u;
             if (q < e) {
-                c[u] = load_idx(A.col + q);
-                v[u] = Quad<Tm>::load(A.val + q);
+                c[u] = load_idx<NT>(A.col + q);
+                v[u] = Quad<Tm>::template load<NT>(A.val + q);
             }
         }
 #pragma unroll
@@ -88,7 +106,7 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
 }
 
 // One block: each group of G lanes takes one row of the block's slice of the row list.
-template <int G, int U, typename Op>
+template <int G, int U, bool NT, typename Op>
 __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d) {
     using Acc = typename Op::Acc;
     const int lane = threadIdx.x & (G - 1);
@@ -101,7 +119,7 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     if constexpr (Op::NV > 0) {
         const int64_t b = rr.start;
         const int64_t e = b + (int64_t)kVec * rr.quads;
-        group_dot<G, U, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
+        group_dot<G, U, NT, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
     }
@@ -127,19 +145,19 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
 }
 
 // Ops with NQ > 0 (reductions) never skip a block: every block writes its partials.
-template <typename Op, int U>
+template <typename Op, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
     const BlockDesc d = A.sched[blockIdx.x];
     Op op = op_in;
     if (!op.init(d)) return;
     switch (d.bin) {
-        case 0: run_bin<1, U>(A, op, d); break;
-        case 1: run_bin<2, U>(A, op, d); break;
-        case 2: run_bin<4, U>(A, op, d); break;
-        case 3: run_bin<8, U>(A, op, d); break;
-        case 4: run_bin<16, U>(A, op, d); break;
-        case 5: run_bin<32, U>(A, op, d); break;
-        default: run_bin<64, U>(A, op, d); break;
+        case 0: run_bin<1, U, NT>(A, op, d); break;
+        case 1: run_bin<2, U, NT>(A, op, d); break;
+        case 2: run_bin<4, U, NT>(A, op, d); break;
+        case 3: run_bin<8, U, NT>(A, op, d); break;
+        case 4: run_bin<16, U, NT>(A, op, d); break;
+        case 5: run_bin<32, U, NT>(A, op, d); break;
+        default: run_bin<64, U, NT>(A, op, d); break;
     }
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
@@ -148,11 +166,20 @@ template <typename Op>
 static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st) {
     const int nb = A.nblocks;
     if (nb <= 0) return;
-    switch (A.unroll) {
-        case 1: hipLaunchKernelGGL((csr_kernel<Op, 1>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-        case 2: hipLaunchKernelGGL((csr_kernel<Op, 2>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-        case 8: hipLaunchKernelGGL((csr_kernel<Op, 8>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-        default: hipLaunchKernelGGL((csr_kernel<Op, 4>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+    if (A.nontemporal) {
+        switch (A.unroll) {
+            case 1: hipLaunchKernelGGL((csr_kernel<Op, 1, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 2: hipLaunchKernelGGL((csr_kernel<Op, 2, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 8: hipLaunchKernelGGL((csr_kernel<Op, 8, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            default: hipLaunchKernelGGL((csr_kernel<Op, 4, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+        }
+    } else {
+        switch (A.unroll) {
+            case 1: hipLaunchKernelGGL((csr_kernel<Op, 1, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 2: hipLaunchKernelGGL((csr_kernel<Op, 2, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 8: hipLaunchKernelGGL((csr_kernel<Op, 8, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            default: hipLaunchKernelGGL((csr_kernel<Op, 4, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+        }
     }
 }
 

@@ -204,6 +204,7 @@ static int validate_opts(const hpr_opts* o) {
     if (o->power_max_iter < 1) return fail(HPR_ERR_INVALID, "power_max_iter must be >= 1");
     if (std::isnan(o->lambda)) return fail(HPR_ERR_INVALID, "lambda is NaN");
     if ((o->scaling & HPR_SCALE_RUIZ) && o->ruiz_iters < 0) return fail(HPR_ERR_INVALID, "ruiz_iters < 0");
+    if (!(o->warm_fallback_ratio > 0)) return fail(HPR_ERR_INVALID, "warm_fallback_ratio must be > 0");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
     return HPR_OK;
@@ -362,7 +363,7 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
 struct DevMatrix {
     DBuf start, col, rows, sched, seg, val64, val32;
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
-    int32_t nrows = 0, nblocks = 0, unroll = 4;
+    int32_t nrows = 0, nblocks = 0, unroll = 4, nontemporal = 0;
     int64_t padded = 0;
     void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, bool fp32, hipStream_t st) {
         nrows = (int32_t)L.start.size() - 1;
@@ -399,6 +400,7 @@ struct DevMatrix {
         d.sched = sched.as<BlockDesc>();
         d.nblocks = nblocks;
         d.unroll = unroll;
+        d.nontemporal = nontemporal;
         return d;
     }
 };
@@ -492,6 +494,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->unroll = 0;
     o->use_graph = 1;
     o->warm_fallback = 1;
+    o->warm_fallback_ratio = 1000.0;
     o->stream = nullptr;
 }
 
@@ -562,8 +565,9 @@ static void put_ctrl(Engine* e) {
 }
 
 // Schedule tuner: for each pooled matrix, time the fused step kernel that streams it (dual
-// step for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass, and keep
-// the fastest. A forced opts.unroll skips the timing.
+// step for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass, each with
+// ordinary and with non-temporal loads of the matrix, and keep the fastest. A forced
+// opts.unroll skips the timing (ordinary loads).
 template <typename T>
 static void autotune(Engine* e) {
     hipStream_t st = e->st;
@@ -590,13 +594,16 @@ static void autotune(Engine* e) {
         DevMatrix& Mx = which == 0 ? e->A : e->At;
         if (forced) {
             Mx.set_unroll(forced, st);
+            Mx.nontemporal = 0;
             continue;
         }
         if (Mx.nrows == 0) continue;
-        int bestU = 4;
+        int bestU = 4, bestNT = 0;
         float best = 1e30f;
-        for (int U : {1, 2, 4, 8}) {
-            Mx.set_unroll(U, st);
+        for (int cand = 0; cand < 8; ++cand) {
+            const int U = 1 << (cand >> 1), NT = cand & 1;
+            if ((cand & 1) == 0) Mx.set_unroll(U, st);
+            Mx.nontemporal = NT;
             const DevCsr<T> view = Mx.view<T>();
             auto launch = [&]() {
                 if (which == 0) launch_dual_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
@@ -612,9 +619,11 @@ static void autotune(Engine* e) {
             if (ms < best) {
                 best = ms;
                 bestU = U;
+                bestNT = NT;
             }
         }
         Mx.set_unroll(bestU, st);
+        Mx.nontemporal = bestNT;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1032,7 +1041,7 @@ void solve_loop(Engine* e, double t0) {
         e->graphs_built = true;
     }
     // Warm starts fall back to the cold start (zero) for every LP whose first check from the
-    // warm point is worse (or not finite) than from zero.
+    // warm point is not finite or worse than warm_fallback_ratio times the first check from zero.
     e->warm_used.assign(e->L, 0);
     bool any_start = false;
     for (const LpHost& h : e->lps) any_start = any_start || !h.x_start.empty() || !h.y_start.empty();
@@ -1044,7 +1053,8 @@ void solve_loop(Engine* e, double t0) {
             const std::vector<double> cold = probe_first_check<T>(e, false);
             const std::vector<double> warm = probe_first_check<T>(e, true);
             for (int l = 0; l < e->L; ++l)
-                if (e->warm_used[l] && !(std::isfinite(warm[l]) && warm[l] <= cold[l])) e->warm_used[l] = 0;
+                if (e->warm_used[l] && !(std::isfinite(warm[l]) && warm[l] <= o.warm_fallback_ratio * cold[l]))
+                    e->warm_used[l] = 0;
         }
     }
     e->use_start_mask = e->warm_used;
@@ -1165,6 +1175,8 @@ static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     *out = e->kstats;
     out->unroll_a = e->A.unroll;
     out->unroll_at = e->At.unroll;
+    out->nontemporal_a = e->A.nontemporal;
+    out->nontemporal_at = e->At.nontemporal;
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;

@@ -41,12 +41,13 @@ class hpr_opts(C.Structure):
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
                 ("unroll", C.c_int32), ("use_graph", C.c_int32),
-                ("warm_fallback", C.c_int32), ("stream", C.c_void_p)]
+                ("warm_fallback", C.c_int32), ("warm_fallback_ratio", C.c_double), ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
     _fields_ = [("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
-                ("unroll_a", C.c_int32), ("unroll_at", C.c_int32)]
+                ("unroll_a", C.c_int32), ("unroll_at", C.c_int32), ("nontemporal_a", C.c_int32),
+                ("nontemporal_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -109,6 +110,7 @@ class Options:
     unroll: int = 0
     use_graph: int = 1
     warm_fallback: int = 1
+    warm_fallback_ratio: float = 1000.0
     stream: int = 0
 
     def to_c(self) -> hpr_opts:
@@ -223,7 +225,7 @@ def hpr_get_kernel_stats(h: Handle) -> dict:
     s = hpr_kernel_stats()
     _check(lib().hpr_get_kernel_stats(h.ptr, C.byref(s)))
     return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
-                unroll_at=s.unroll_at)
+                unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at)
 
 
 def solve(lp, opts: Options | None = None, x0=None, y0=None):
@@ -313,7 +315,7 @@ def hpr_batch_get_kernel_stats(b: Batch) -> dict:
     s = hpr_kernel_stats()
     _check(lib().hpr_batch_get_kernel_stats(b.ptr, C.byref(s)))
     return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
-                unroll_at=s.unroll_at)
+                unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at)
 
 
 def batch_solve(lps, opts: Options | None = None, starts=None):

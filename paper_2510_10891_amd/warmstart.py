@@ -20,7 +20,7 @@ from . import scuc
 from .mlp import MLP, init_params
 
 GEN_FEATURES = 14
-LINE_FEATURES = 9
+LINE_FEATURES = 14
 GEN_SIZES = [GEN_FEATURES, 256, 256, 4]
 LINE_SIZES = [LINE_FEATURES, 256, 256, 1]
 
@@ -49,8 +49,23 @@ def gen_features(meta) -> np.ndarray:
     return F.astype(np.float32)
 
 
-def line_features(meta) -> tuple[np.ndarray, np.ndarray]:
-    """Features [R, 9] of the parent's security rows and their parent row indices [R]."""
+def merit_order_dispatch(d: scuc.SCUCData) -> np.ndarray:
+    """[T, G] dispatch that meets each hour's demand with the cheapest units, ignoring the
+    network and inter-temporal rows (an input-side estimate, no LP solve)."""
+    order = np.argsort(d.cost, kind="stable")
+    before = np.zeros(len(d.cost))
+    before[order] = np.cumsum(d.p_max[order]) - d.p_max[order]
+    return np.clip(d.demand[:, None] - before[None, :], 0.0, d.p_max[None, :])
+
+
+def line_features(meta, dispatch) -> tuple[np.ndarray, np.ndarray]:
+    """Features [R, 14] of the parent's security rows and their parent row indices [R].
+
+    `dispatch` [T, G] (MW) is the generation the row flows are evaluated at: the solution's
+    when building training data, the unit-hour network's prediction at inference. A row whose
+    flow reaches its limit (ratio -1: lower side, +1: upper side) is the one that binds and
+    carries a dual; the ratio under the merit-order dispatch, the PTDF magnitudes, the limit,
+    the outage flag, a cost-weighted sensitivity and the hour complete the features."""
     d: scuc.SCUCData = meta["data"]
     P = d.p_max.sum()
     rows = np.nonzero(meta["row_sec"] >= 0)[0]
@@ -58,10 +73,18 @@ def line_features(meta) -> tuple[np.ndarray, np.ndarray]:
     t = meta["row_hour"][rows].astype(int)
     T = d.cfg.T
     coef = np.abs(d.sec_coef)
-    q = d.sec_coef @ d.p_max / P - d.sec_const
-    load = np.abs(q[s]) * d.demand[t] / d.sec_limit[s]
-    F = np.concatenate([np.stack([coef.mean(1)[s], coef.max(1)[s], d.sec_limit[s] / P, load,
-                                  (d.sec_label[s, 1] >= 0).astype(float), d.demand[t] / P], -1),
+
+    def ratio(p):
+        flow = d.sec_coef @ p.T - d.sec_const[:, None] * d.demand[None, :]   # [S, T]
+        return flow[s, t] / d.sec_limit[s]
+
+    r = ratio(dispatch)
+    r_ed = ratio(merit_order_dispatch(d))
+    sens = (d.sec_coef @ d.cost) / np.maximum(coef.sum(1), 1e-12) / meta["eta_c"]
+    F = np.concatenate([np.stack([coef.mean(1)[s], coef.max(1)[s], d.sec_limit[s] / P,
+                                  (d.sec_label[s, 1] >= 0).astype(float), d.demand[t] / P,
+                                  r, np.abs(r), 20.0 * np.maximum(np.abs(r) - 0.95, 0.0), r_ed, sens[s],
+                                  np.sign(r) * np.maximum(np.abs(r) - 0.95, 0.0) * 20.0], -1),
                         _hour_feats(t, T)], -1)
     return F.astype(np.float32), rows
 
@@ -76,8 +99,8 @@ def _unit_hour_cols(meta):
 
 def targets(lp, x_red, y_red):
     """Training targets of one solved reduced LP: unit-hour (u, v, w, p/p_max) [G*T, 4] with the
-    fixed values of presolved columns, and the duals of its security rows [R] (0 where the
-    presolve dropped the row)."""
+    fixed values of presolved columns, and the duals of its security rows [R] divided by eta^P
+    (0 where the presolve dropped the row)."""
     meta = lp.meta
     d = meta["data"]
     n_parent = 4 * d.cfg.n_gen * d.cfg.T
@@ -91,7 +114,7 @@ def targets(lp, x_red, y_red):
     x[meta["cols"]] = x_red
     pmax_rep = np.repeat(d.p_max, T) / meta["eta_p"]
     tg = np.stack([x[cols[0]], x[cols[1]], x[cols[2]], x[cols[3]] / pmax_rep], -1)
-    _, srows = line_features(meta)
+    srows = np.nonzero(meta["row_sec"] >= 0)[0]
     y_parent = np.zeros(len(meta["row_sec"]))
     y_parent[meta["rows"]] = y_red
     # duals are learned relative to eta^P, the largest scaled production cost
@@ -113,7 +136,8 @@ def predict_start(gen_net: MLP, line_net: MLP, lp):
     x[cols[2]] = out[:, 2]
     x[cols[3]] = out[:, 3] * pmax_rep
     x0 = x[meta["cols"]]
-    Fl, srows = line_features(meta)
+    dispatch = (np.clip(out[:, 3], 0.0, 1.0) * np.repeat(d.p_max, T)).reshape(G, T).T
+    Fl, srows = line_features(meta, dispatch)
     y_parent = np.zeros(len(meta["row_sec"]))
     if len(srows):
         y_parent[srows] = line_net.forward(Fl)[:, 0] * meta["eta_p"]
@@ -128,7 +152,9 @@ def training_set(lps, solutions):
         a, b = targets(lp, x, y)
         xg.append(gen_features(lp.meta))
         tg.append(a)
-        F, _ = line_features(lp.meta)
+        d = lp.meta["data"]
+        dispatch = (a[:, 3] * np.repeat(d.p_max, d.cfg.T)).reshape(d.cfg.n_gen, d.cfg.T).T
+        F, _ = line_features(lp.meta, dispatch)
         xl.append(F)
         tl.append(b[:, None])
     return np.concatenate(xg), np.concatenate(tg), np.concatenate(xl), np.concatenate(tl)
@@ -143,3 +169,31 @@ def train(sizes, X, T, steps=1500, batch=4096, lr=1e-3, seed=0, stream=None):
         idx = rng.integers(0, len(X), min(batch, len(X)))
         losses.append(net.train_step(X[idx], T[idx], lr))
     return net, losses
+
+
+def _train_lp(i):
+    from . import fixing
+    return fixing.reduced_lp(fixing.BATCH_PARENTS[i % 2], 10000 + i, 0.2 + 0.7 * ((i * 37) % 64) / 63).lp
+
+
+def training_lps(count: int, workers: int = 1):
+    """Training instances: reduced LPs of the two smallest parent classes with seeds
+    10000 + i (disjoint from the evaluation seeds 100-163), fixing targets spread over
+    20-90% of u."""
+    if workers <= 1:
+        return [_train_lp(i) for i in range(count)]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_train_lp, range(count), chunksize=16)
+
+
+def label(lps, opts, chunk: int = 500):
+    """(x*, y*) of every training LP from batched solves; LPs that do not reach the
+    tolerance are left out (returned mask)."""
+    from . import hprlp
+    sols, ok = [], []
+    for k in range(0, len(lps), chunk):
+        for info, x, y, z in hprlp.batch_solve(lps[k:k + chunk], opts):
+            sols.append((x, y))
+            ok.append(info.term == "solved")
+    return sols, np.array(ok)
