@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=640)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="LPs in the batch leg (0: skip)")
+    ap.add_argument("--successive", type=int, default=0,
+                    help="rounds of the successive-fixing leg on the bench instance (0: skip)")
     ap.add_argument("--warmstart", type=int, default=0,
                     help="training LPs of the learned warm-start leg (0: skip)")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -257,6 +259,14 @@ def main():
 
     batch = batch_leg(args.batch, stream) if args.batch > 0 else None
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
+    sf = None
+    if args.successive > 0:
+        from paper_2510_10891_amd import successive
+        r = successive.run(data, lp, rounds=args.successive, tau=0.1,
+                           opts=hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=200000, stream=stream))
+        sf = [dict(round=x.index, term=x.term, iters=x.iters, solve_s=round(x.solve_s, 3),
+                   objective=x.objective, fixed_u=round(x.fixed_u, 4), newly_fixed=x.newly_fixed) for x in r.rounds]
+        log(f"successive fixing: {sf}")
 
     cpu = None
     if not args.no_cpu:
@@ -295,6 +305,7 @@ def main():
         "roofline": roof,
         "batch": batch,
         "warm_start": warm,
+        "successive_fixing": sf,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

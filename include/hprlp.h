@@ -97,6 +97,8 @@ typedef struct {
     uint64_t seed;              /* power-method start vector (SplitMix64 stream, default 0) */
     int32_t restart;            /* restart rule on (default 1) */
     int32_t sigma_update;       /* sigma adaptation at restarts on (default 1) */
+    double sigma_smoothing;     /* weight w in (0, 1] of the target in the log-space update
+                                   log sigma <- (1 - w) log sigma + w log sigma* (default 0.5) */
     int32_t power_max_iter;     /* default 200 */
     double power_tol;           /* relative change that stops the power method (default 1e-6) */
     int32_t profile;            /* 1: time one primal and one dual kernel per block of

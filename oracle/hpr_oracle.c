@@ -66,6 +66,7 @@ typedef struct {
     int32_t power_max_iter;
     double power_tol;
     double time_limit;       /* seconds, <= 0: none */
+    double sigma_smoothing;  /* weight w of sigma* in log sigma <- (1 - w) log sigma + w log sigma* */
     const double *x0;        /* warm start (original space) or NULL */
     const double *y0;
 } orc_opts;
@@ -497,7 +498,8 @@ static void unscale(const scaled_lp *s, const double *xb, const double *yb, cons
  *   - first check: r0 = r_prev = r, no restart;
  *   - restart when r <= 0.2 r0, or (r <= 0.8 r0 and r > r_prev), or when the
  *     iterations since the last restart are >= 0.2 of all iterations so far;
- *   - on restart: sigma <- sqrt(sigma * sigma*) with sigma* = ||dx|| / (sqrt(lambda) ||dy||),
+ *   - on restart: log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing, 1/2 by
+ *     default, i.e. sigma <- sqrt(sigma * sigma*)) with sigma* = ||dx|| / (sqrt(lambda) ||dy||),
  *     (dx, dy) = (xbar - x0, ybar - y0) the move of the anchor, skipped when either norm is
  *     below 1e-12, clamped to [1e-4, 1e4]; then anchor = current = (xbar, ybar), k = 0,
  *     r0 = r.
@@ -589,7 +591,9 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
                 ddy = sqrt(ddy);
                 if (ddx > 1e-12 && ddy > 1e-12) {
                     double star = ddx / (sqrt(lambda) * ddy);
-                    sigma = clampd(sqrt(sigma * star), 1e-4, 1e4);
+                    double w = o->sigma_smoothing;
+                    double next = (w == 0.5) ? sqrt(sigma * star) : exp((1.0 - w) * log(sigma) + w * log(star));
+                    sigma = clampd(next, 1e-4, 1e4);
                 }
             }
             memcpy(x0, xb, sizeof(double) * n);

@@ -28,20 +28,26 @@ struct BlockDesc {
     int32_t count;
 };
 
-// One entry of a schedule's row list: which row, where its stored entries start and
-// how many quads (4 entries) it has, fetched by one 16-byte load.
+// One entry of a schedule's row list, fetched by one 16-byte load: the row, its number of
+// quads (4 stored entries; the top bit marks a "wide" row), the smallest column of the row
+// and the position of its first entry divided by 4.
 struct RowRef {
     int32_t row;
-    int32_t quads;
-    int64_t start;
+    int32_t quads;      // bit 31: wide row (column span >= 65536, read from the 32-bit indices)
+    int32_t base;       // smallest column of the row
+    int32_t start4;     // first stored entry / 4
 };
+constexpr int32_t kWide = int32_t(0x80000000u);
 
-// A sparse matrix on the device: CSR whose rows start at multiples of 4 entries, so a
-// lane reads 4 values and 4 column indices with 16-byte loads. Padding entries carry
-// value 0 and a column index the row already uses. Column indices are global (pooled).
+// A sparse matrix on the device: CSR whose rows start at multiples of 4 entries. Padding
+// entries carry value 0 and a column index the row already uses. Column indices are global
+// (pooled). A row whose columns span less than 65536 is read through 16-bit offsets from its
+// smallest column (a quad = 16 bytes of FP32 values + 8 bytes of offsets); wider rows through
+// the 32-bit indices.
 template <typename Tm>
 struct DevCsr {
-    const int32_t* col;        // [padded nnz]
+    const int32_t* col;        // [padded nnz] 32-bit column indices
+    const uint16_t* col16;     // [padded nnz] column - row base (narrow rows)
     const Tm* val;             // [padded nnz]
     const RowRef* rows;        // row list in schedule order
     const BlockDesc* sched;    // [nblocks]
@@ -125,6 +131,7 @@ struct ControlArgs {
     double tol;
     int restart_rule;
     int sigma_update;
+    double sigma_smoothing;  // weight of sigma* in the log-space update
 };
 void launch_control(const ControlArgs& a, hipStream_t st);
 // y = A x (plain product, used by the power method).

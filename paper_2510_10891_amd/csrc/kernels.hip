@@ -57,6 +57,18 @@ __device__ __forceinline__ int4 load_idx(const int32_t* p) {
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// 4 column offsets of 16 bits (one 8-byte load) plus the row's base column
+template <bool NT>
+__device__ __forceinline__ int4 load_idx16(const uint16_t* p, int base) {
+    u32x2 v;
+    if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    else v = *reinterpret_cast<const u32x2*>(p);
+    return make_int4(base + (int)(v.x & 0xFFFFu), base + (int)(v.x >> 16), base + (int)(v.y & 0xFFFFu),
+                     base + (int)(v.y >> 16));
+}
+
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
@@ -73,8 +85,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
 // group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
 // before any gather so U 16-byte loads per array are in flight per lane.
-template <int G, int U, bool NT, int NV, typename Tm, typename Tx, typename Acc>
-__device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int lane,
+template <int G, int U, bool NT, bool WIDE, int NV, typename Tm, typename Tx, typename Acc>
+__device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int base, int lane,
                                           const Tx* __restrict__ g0, const Tx* __restrict__ g1,
                                           Acc& s0, Acc& s1) {
     s0 = Acc(0);
@@ -86,7 +98,8 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
         for (int u = 0; u < U; ++u) {
             const int64_t q = p + (int64_t)kVec * G * u;
             if (q < e) {
-                c[u] = load_idx<NT>(A.col + q);
+                if constexpr (WIDE) c[u] = load_idx<NT>(A.col + q);
+                else c[u] = load_idx16<NT>(A.col16 + q, base);
                 v[u] = Quad<Tm>::template load<NT>(A.val + q);
             }
         }
@@ -112,14 +125,15 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const bool active = grp < d.count;
-    const RowRef rr = active ? A.rows[d.first + grp] : RowRef{0, 0, 0};
+    const RowRef rr = active ? A.rows[d.first + grp] : RowRef{0, 0, 0, 0};
     const int row = rr.row;
     if (active && lane == 0) op.pre(row);   // epilogue operands, loaded while the row streams
     Acc s0 = Acc(0), s1 = Acc(0);
     if constexpr (Op::NV > 0) {
-        const int64_t b = rr.start;
-        const int64_t e = b + (int64_t)kVec * rr.quads;
-        group_dot<G, U, NT, Op::NV>(A, b, e, lane, op.g0, op.g1, s0, s1);
+        const int64_t b = (int64_t)kVec * rr.start4;
+        const int64_t e = b + (int64_t)kVec * (rr.quads & ~kWide);
+        if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
+        else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
     }
@@ -518,7 +532,8 @@ __device__ void store_values(LpState& S, const CheckValues& v) {
 // After a check that did not terminate: iteration limit, then the restart rule:
 // restart when r <= 0.2 r0, or r <= 0.8 r0 while rising (r > r_prev), or when the
 // iterations since the last restart are >= 0.2 of all iterations. At a restart
-// sigma <- sqrt(sigma sigma*), sigma* = ||dx|| / (sqrt(lambda) ||dy||) from the anchor
+// log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing; w = 1/2 is
+// sigma <- sqrt(sigma sigma*)), sigma* = ||dx|| / (sqrt(lambda) ||dy||) from the anchor
 // move (skipped below 1e-12), clamped to [1e-4, 1e4]; anchor = iterate = bar point, k = 0.
 __device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, double move_x, double move_y) {
 #pragma clang fp contract(off)
@@ -543,7 +558,8 @@ __device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, doub
         double sigma = c.sigma;
         if (a.sigma_update && move_x > 1e-12 && move_y > 1e-12) {
             const double star = move_x / (sqrt(c.lambda) * move_y);
-            sigma = sqrt(sigma * star);
+            const double w = a.sigma_smoothing;
+            sigma = (w == 0.5) ? sqrt(sigma * star) : exp((1.0 - w) * log(sigma) + w * log(star));
             sigma = sigma < 1e-4 ? 1e-4 : (sigma > 1e4 ? 1e4 : sigma);
         }
         c.sigma = sigma;

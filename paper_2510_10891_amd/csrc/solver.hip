@@ -84,6 +84,8 @@ struct DBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+static void sync_stream(hipStream_t st) { HIP_OK(hipStreamSynchronize(st)); }
+
 template <typename T>
 static void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
     d.alloc(h.size() * sizeof(T));
@@ -126,6 +128,31 @@ struct Layout {
     std::vector<int32_t> col;
     std::vector<double> val;
 };
+
+// 16-bit offsets of every entry from its row's smallest column (rows spanning 65536 columns
+// or more are "wide": their offsets are unused and the 32-bit indices are read instead)
+static void short_indices(const Layout& L, std::vector<uint16_t>& col16, std::vector<int32_t>& base,
+                          std::vector<uint8_t>& wide) {
+    const int64_t R = (int64_t)L.start.size() - 1;
+    col16.assign(L.col.size(), 0);
+    base.assign(R, 0);
+    wide.assign(R, 0);
+    for (int64_t i = 0; i < R; ++i) {
+        const int64_t b = L.start[i], e = L.start[i + 1];
+        if (b == e) continue;
+        int32_t lo = L.col[b], hi = L.col[b];
+        for (int64_t k = b; k < e; ++k) {
+            lo = std::min(lo, L.col[k]);
+            hi = std::max(hi, L.col[k]);
+        }
+        base[i] = lo;
+        if ((int64_t)hi - lo >= 65536) {
+            wide[i] = 1;
+            continue;
+        }
+        for (int64_t k = b; k < e; ++k) col16[k] = (uint16_t)(L.col[k] - lo);
+    }
+}
 
 static Layout make_layout(const HostCsr& a) {
     Layout L;
@@ -205,6 +232,8 @@ static int validate_opts(const hpr_opts* o) {
     if (std::isnan(o->lambda)) return fail(HPR_ERR_INVALID, "lambda is NaN");
     if ((o->scaling & HPR_SCALE_RUIZ) && o->ruiz_iters < 0) return fail(HPR_ERR_INVALID, "ruiz_iters < 0");
     if (!(o->warm_fallback_ratio > 0)) return fail(HPR_ERR_INVALID, "warm_fallback_ratio must be > 0");
+    if (!(o->sigma_smoothing > 0 && o->sigma_smoothing <= 1))
+        return fail(HPR_ERR_INVALID, "sigma_smoothing must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
     return HPR_OK;
@@ -325,7 +354,8 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
 // The work list of one pooled matrix for U quads per lane and pass: per LP, per bin (bin b:
 // rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
 // rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
-static void make_schedule(const std::vector<int64_t>& start, const std::vector<int64_t>& lp_rows, int U,
+static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
+                          const std::vector<uint8_t>& wide, const std::vector<int64_t>& lp_rows, int U,
                           std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
     const int L = (int)lp_rows.size() - 1;
     rows.clear();
@@ -352,7 +382,8 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 sched.push_back(d);
                 for (int32_t r = 0; r < d.count; ++r) {
                     const int32_t i = by_bin[b][k + r];
-                    rows.push_back(RowRef{i, (int32_t)((start[i + 1] - start[i]) / kVec), start[i]});
+                    const int32_t quads = (int32_t)((start[i + 1] - start[i]) / kVec);
+                    rows.push_back(RowRef{i, quads | (wide[i] ? kWide : 0), base[i], (int32_t)(start[i] / kVec)});
                 }
             }
         }
@@ -361,8 +392,10 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
 }
 
 struct DevMatrix {
-    DBuf start, col, rows, sched, seg, val64, val32;
+    DBuf start, col, col16, rows, sched, seg, val64, val32;
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
+    std::vector<int32_t> base_h;
+    std::vector<uint8_t> wide_h;
     int32_t nrows = 0, nblocks = 0, unroll = 4, nontemporal = 0;
     int64_t padded = 0;
     void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, bool fp32, hipStream_t st) {
@@ -370,8 +403,16 @@ struct DevMatrix {
         padded = (int64_t)L.col.size();
         start_h = L.start;
         lp_rows = lp_rows_in;
+        if (padded / kVec >= INT32_MAX) {
+            fail(HPR_ERR_INVALID, "matrix too large: more than 2^33 stored entries");
+            throw HipError{HPR_ERR_INVALID};
+        }
+        std::vector<uint16_t> c16;
+        short_indices(L, c16, base_h, wide_h);
         upload(start, L.start, st);
         upload(col, L.col, st);
+        upload(col16, c16, st);
+        sync_stream(st);   // c16 is local
         upload(val64, L.val, st);
         if (fp32) {
             val32.alloc(L.val.size() * sizeof(float));
@@ -383,7 +424,7 @@ struct DevMatrix {
         std::vector<RowRef> r;
         std::vector<int32_t> sg;
         std::vector<BlockDesc> sc;
-        make_schedule(start_h, lp_rows, U, r, sc, sg);
+        make_schedule(start_h, base_h, wide_h, lp_rows, U, r, sc, sg);
         unroll = U;
         nblocks = (int32_t)sc.size();
         upload(rows, r, st);
@@ -395,6 +436,7 @@ struct DevMatrix {
     DevCsr<T> view() const {
         DevCsr<T> d;
         d.col = col.as<int32_t>();
+        d.col16 = col16.as<uint16_t>();
         d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
         d.rows = rows.as<RowRef>();
         d.sched = sched.as<BlockDesc>();
@@ -495,6 +537,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->use_graph = 1;
     o->warm_fallback = 1;
     o->warm_fallback_ratio = 1000.0;
+    o->sigma_smoothing = 0.5;
     o->stream = nullptr;
 }
 
@@ -927,6 +970,7 @@ ControlArgs control_args(Engine* e, int phase, int nb) {
     a.tol = e->opts.tol;
     a.restart_rule = e->opts.restart;
     a.sigma_update = e->opts.sigma_update;
+    a.sigma_smoothing = e->opts.sigma_smoothing;
     return a;
 }
 

@@ -43,9 +43,11 @@ def test_batch_full_solves_match_single_solves():
 
 
 def test_graph_and_direct_launches_are_bitwise_identical():
+    """Same schedule (U fixed: the tuner's timed choice may differ between two engines and U
+    sets the summation order), graph replay vs direct launches: identical bits."""
     lps = uneven_batch()
-    a = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=1))
-    b = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=0))
+    a = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=1, unroll=4))
+    b = hprlp.batch_solve(lps, hprlp.Options(tol=1e-6, max_iter=20000, use_graph=0, unroll=4))
     for (ia, xa, ya, za), (ib, xb, yb, zb) in zip(a, b):
         assert ia.iters == ib.iters and ia.term == ib.term
         assert np.array_equal(xa, xb) and np.array_equal(ya, yb) and np.array_equal(za, zb)

@@ -86,7 +86,46 @@ def assert_parity(o, info, x, y, z, rtol):
     assert abs(info.pobj - o.pobj) <= rtol * (1 + abs(o.pobj))
 
 
+def wide_lp(seed, m=300, n=70000):
+    """Rows whose columns span more than 65536 (read through 32-bit indices) mixed with
+    narrow rows (16-bit offsets from the row's smallest column)."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(m):
+        L = int(rng.choice([2, 5, 20, 90, 400]))
+        if i % 3 == 0:      # wide: both ends of the column range
+            cs = np.unique(np.r_[rng.integers(0, 200, L // 2 + 1), rng.integers(n - 2000, n, L - L // 2)])
+        else:               # narrow: a window of 30000 columns
+            a = int(rng.integers(0, n - 30000))
+            cs = np.unique(rng.integers(a, a + 30000, L))
+        rows += [i] * len(cs)
+        cols += cs.tolist()
+        vals += rng.standard_normal(len(cs)).tolist()
+    import scipy.sparse as sp
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    l, u = -np.ones(n), np.ones(n)
+    xf = rng.uniform(-0.5, 0.5, n)
+    ax = A @ xf
+    lo, hi = ax - rng.uniform(0.1, 1, m), ax + rng.uniform(0.1, 1, m)
+    return scuc.LP(m, n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.copy(), lo, hi, l, u,
+                   rng.standard_normal(n), 0.0)
+
+
 # ----------------------------------------------------------------------------- short-run parity
+
+@pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
+def test_wide_and_narrow_rows_match_oracle(precision):
+    lp = wide_lp(0)
+    K = 130 if precision == hprlp.HPR_FP64 else 2
+    o, info, x, y, z = run_both(lp, K, precision=precision)
+    if precision == hprlp.HPR_FP64:
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+    else:
+        assert info.iters == o.iters
+        assert_close(x, o.x, FP32_RTOL * 20, "x")
+        assert_close(y, o.y, FP32_RTOL * 20, "y")
+
 
 @pytest.mark.parametrize("K", [1, 2, 64, 65, 66, 200, 513])
 @pytest.mark.parametrize("seed", [0, 1])
@@ -120,7 +159,8 @@ def test_fp64_iterates_match_oracle_small_scuc(seed, K):
 
 
 @pytest.mark.parametrize("variant", [dict(use_pc=False, use_bc=False), dict(ruiz_iters=10),
-                                     dict(restart=False, sigma_update=False), dict(lambda_in=0.9)])
+                                     dict(restart=False, sigma_update=False), dict(lambda_in=0.9),
+                                     dict(sigma_smoothing=1.0), dict(sigma_smoothing=0.25)])
 def test_fp64_options_match_oracle(variant):
     _, lp = scuc.make_instance("small", 3)
     o, info, x, y, z = run_both(lp, 300, **variant)
@@ -184,6 +224,22 @@ def test_medium_full_size_parity_and_tolerance():
         assert info.term == "solved", info
         ev = oracle.kkt(lp, x, y, z)
         assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), ev
+
+
+def test_medium_objective_matches_interior_point_golden():
+    """The 2,000-bus instance solved to 1e-6 in FP64 reaches the optimal objective that an
+    independent interior-point solver (HiGHS, stored under tests/golden/) found for it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "highs_medium_seed0.json")) as f:
+        gold = json.load(f)
+    _, lp = scuc.make_instance(gold["preset"], gold["seed"])
+    assert (lp.m, lp.n, lp.nnz) == (gold["m"], gold["n"], gold["nnz"])
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=400000))
+    assert info.term == "solved", info
+    ev = oracle.kkt(lp, x, y, z)
+    assert ev["rel_kkt"] <= 1e-6 * (1 + 1e-6), ev
+    assert rel(ev["pobj"], gold["objective"]) < 2e-5, (ev["pobj"], gold["objective"])
 
 
 # ----------------------------------------------------------------------------- handle semantics
