@@ -24,6 +24,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` measured by rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the ratio a plain copy kernel of known size gives)
+    as recorded under profiles/, or None when no record exists or the kernel source has changed
+    since (the record holds the SHA-256 of the kernel source file it was taken with)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    src = os.path.join(ROOT, "paper_2510_10891_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    m_sha = re.search(r"kernels_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != sha:
+        return None
+    return float(m_val.group(1))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -58,57 +78,81 @@ def run_solves(hprlp, h, steps, warmup, torch):
     return infos, (t1 - t0) / steps
 
 
-def cpu_baseline(lp, gpu_fp64_iters, sample_iters):
-    """The oracle (plain C, FP64, OpenMP row loops) on a bounded sample: `sample_iters`
-    iterations of the same instance; time to 1e-4 is extrapolated to the iteration count
-    the FP64 solve needs (the oracle takes the same iterations: same algorithm)."""
+def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
+    """The oracle (plain C, FP64, OpenMP row loops) on the same instance: a full solve to 1e-4
+    bounded by `limit_s` seconds of wall time. If it reaches the tolerance, its own time is the
+    value and the GPU objectives are compared with its objective (the error against the FP64
+    oracle); if it stops at the limit, the time to 1e-4 is extrapolated from its measured rate
+    to the iteration count of the FP64 GPU solve (same algorithm, same iterations)."""
     import oracle
     oracle.build()
-    r = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=sample_iters))
-    its_per_s = r.iters / r.solve_s
-    est = r.setup_s + gpu_fp64_iters / its_per_s
-    return dict(value=round(est, 3), unit="s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{r.iters} oracle iterations of the same instance ({r.solve_s:.1f} s, "
-                       f"{its_per_s:.2f} it/s) plus its setup ({r.setup_s:.1f} s); time to 1e-4 "
-                       f"extrapolated to the {gpu_fp64_iters} iterations the FP64 solve takes",
-                iters_per_s=round(its_per_s, 3))
+    r = oracle.solve(lp, oracle.Options(tol=1e-4, max_iter=1000000, time_limit=limit_s))
+    its_per_s = r.iters / max(r.solve_s, 1e-9)
+    out = dict(unit="s", cores=oracle.num_threads(), kind="oracle", iters=r.iters,
+               iters_per_s=round(its_per_s, 3), setup_s=round(r.setup_s, 3))
+    if r.term == "solved":
+        out["value"] = round(r.setup_s + r.solve_s, 3)
+        out["sample"] = (f"full oracle solve of the same instance to 1e-4: {r.iters} iterations, "
+                         f"{r.solve_s:.1f} s + setup {r.setup_s:.1f} s")
+        out["oracle_pobj"] = r.pobj
+        out["gpu_obj_rel_err_vs_oracle"] = {k: abs(v - r.pobj) / max(1.0, abs(r.pobj)) for k, v in gpu_objs.items()}
+    else:
+        out["value"] = round(r.setup_s + gpu_fp64_iters / its_per_s, 3)
+        out["sample"] = (f"{r.iters} oracle iterations of the same instance in {r.solve_s:.1f} s (stopped at "
+                         f"the {limit_s:.0f} s bound) plus setup {r.setup_s:.1f} s; time to 1e-4 extrapolated "
+                         f"to the {gpu_fp64_iters} iterations the FP64 GPU solve takes")
+    return out
 
 
-def batch_leg(count, stream):
+def batch_leg(count, stream, parent="mixed"):
     """The reduced LPs of successive-fixing rounds (uneven sizes) solved as one batch with FP32
-    storage, against the same LPs solved one after another with the same options."""
+    storage, against the same LPs solved one after another with the same options. `parent`:
+    "mixed" = parents of 30 to 1,000 buses; "medium" = 2,000-bus parents (seeds 100 + i), each
+    member filling the GPU on its own (no warm-up solves there: one batch solve takes minutes
+    and its graph capture is a negligible share)."""
     import numpy as np
     import torch
 
-    from paper_2510_10891_amd import fixing, hprlp
+    from paper_2510_10891_amd import fixing, hprlp, scuc
 
+    big = parent == "medium"
     t = time.perf_counter()
-    lps = [p.lp for p in fixing.make_reduced_batch(count=count, seed0=100)]
+    pre = fixing.make_reduced_batch(count=count, seed0=100, parent=scuc.MEDIUM if big else None,
+                                    workers=min(8, os.cpu_count() or 1) if big else 1, log=log if big else None)
+    lps = [p.lp for p in pre]
+    del pre
     log(f"batch: {count} reduced LPs, n {min(lp.n for lp in lps)}..{max(lp.n for lp in lps)}, "
         f"nnz total {sum(lp.nnz for lp in lps)} ({time.perf_counter() - t:.1f} s)")
     opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream)
     b = hprlp.hpr_batch_create(lps, opts)
-    hprlp.hpr_batch_solve(b)                     # warm-up
+    if not big:
+        hprlp.hpr_batch_solve(b)                 # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = hprlp.hpr_batch_solve(b)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    log(f"batch solve {t_batch:.2f} s")
     worst = max(i.rel_kkt for i in infos)       # FP64 evaluation by the library
     setup = infos[0].setup_s
     hprlp.hpr_batch_destroy(b)
-    handles = [hprlp.hpr_create(lp, opts) for lp in lps]
-    for h in handles:
-        hprlp.hpr_solve(h)                       # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    seq = [hprlp.hpr_solve(h) for h in handles]
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    for h in handles:
-        hprlp.hpr_destroy(h)
+    seq, t_seq = [], 0.0
+    for k in range(0, count, 16 if big else count):   # big members: 16 handles at a time
+        handles = [hprlp.hpr_create(lp, opts) for lp in lps[k:k + (16 if big else count)]]
+        if not big:
+            for h in handles:
+                hprlp.hpr_solve(h)               # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq += [hprlp.hpr_solve(h) for h in handles]
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        for h in handles:
+            hprlp.hpr_destroy(h)
+        log(f"sequential: {len(seq)}/{count} solved one by one ({t_seq:.1f} s)")
     iters = np.array([i.iters for i in infos])
-    out = dict(workload=f"{count} reduced SCUC LPs (Algorithm 1 fixings, 20-90% of u fixed, presolved)",
+    name = "2,000-bus parents" if big else "parents of 30-1,000 buses"
+    out = dict(workload=f"{count} reduced SCUC LPs ({name}; Algorithm 1 fixings, 20-90% of u fixed, presolved)",
                lps=count, nnz_total=int(sum(lp.nnz for lp in lps)),
                n_min=int(min(lp.n for lp in lps)), n_max=int(max(lp.n for lp in lps)),
                batch_s=round(t_batch, 4), lps_per_s=round(count / t_batch, 2),
@@ -116,7 +160,8 @@ def batch_leg(count, stream):
                solved=int(sum(i.term == "solved" for i in infos)),
                seq_solved=int(sum(i.term == "solved" for i in seq)),
                worst_rel_kkt_fp64_eval=worst, setup_s=round(setup, 2),
-               iters_min=int(iters.min()), iters_median=int(np.median(iters)), iters_max=int(iters.max()))
+               iters_min=int(iters.min()), iters_median=int(np.median(iters)), iters_max=int(iters.max()),
+               iters_total=int(iters.sum()), warmed_up=not big)
     log(f"batch: {out}")
     return out
 
@@ -165,6 +210,18 @@ def warmstart_leg(n_train, n_eval, stream):
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     hprlp.hpr_batch_destroy(b)
+    # the plain solver on the same LPs: FP64, cold, one LP after another
+    opts64 = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP64, max_iter=100000, stream=stream)
+    handles = [hprlp.hpr_create(lp, opts64) for lp in ev]
+    for h in handles:
+        hprlp.hpr_solve(h)                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [hprlp.hpr_solve(h) for h in handles]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for h in handles:
+        hprlp.hpr_destroy(h)
     ci = np.array([i.iters for i in cold])
     wi = np.array([i.iters for i in warm])
     out = dict(train_lps=len(keep), eval_lps=len(ev), train_s=round(t_train, 2),
@@ -175,9 +232,46 @@ def warmstart_leg(n_train, n_eval, stream):
                median_lp_ratio=round(float(np.median(wi / ci)), 4),
                warm_used=int(sum(i.warm_start for i in warm)),
                cold_batch_s=round(t_cold, 3), warm_batch_s=round(t_warm + t_inf, 3), inference_s=round(t_inf, 3),
-               all_solved=bool(all(i.term == "solved" for i in cold + warm)),
+               plain_fp64_sequential_s=round(t_plain, 3),
+               speedup_fp32_batched_warm_vs_plain_fp64=round(t_plain / (t_warm + t_inf), 3),
+               all_solved=bool(all(i.term == "solved" for i in cold + warm + plain)),
                worst_rel_kkt_fp64_eval=float(max(i.rel_kkt for i in warm)))
     log(f"warm start: {out}")
+    return out
+
+
+def ablation_leg(data, rounds, stream):
+    """LP-side analogue of the paper's ablation (Section V): successive fixing with `rounds`
+    rounds on the bench instance under three solver configurations, LP time only (creation
+    with scaling and lambda, plus the rounds' solves). SF(FOM): Ruiz (10 passes) + Pock-
+    Chambolle + b/c normalisation, no instance-aware scaling, FP64. SF(FOM+FP32): the same
+    with FP32 storage. SF: instance-aware scaling (Section III-A), Ruiz off, FP32."""
+    import torch
+
+    from paper_2510_10891_amd import hprlp, scuc, successive
+
+    full = hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_RUIZ | hprlp.HPR_SCALE_BC
+    runs = [("SF(FOM)", False, full, hprlp.HPR_FP64), ("SF(FOM+FP32)", False, full, hprlp.HPR_FP32),
+            ("SF", True, hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_BC, hprlp.HPR_FP32)]
+    out = []
+    for name, inst, scaling, prec in runs:
+        lp = scuc.build_lp(data, instance_scaling=inst)
+        eta_c = lp.meta["eta_c"]
+        opts = hprlp.Options(tol=1e-4, precision=prec, scaling=scaling, ruiz_iters=10, max_iter=200000,
+                             stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = successive.run(data, lp, rounds=rounds, tau=0.1, opts=opts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        rec = dict(method=name, instance_scaling=inst, ruiz=bool(scaling & hprlp.HPR_SCALE_RUIZ),
+                   precision="fp32" if prec == hprlp.HPR_FP32 else "fp64", lp_time_s=round(total, 3),
+                   solve_s=round(sum(x.solve_s for x in r.rounds), 3),
+                   iters=[x.iters for x in r.rounds], terms=[x.term for x in r.rounds],
+                   objective=[x.objective * eta_c for x in r.rounds],
+                   fixed_u=[round(x.fixed_u, 4) for x in r.rounds])
+        log(f"ablation: {rec}")
+        out.append(rec)
     return out
 
 
@@ -188,11 +282,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="medium")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample-iters", type=int, default=640)
+    ap.add_argument("--cpu-limit", type=float, default=40.0,
+                    help="wall-time bound (s) of the oracle solve in the cpu_baseline leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="LPs in the batch leg (0: skip)")
+    ap.add_argument("--batch-parent", choices=["mixed", "medium"], default="mixed",
+                    help="parents of the batch's reduced LPs: 30-1,000 buses, or the 2,000-bus preset")
     ap.add_argument("--successive", type=int, default=0,
                     help="rounds of the successive-fixing leg on the bench instance (0: skip)")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="rounds of the scaling/precision ablation leg (successive fixing; 0: skip)")
     ap.add_argument("--warmstart", type=int, default=0,
                     help="training LPs of the learned warm-start leg (0: skip)")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -249,7 +348,7 @@ def main():
         kname, kbytes, kms = "primal_step_fp32", pb, ks["primal_ms"]
     achieved = kbytes / (kms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, data.cfg.name),
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
                 schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
@@ -257,7 +356,7 @@ def main():
                 stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
                 frac_of_stream_read=round(achieved / read_gbs, 4))
 
-    batch = batch_leg(args.batch, stream) if args.batch > 0 else None
+    batch = batch_leg(args.batch, stream, args.batch_parent) if args.batch > 0 else None
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
     sf = None
     if args.successive > 0:
@@ -268,9 +367,12 @@ def main():
                    objective=x.objective, fixed_u=round(x.fixed_u, 4), newly_fixed=x.newly_fixed) for x in r.rounds]
         log(f"successive fixing: {sf}")
 
+    abl = ablation_leg(data, args.ablation, stream) if args.ablation > 0 else None
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(lp, f64["info"].iters, args.cpu_sample_iters)
+        cpu = cpu_baseline(lp, f64["info"].iters, args.cpu_limit,
+                           {"fp32": f32["info"].pobj, "fp64": f64["info"].pobj})
         log(f"cpu baseline: {cpu}")
 
     rel_obj = abs(f32["info"].pobj - f64["info"].pobj) / max(1.0, abs(f64["info"].pobj))
@@ -306,6 +408,7 @@ def main():
         "batch": batch,
         "warm_start": warm,
         "successive_fixing": sf,
+        "ablation": abl,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -98,14 +98,20 @@ typedef struct {
     int32_t restart;            /* restart rule on (default 1) */
     int32_t sigma_update;       /* sigma adaptation at restarts on (default 1) */
     double sigma_smoothing;     /* weight w in (0, 1] of the target in the log-space update
-                                   log sigma <- (1 - w) log sigma + w log sigma* (default 0.5) */
+                                   log sigma <- (1 - w) log sigma + w log sigma* at restarts;
+                                   default 1 (sigma <- sigma*); 0.5 = geometric mean */
+    double sigma_smoothing_warm;/* w for an LP whose solve starts from the point given by
+                                   hpr_set_start / hpr_batch_set_start (default 0.5: near the
+                                   solution the anchor move that sigma* is built from is small
+                                   and noisy, so it is followed halfway) */
     int32_t power_max_iter;     /* default 200 */
     double power_tol;           /* relative change that stops the power method (default 1e-6) */
     int32_t profile;            /* 1: time one primal and one dual kernel per block of
                                    iterations with HIP events (hpr_get_kernel_stats) */
     int32_t unroll;             /* quads (4 entries) per lane and pass in the matrix products:
                                    1, 2, 4 or 8; 0 (default) = pick per matrix by timing at
-                                   hpr_create. The choice fixes the summation order. */
+                                   hpr_create (U = 1, 2, 4; ordinary or non-temporal loads).
+                                   The choice fixes the summation order. */
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
                                    its check and its control step as one captured HIP graph;
                                    0: launch every kernel directly */

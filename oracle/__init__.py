@@ -51,6 +51,7 @@ class _Opts(C.Structure):
                 ("restart", C.c_int32), ("sigma_update", C.c_int32), ("sigma0", C.c_double),
                 ("lambda_in", C.c_double), ("seed", C.c_uint64), ("power_max_iter", C.c_int32),
                 ("power_tol", C.c_double), ("time_limit", C.c_double), ("sigma_smoothing", C.c_double),
+                ("sigma_smoothing_warm", C.c_double),
                 ("x0", C.c_void_p), ("y0", C.c_void_p)]
 
 
@@ -116,13 +117,14 @@ class Options:
     power_max_iter: int = 200
     power_tol: float = 1e-6
     time_limit: float = 0.0
-    sigma_smoothing: float = 0.5
+    sigma_smoothing: float = 1.0
+    sigma_smoothing_warm: float = 0.5
 
 
 def _opts(o: Options, x0=None, y0=None):
     return _Opts(o.tol, o.max_iter, o.check_every, o.ruiz_iters, int(o.use_pc), int(o.use_bc),
                  int(o.restart), int(o.sigma_update), o.sigma0, o.lambda_in, o.seed,
-                 o.power_max_iter, o.power_tol, o.time_limit, o.sigma_smoothing,
+                 o.power_max_iter, o.power_tol, o.time_limit, o.sigma_smoothing, o.sigma_smoothing_warm,
                  x0.ctypes.data if x0 is not None else None,
                  y0.ctypes.data if y0 is not None else None)
 

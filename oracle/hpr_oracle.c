@@ -67,6 +67,7 @@ typedef struct {
     double power_tol;
     double time_limit;       /* seconds, <= 0: none */
     double sigma_smoothing;  /* weight w of sigma* in log sigma <- (1 - w) log sigma + w log sigma* */
+    double sigma_smoothing_warm;  /* the same weight when a start point (x0 or y0) is given */
     const double *x0;        /* warm start (original space) or NULL */
     const double *y0;
 } orc_opts;
@@ -498,8 +499,10 @@ static void unscale(const scaled_lp *s, const double *xb, const double *yb, cons
  *   - first check: r0 = r_prev = r, no restart;
  *   - restart when r <= 0.2 r0, or (r <= 0.8 r0 and r > r_prev), or when the
  *     iterations since the last restart are >= 0.2 of all iterations so far;
- *   - on restart: log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing, 1/2 by
- *     default, i.e. sigma <- sqrt(sigma * sigma*)) with sigma* = ||dx|| / (sqrt(lambda) ||dy||),
+ *   - on restart: log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing from a cold
+ *     start, 1 by default: sigma <- sigma*; w = sigma_smoothing_warm when a start point is given,
+ *     1/2 by default: sigma <- sqrt(sigma * sigma*); w = 1 and 1/2 evaluated without exp/log)
+ *     with sigma* = ||dx|| / (sqrt(lambda) ||dy||),
  *     (dx, dy) = (xbar - x0, ybar - y0) the move of the anchor, skipped when either norm is
  *     below 1e-12, clamped to [1e-4, 1e4]; then anchor = current = (xbar, ybar), k = 0,
  *     r0 = r.
@@ -591,8 +594,10 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
                 ddy = sqrt(ddy);
                 if (ddx > 1e-12 && ddy > 1e-12) {
                     double star = ddx / (sqrt(lambda) * ddy);
-                    double w = o->sigma_smoothing;
-                    double next = (w == 0.5) ? sqrt(sigma * star) : exp((1.0 - w) * log(sigma) + w * log(star));
+                    double w = (o->x0 || o->y0) ? o->sigma_smoothing_warm : o->sigma_smoothing;
+                    double next = (w == 1.0)   ? star
+                                  : (w == 0.5) ? sqrt(sigma * star)
+                                               : exp((1.0 - w) * log(sigma) + w * log(star));
                     sigma = clampd(next, 1e-4, 1e4);
                 }
             }

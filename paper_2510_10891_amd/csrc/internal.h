@@ -76,6 +76,7 @@ struct LpState {
     int64_t it, k, restarts;
     int32_t term;                // 0 running, else HPR_SOLVED ...
     int32_t candidate;           // FP32 check passed, awaiting FP64 confirmation
+    int32_t warm;                // the solve started from the caller's point (sigma weight)
 };
 
 // Problem vectors of the scaled LP (type Tp) and the diagonal scaling (FP64).
@@ -131,7 +132,8 @@ struct ControlArgs {
     double tol;
     int restart_rule;
     int sigma_update;
-    double sigma_smoothing;  // weight of sigma* in the log-space update
+    double sigma_smoothing;       // weight of sigma* in the log-space update (cold start)
+    double sigma_smoothing_warm;  // the same from the caller's start point
 };
 void launch_control(const ControlArgs& a, hipStream_t st);
 // y = A x (plain product, used by the power method).

@@ -69,10 +69,37 @@ __device__ __forceinline__ int4 load_idx16(const uint16_t* p, int base) {
                      base + (int)(v.y >> 16));
 }
 
+// Lane moves within rows of 16 lanes (DPP): each lane reads the value of the lane that the
+// control word names (quad permutations, half-row and row mirrors).
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i within each 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <- lane 15 - i within each 16 lanes
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xFFFFFFFFull), CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over each aligned group of G lanes, left in every lane of the group. Pairs first
+// (lanes i and i^1, then quads, half-rows of 8, rows of 16 by DPP moves, which are exact
+// because after each step every lane of a block holds the same value), then rows of 16 and
+// 32 by cross-lane shuffles; a fixed tree, so the result is the same in every run.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    if constexpr (G >= 2) v += dpp_move<kDppXor1>(v);
+    if constexpr (G >= 4) v += dpp_move<kDppXor2>(v);
+    if constexpr (G >= 8) v += dpp_move<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_move<kDppMirror>(v);
+    if constexpr (G >= 32) v += __shfl_xor(v, 16, G);
+    if constexpr (G >= 64) v += __shfl_xor(v, 32, G);
     return v;
 }
 
@@ -532,8 +559,9 @@ __device__ void store_values(LpState& S, const CheckValues& v) {
 // After a check that did not terminate: iteration limit, then the restart rule:
 // restart when r <= 0.2 r0, or r <= 0.8 r0 while rising (r > r_prev), or when the
 // iterations since the last restart are >= 0.2 of all iterations. At a restart
-// log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing; w = 1/2 is
-// sigma <- sqrt(sigma sigma*)), sigma* = ||dx|| / (sqrt(lambda) ||dy||) from the anchor
+// log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing, or sigma_smoothing_warm for
+// an LP started from the caller's point; w = 1 is sigma <- sigma*, w = 1/2 is sigma <- sqrt(sigma
+// sigma*)), sigma* = ||dx|| / (sqrt(lambda) ||dy||) from the anchor
 // move (skipped below 1e-12), clamped to [1e-4, 1e4]; anchor = iterate = bar point, k = 0.
 __device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, double move_x, double move_y) {
 #pragma clang fp contract(off)
@@ -558,8 +586,10 @@ __device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, doub
         double sigma = c.sigma;
         if (a.sigma_update && move_x > 1e-12 && move_y > 1e-12) {
             const double star = move_x / (sqrt(c.lambda) * move_y);
-            const double w = a.sigma_smoothing;
-            sigma = (w == 0.5) ? sqrt(sigma * star) : exp((1.0 - w) * log(sigma) + w * log(star));
+            const double w = S.warm ? a.sigma_smoothing_warm : a.sigma_smoothing;
+            sigma = (w == 1.0)   ? star
+                  : (w == 0.5) ? sqrt(sigma * star)
+                               : exp((1.0 - w) * log(sigma) + w * log(star));
             sigma = sigma < 1e-4 ? 1e-4 : (sigma > 1e4 ? 1e4 : sigma);
         }
         c.sigma = sigma;

@@ -232,8 +232,9 @@ static int validate_opts(const hpr_opts* o) {
     if (std::isnan(o->lambda)) return fail(HPR_ERR_INVALID, "lambda is NaN");
     if ((o->scaling & HPR_SCALE_RUIZ) && o->ruiz_iters < 0) return fail(HPR_ERR_INVALID, "ruiz_iters < 0");
     if (!(o->warm_fallback_ratio > 0)) return fail(HPR_ERR_INVALID, "warm_fallback_ratio must be > 0");
-    if (!(o->sigma_smoothing > 0 && o->sigma_smoothing <= 1))
-        return fail(HPR_ERR_INVALID, "sigma_smoothing must be in (0, 1]");
+    if (!(o->sigma_smoothing > 0 && o->sigma_smoothing <= 1) ||
+        !(o->sigma_smoothing_warm > 0 && o->sigma_smoothing_warm <= 1))
+        return fail(HPR_ERR_INVALID, "sigma_smoothing and sigma_smoothing_warm must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
     return HPR_OK;
@@ -537,7 +538,8 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->use_graph = 1;
     o->warm_fallback = 1;
     o->warm_fallback_ratio = 1000.0;
-    o->sigma_smoothing = 0.5;
+    o->sigma_smoothing = 1.0;
+    o->sigma_smoothing_warm = 0.5;
     o->stream = nullptr;
 }
 
@@ -608,9 +610,10 @@ static void put_ctrl(Engine* e) {
 }
 
 // Schedule tuner: for each pooled matrix, time the fused step kernel that streams it (dual
-// step for A~, primal step for A~^T) with U = 1, 2, 4, 8 quads per lane and pass, each with
-// ordinary and with non-temporal loads of the matrix, and keep the fastest. A forced
-// opts.unroll skips the timing (ordinary loads).
+// step for A~, primal step for A~^T) with U = 1, 2, 4 quads per lane and pass, then the best U
+// with ordinary and with non-temporal loads of the matrix, and keep the fastest. A forced
+// opts.unroll skips all timing (ordinary loads), so two engines with the same forced options
+// run the same schedule (same summation order, bitwise equal results).
 template <typename T>
 static void autotune(Engine* e) {
     hipStream_t st = e->st;
@@ -627,7 +630,7 @@ static void autotune(Engine* e) {
         c.active = 1;
     }
     put_ctrl(e);
-    const int forced = e->opts.unroll;
+    const int fU = e->opts.unroll;
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
@@ -635,18 +638,12 @@ static void autotune(Engine* e) {
     const DevIter<T> v = e->iter<T>();
     for (int which = 0; which < 2; ++which) {
         DevMatrix& Mx = which == 0 ? e->A : e->At;
-        if (forced) {
-            Mx.set_unroll(forced, st);
-            Mx.nontemporal = 0;
+        Mx.nontemporal = 0;
+        if (fU || Mx.nrows == 0) {
+            Mx.set_unroll(fU ? fU : 4, st);
             continue;
         }
-        if (Mx.nrows == 0) continue;
-        int bestU = 4, bestNT = 0;
-        float best = 1e30f;
-        for (int cand = 0; cand < 8; ++cand) {
-            const int U = 1 << (cand >> 1), NT = cand & 1;
-            if ((cand & 1) == 0) Mx.set_unroll(U, st);
-            Mx.nontemporal = NT;
+        auto time_it = [&]() {
             const DevCsr<T> view = Mx.view<T>();
             auto launch = [&]() {
                 if (which == 0) launch_dual_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
@@ -659,14 +656,20 @@ static void autotune(Engine* e) {
             HIP_OK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bestU = U;
-                bestNT = NT;
-            }
+            return ms;
+        };
+        int bestU = 4;
+        float best = 1e30f;
+        for (int U : {1, 2, 4}) {
+            Mx.set_unroll(U, st);
+            const float ms = time_it();
+            if (ms < best) best = ms, bestU = U;
         }
         Mx.set_unroll(bestU, st);
-        Mx.nontemporal = bestNT;
+        const float ms_plain = time_it();
+        Mx.nontemporal = 1;
+        const float ms_nt = time_it();
+        Mx.nontemporal = ms_nt < ms_plain ? 1 : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -971,6 +974,7 @@ ControlArgs control_args(Engine* e, int phase, int nb) {
     a.restart_rule = e->opts.restart;
     a.sigma_update = e->opts.sigma_update;
     a.sigma_smoothing = e->opts.sigma_smoothing;
+    a.sigma_smoothing_warm = e->opts.sigma_smoothing_warm;
     return a;
 }
 
@@ -1038,7 +1042,9 @@ int32_t read_stat(Engine* e, int which) {
 // cut at max_iter), each ending with a check of every running LP; the device takes every
 // decision (control_kernel), the host only polls how many LPs are still running, confirms
 // FP32-storage candidates in FP64 and applies the time limit.
-void init_control(Engine* e) {
+// per-LP controls and state; `use_start`: the solve starts from the uploaded caller's points
+// (the LPs that have one and are not masked out), which selects the warm sigma weight
+void init_control(Engine* e, bool use_start) {
     const hpr_opts& o = e->opts;
     for (int l = 0; l < e->L; ++l) {
         const LpHost& h = e->lps[l];
@@ -1057,6 +1063,8 @@ void init_control(Engine* e) {
         S.norm_b = h.norm_b;
         S.norm_c = h.norm_c;
         S.obj_offset = h.obj_offset;
+        const bool has_start = !h.x_start.empty() || !h.y_start.empty();
+        S.warm = (use_start && has_start && (e->use_start_mask.empty() || e->use_start_mask[l])) ? 1 : 0;
     }
     HIP_OK(hipMemcpyAsync(e->state.p, e->state_h.data(), sizeof(LpState) * e->L, hipMemcpyHostToDevice, e->st));
     put_ctrl(e);
@@ -1066,7 +1074,7 @@ void init_control(Engine* e) {
 template <typename T>
 std::vector<double> probe_first_check(Engine* e, bool use_start) {
     upload_start<T>(e, use_start);
-    init_control(e);
+    init_control(e, use_start);
     if (e->g_first) HIP_OK(hipGraphLaunch(e->g_first, e->st));
     else enqueue_block<T>(e, 1, false);
     HIP_OK(hipMemcpyAsync(e->state_h.data(), e->state.p, sizeof(LpState) * e->L, hipMemcpyDeviceToHost, e->st));
@@ -1103,7 +1111,7 @@ void solve_loop(Engine* e, double t0) {
     }
     e->use_start_mask = e->warm_used;
     upload_start<T>(e, true);
-    init_control(e);
+    init_control(e, true);
     e->kstats = hpr_kernel_stats{};
     if (o.profile && !e->ev[0])
         for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));

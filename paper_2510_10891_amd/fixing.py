@@ -150,12 +150,32 @@ def reduced_lp(parent: scuc.SCUCConfig, seed: int, target: float, tau: float = 0
     return pre
 
 
-def make_reduced_batch(count: int = 64, seed0: int = 100, classes: int | None = None):
-    """`count` reduced LPs: LP i has parent size class i mod (number of classes), parent seed
-    seed0 + i, and about 0.2 + 0.7 i / (count - 1) of its u variables fixed."""
+def _batch_member(args):
+    parent, seed, target = args
+    return reduced_lp(parent, seed, target)
+
+
+def make_reduced_batch(count: int = 64, seed0: int = 100, classes: int | None = None,
+                       parent: scuc.SCUCConfig | None = None, workers: int = 1, log=None):
+    """`count` reduced LPs: LP i has parent seed seed0 + i and about 0.2 + 0.7 i / (count - 1)
+    of its u variables fixed. Its parent is `parent` when given (e.g. the 2,000-bus preset),
+    else size class i mod (number of classes) of the mixed parent list."""
     k = classes or len(BATCH_PARENTS)
-    out = []
-    for i in range(count):
-        target = 0.2 + 0.7 * i / max(count - 1, 1)
-        out.append(reduced_lp(BATCH_PARENTS[i % k], seed0 + i, target))
-    return out
+    jobs = [(parent if parent is not None else BATCH_PARENTS[i % k], seed0 + i,
+             0.2 + 0.7 * i / max(count - 1, 1)) for i in range(count)]
+    if workers <= 1:
+        out = []
+        for j in jobs:
+            out.append(_batch_member(j))
+            if log is not None:
+                log(f"reduced LP {len(out)}/{count}: parent {j[0].name} seed {j[1]} nnz {out[-1].lp.nnz}")
+        return out
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = []
+        for r in pool.imap(_batch_member, jobs):
+            out.append(r)
+            if log is not None:
+                log(f"reduced LP {len(out)}/{count}: parent {r.lp.meta['parent']} seed {r.lp.meta['seed']} "
+                    f"nnz {r.lp.nnz}")
+        return out

@@ -39,7 +39,7 @@ class hpr_opts(C.Structure):
                 ("precision", C.c_int32), ("scaling", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
-                ("sigma_smoothing", C.c_double), ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
+                ("sigma_smoothing", C.c_double), ("sigma_smoothing_warm", C.c_double), ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
                 ("unroll", C.c_int32), ("use_graph", C.c_int32),
                 ("warm_fallback", C.c_int32), ("warm_fallback_ratio", C.c_double), ("stream", C.c_void_p)]
 
@@ -104,7 +104,8 @@ class Options:
     seed: int = 0
     restart: int = 1
     sigma_update: int = 1
-    sigma_smoothing: float = 0.5
+    sigma_smoothing: float = 1.0
+    sigma_smoothing_warm: float = 0.5
     power_max_iter: int = 200
     power_tol: float = 1e-6
     profile: int = 0

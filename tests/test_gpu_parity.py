@@ -160,10 +160,25 @@ def test_fp64_iterates_match_oracle_small_scuc(seed, K):
 
 @pytest.mark.parametrize("variant", [dict(use_pc=False, use_bc=False), dict(ruiz_iters=10),
                                      dict(restart=False, sigma_update=False), dict(lambda_in=0.9),
-                                     dict(sigma_smoothing=1.0), dict(sigma_smoothing=0.25)])
+                                     dict(sigma_smoothing=0.5), dict(sigma_smoothing=0.25)])
 def test_fp64_options_match_oracle(variant):
     _, lp = scuc.make_instance("small", 3)
     o, info, x, y, z = run_both(lp, 300, **variant)
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("variant", [dict(), dict(sigma_smoothing_warm=1.0), dict(sigma_smoothing_warm=0.25)])
+def test_warm_started_iterates_match_oracle(variant):
+    """From a caller's start point (the warm sigma weight applies), iterations with restarts
+    agree element by element with the oracle started from the same point."""
+    _, lp = scuc.make_instance("small", 2)
+    ref = oracle.solve(lp, oracle.Options(tol=1e-3, max_iter=100000))
+    rng = np.random.default_rng(0)
+    x0 = ref.x + 0.05 * rng.standard_normal(lp.n)
+    y0 = ref.y * (1 + 0.2 * rng.standard_normal(lp.m))
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=700, **variant), x0, y0)
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=0.0, max_iter=700, warm_fallback=0, **variant), x0=x0, y0=y0)
+    assert o.restarts > 0 and info.warm_start == 1
     assert_parity(o, info, x, y, z, FP64_RTOL)
 
 
