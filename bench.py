@@ -96,6 +96,15 @@ def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
                          f"{r.solve_s:.1f} s + setup {r.setup_s:.1f} s")
         out["oracle_pobj"] = r.pobj
         out["gpu_obj_rel_err_vs_oracle"] = {k: abs(v - r.pobj) / max(1.0, abs(r.pobj)) for k, v in gpu_objs.items()}
+        # the same instance on one core: a short sample, extrapolated to the full solve
+        nt = oracle.num_threads()
+        oracle.set_num_threads(1)
+        k = 64
+        r1 = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=k))
+        oracle.set_num_threads(nt)
+        out["single_thread"] = dict(value=round(r1.setup_s + r.iters * r1.solve_s / r1.iters, 3), cores=1,
+                                    sample=f"{r1.iters} iterations on one core in {r1.solve_s:.1f} s plus setup "
+                                           f"{r1.setup_s:.1f} s, extrapolated to the {r.iters} iterations above")
     else:
         out["value"] = round(r.setup_s + gpu_fp64_iters / its_per_s, 3)
         out["sample"] = (f"{r.iters} oracle iterations of the same instance in {r.solve_s:.1f} s (stopped at "
@@ -176,11 +185,14 @@ def warmstart_leg(n_train, n_eval, stream):
     from paper_2510_10891_amd import fixing, hprlp, warmstart
 
     t0 = time.perf_counter()
-    lps = warmstart.training_lps(n_train, workers=min(16, os.cpu_count() or 1))
+    lps = []
+    for k in range(0, n_train, 200):
+        lps += warmstart.training_lps_range(k, min(k + 200, n_train), workers=min(16, os.cpu_count() or 1))
+        log(f"warm start: {len(lps)} of {n_train} training LPs generated")
     t_gen = time.perf_counter() - t0
     opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream)
     t0 = time.perf_counter()
-    sols, ok = warmstart.label(lps, opts)
+    sols, ok = warmstart.label(lps, opts, log=log)
     t_label = time.perf_counter() - t0
     keep = [i for i in range(len(lps)) if ok[i]]
     Xg, Tg, Xl, Tl = warmstart.training_set([lps[i] for i in keep], [sols[i] for i in keep])

@@ -48,7 +48,15 @@ enum {
     HPR_SOLVED = 1,         /* rel_kkt <= tol, verified in FP64 */
     HPR_ITER_LIMIT = 2,
     HPR_TIME_LIMIT = 3,
-    HPR_NUMERIC_FAIL = 4    /* NaN or Inf appeared in a check */
+    HPR_NUMERIC_FAIL = 4,   /* NaN or Inf appeared in a check */
+    HPR_PRIMAL_INFEASIBLE = 5   /* at a check, the dual bar point ybar certifies that no x
+                                   satisfies the rows and bounds: with dz = -A^T ybar (scaled
+                                   problem), h = sum lo_i ybar_i+ - hi_i ybar_i- + sum l_j dz_j+
+                                   - u_j dz_j- exceeds 1e-6 times the sum of its terms'
+                                   magnitudes (h <= 0 for every sign-feasible y of a feasible
+                                   LP), and the sign violations of dz on infinite column bounds
+                                   sum to at most 1e-6 sum |ybar_i|; FP64-evaluated. Dual infeasibility
+                                   (an unbounded LP) is not detected: it runs to max_iter. */
 };
 
 /* storage precision of A and of the iterates (hpr_opts.precision) */

@@ -63,7 +63,7 @@ class _Info(C.Structure):
                 ("solve_s", C.c_double)]
 
 
-TERM = {1: "solved", 2: "iter_limit", 3: "time_limit", 4: "numeric_fail"}
+TERM = {1: "solved", 2: "iter_limit", 3: "time_limit", 4: "numeric_fail", 5: "primal_infeasible"}
 _lib = None
 
 
@@ -225,6 +225,11 @@ def hpr_step(lp, sigma, lam, k, x0, y0, x, y):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """Threads of the oracle's row loops from now on; returns the number in use."""
+    return _load().orc_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------------- numpy KKT

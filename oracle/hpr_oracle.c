@@ -73,12 +73,16 @@ typedef struct {
 } orc_opts;
 
 typedef struct {
-    int32_t term;            /* 1 solved, 2 iteration limit, 3 time limit, 4 numeric failure */
+    int32_t term;            /* 1 solved, 2 iteration limit, 3 time limit, 4 numeric failure,
+                                5 primal infeasible */
     int64_t iters, restarts;
     double pobj, dobj, rel_p, rel_d, rel_gap, rel_kkt, lambda, sigma, setup_s, solve_s;
 } orc_info;
 
-enum { ORC_SOLVED = 1, ORC_ITER_LIMIT = 2, ORC_TIME_LIMIT = 3, ORC_NUMERIC_FAIL = 4 };
+enum { ORC_SOLVED = 1, ORC_ITER_LIMIT = 2, ORC_TIME_LIMIT = 3, ORC_NUMERIC_FAIL = 4, ORC_PRIMAL_INFEASIBLE = 5 };
+
+/* relative margin of the primal infeasibility certificate */
+#define ORC_INFEAS_TOL 1e-6
 
 static double now_s(void) {
     struct timespec ts;
@@ -487,6 +491,43 @@ static void unscale(const scaled_lp *s, const double *xb, const double *yb, cons
     for (int32_t i = 0; i < s->m; ++i) y[i] = s->beta_c * s->dr[i] * yb[i];
 }
 
+/* Primal infeasibility certificate test (an addition to the method: the paper does not
+ * treat infeasible LPs). Weak duality for the row-bounded LP gives, for any feasible x and
+ * any y that is sign-feasible (y_i > 0 only where lo_i is finite, y_i < 0 only where hi_i is
+ * finite) with dz = -A^T y sign-feasible for the column bounds:
+ *     h(y) = sum_i (lo_i y_i+ - hi_i y_i-) + sum_j (l_j dz_j+ - u_j dz_j-)
+ *          <= sum_i (Ax)_i y_i + sum_j x_j dz_j = 0,
+ * so h(y) > 0 proves that no feasible x exists. Evaluated on the scaled problem at the bar
+ * point ybar (sign-feasible by its projection); the ratios below do not change under the
+ * diagonal scaling of rows and columns. out: [0] h, [1] sum of the magnitudes of h's terms,
+ * [2] sign violations of dz on infinite bounds (zero when every column is bounded), [3] the
+ * size of ybar, sum |ybar_i| (the rows of the scaled matrix have norms near 1, so violations
+ * are compared with it). aty: n doubles of work. */
+static void certificate(const scaled_lp *s, const double *yb, double *aty, double out[4]) {
+    double h = 0.0, mag = 0.0, viol = 0.0, ysum = 0.0;
+    for (int32_t i = 0; i < s->m; ++i) {
+        ysum += fabs(yb[i]);
+        if (yb[i] > 0.0) { h += s->lo[i] * yb[i]; mag += fabs(s->lo[i]) * yb[i]; }
+        else if (yb[i] < 0.0) { h += s->hi[i] * yb[i]; mag += fabs(s->hi[i]) * -yb[i]; }
+    }
+    spmv(s->n, s->trp, s->tci, s->tv, yb, aty);   /* A~^T ybar */
+    for (int32_t j = 0; j < s->n; ++j) {
+        double dz = -aty[j];
+        if (dz > 0.0) {
+            if (isfinite(s->l[j])) { h += s->l[j] * dz; mag += fabs(s->l[j]) * dz; }
+            else viol += dz;
+        } else if (dz < 0.0) {
+            if (isfinite(s->u[j])) { h += s->u[j] * dz; mag += fabs(s->u[j]) * -dz; }
+            else viol += -dz;
+        }
+    }
+    out[0] = h; out[1] = mag; out[2] = viol; out[3] = ysum;
+}
+
+static int certifies_infeasibility(const double c[4]) {
+    return c[0] > ORC_INFEAS_TOL * c[1] && c[2] <= ORC_INFEAS_TOL * c[3];
+}
+
 /*
  * Full solve. Outputs the unscaled (x, y, z) of the last check and fills info.
  *
@@ -527,6 +568,7 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     double *yprev = (double *)malloc(sizeof(double) * mm);
     double *yb = (double *)malloc(sizeof(double) * mm), *wm = (double *)malloc(sizeof(double) * mm);
     double *dxv = (double *)malloc(sizeof(double) * n), *adx = (double *)malloc(sizeof(double) * mm);
+    double *aty = (double *)malloc(sizeof(double) * n), cert[4];
 
     /* start point: projections of the (scaled) warm start, or of zero */
     for (int32_t j = 0; j < n; ++j) {
@@ -562,6 +604,8 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
         orc_kkt(lp, x_out, y_out, z_out, kk);
         if (isnan(kk[3]) || !isfinite(kk[4])) { term = ORC_NUMERIC_FAIL; break; }
         if (kk[3] <= o->tol) { term = ORC_SOLVED; break; }
+        certificate(&s, yb, aty, cert);
+        if (certifies_infeasibility(cert)) { term = ORC_PRIMAL_INFEASIBLE; break; }
         if (last) { term = ORC_ITER_LIMIT; break; }
         if (timed_out) { term = ORC_TIME_LIMIT; break; }
 
@@ -621,7 +665,7 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     info->setup_s = t1 - t0;
     info->solve_s = t2 - t1;
     free(x); free(x0); free(xprev); free(xb); free(zb); free(xh); free(wn);
-    free(y); free(y0); free(yprev); free(yb); free(wm); free(dxv); free(adx);
+    free(y); free(y0); free(yprev); free(yb); free(wm); free(dxv); free(adx); free(aty);
     free_scaled(&s);
     return 0;
 }
@@ -630,6 +674,17 @@ int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
+    return 1;
+#endif
+}
+
+/* threads of the row loops from now on (n >= 1); returns the number now in use */
+int orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
     return 1;
 #endif
 }

@@ -338,6 +338,8 @@ struct DualOp {
 //   q3 = sum lo_i ybar_i+ - hi_i ybar_i-                      (scaled dual objective, rows)
 //   q4 = sum (ybar_i - y0_i)^2                                (anchor move)
 //   q5 = number of non-finite values
+//   q6 = sum |lo_i| ybar_i+ + |hi_i| ybar_i-                  (magnitude of q3's terms)
+//   q7 = sum |ybar_i|                                         (size of ybar)
 template <typename M, typename P, typename V>
 struct CheckRowsOp {
     using Tm = M;
@@ -375,6 +377,9 @@ struct CheckRowsOp {
         const double d0 = yb - double(v.y0[row]);
         q[4] += d0 * d0;
         if (!isfinite(a) || !isfinite(yb) || !isfinite(double(adx)) || !isfinite(dy)) q[5] += 1.0;
+        if (yb > 0.0) q[6] += fabs(lo) * yb;
+        else if (yb < 0.0) q[6] -= fabs(hi) * yb;
+        q[7] += fabs(yb);
     }
 };
 
@@ -383,6 +388,10 @@ struct CheckRowsOp {
 //   q1 = sum c_j xbar_j                                        (scaled primal objective)
 //   q2 = sum l_j zbar_j+ - u_j zbar_j-                          (scaled dual objective, columns)
 //   q3 = sum dx_j^2,  q4 = sum (xbar_j - x0_j)^2,  q5 = non-finite count
+// and, with dz = -(A^T ybar)_j (the column part of a primal infeasibility certificate built
+// from ybar, which is sign-feasible by construction):
+//   q6 = sum l_j dz_j+ - u_j dz_j- over finite bounds,  q7 = the same with |l_j|, |u_j|,
+//   q8 = sum of dz_j+ with l_j = -inf and dz_j- with u_j = +inf (sign violations)
 template <typename M, typename P, typename V>
 struct CheckColsOp {
     using Tm = M;
@@ -418,6 +427,23 @@ struct CheckColsOp {
         const double d0 = xb - double(v.x0[col]);
         q[4] += d0 * d0;
         if (!isfinite(double(aty)) || !isfinite(xb) || !isfinite(zb)) q[5] += 1.0;
+        const double dz = -double(aty);
+        const double l = double(p.l[col]), u = double(p.u[col]);
+        if (dz > 0.0) {
+            if (isfinite(l)) {
+                q[6] += l * dz;
+                q[7] += fabs(l) * dz;
+            } else {
+                q[8] += dz;
+            }
+        } else if (dz < 0.0) {
+            if (isfinite(u)) {
+                q[6] += u * dz;
+                q[7] -= fabs(u) * dz;
+            } else {
+                q[8] -= dz;
+            }
+        }
     }
 };
 
@@ -520,6 +546,7 @@ __global__ __launch_bounds__(kBlock) void finish_sums_kernel(const double* parti
 struct CheckValues {
     double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit, move_x, move_y;
     bool bad;
+    bool infeasible;   // ybar is a primal infeasibility certificate
 };
 
 // The relative KKT residuals of the original problem and the merit from the check sums
@@ -528,7 +555,7 @@ struct CheckValues {
 __device__ CheckValues check_values(const double* s, const Ctrl& c, const LpState& S) {
 #pragma clang fp contract(off)
     const double* r = s;
-    const double* k = s + 8;
+    const double* k = s + kColOff;
     CheckValues v;
     const double bb = c.beta_b * c.beta_c;
     v.rel_p = sqrt(r[0]) / (1.0 + S.norm_b);
@@ -543,6 +570,11 @@ __device__ CheckValues check_values(const double* s, const Ctrl& c, const LpStat
     v.move_y = sqrt(r[4]);
     v.bad = (r[5] + k[5]) > 0.0 || isnan(v.rel_p) || isnan(v.rel_d) || isnan(v.rel_gap) ||
             !isfinite(v.rel_kkt) || !isfinite(v.pobj) || !isfinite(v.merit);
+    // For a feasible LP, h(y) = sum lo_i y_i+ - hi_i y_i- + sum l_j dz_j+ - u_j dz_j- with
+    // dz = -A^T y is <= 0 for every sign-feasible y (it is bounded by y'Ax - y'Ax = 0), so
+    // h(ybar) > 0 certifies primal infeasibility; margins relative to the terms' magnitude.
+    const double h = r[3] + k[6], mag = r[6] + k[7];
+    v.infeasible = h > kInfeasTol * mag && k[8] <= kInfeasTol * r[7];
     return v;
 }
 
@@ -624,11 +656,11 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
                 if (v.bad) {
                     S.term = 4;   // HPR_NUMERIC_FAIL
                     c.active = 0;
-                } else if (v.rel_kkt <= a.tol) {
+                } else if (v.rel_kkt <= a.tol || v.infeasible) {
                     if (!a.fp32) {
-                        S.term = 1;   // HPR_SOLVED
+                        S.term = v.rel_kkt <= a.tol ? 1 : 5;   // HPR_SOLVED, HPR_PRIMAL_INFEASIBLE
                         c.active = 0;
-                    } else {
+                    } else {   // FP32 storage: confirmed (or not) by the FP64 re-evaluation
                         S.candidate = 1;
                         S.p32[0] = v.merit;
                         S.p32[1] = v.move_x;
@@ -643,9 +675,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
             if (c.active && S.candidate) {
                 S.candidate = 0;
                 const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
-                if (!v.bad && v.rel_kkt <= a.tol) {
+                if (!v.bad && (v.rel_kkt <= a.tol || v.infeasible)) {
                     store_values(S, v);
-                    S.term = 1;
+                    S.term = v.rel_kkt <= a.tol ? 1 : 5;
                     c.active = 0;
                 } else {
                     decide(S, c, a, S.p32[0], S.p32[1], S.p32[2]);

@@ -987,7 +987,7 @@ void enqueue_check(Engine* e, double* out) {
     launch_check_rows<Tm, Tp, Tv>(A, p, v, e->ctrl.as<Ctrl>(), e->part_r.as<double>(), e->st);
     launch_check_cols<Tm, Tp, Tv>(At, p, v, e->ctrl.as<Ctrl>(), e->part_c.as<double>(), e->st);
     launch_finish_sums(e->part_r.as<double>(), kRowQ, A.nblocks, e->A.seg.as<int32_t>(), e->L, out, 0, e->st);
-    launch_finish_sums(e->part_c.as<double>(), kColQ, At.nblocks, e->At.seg.as<int32_t>(), e->L, out, 8, e->st);
+    launch_finish_sums(e->part_c.as<double>(), kColQ, At.nblocks, e->At.seg.as<int32_t>(), e->L, out, kColOff, e->st);
 }
 
 // One block of nb iterations, the storage-precision check, the control (phase 1) and the

@@ -442,8 +442,10 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
 
     col_lo = np.zeros(n)
     col_hi = np.ones(n)
+    # p <= p_max: implied by p - p_max u <= 0 and u <= 1 (the feasible set does not change);
+    # stated as a column bound so that every column is boxed
     pcols = col_index(G, np.arange(T)[:, None], P, g[None, :]).ravel()
-    col_hi[pcols] = inf
+    col_hi[pcols] = np.tile(pmax, T)
     c = np.zeros(n)
     tt = np.arange(T)[:, None]
     c[col_index(G, tt, P, g[None, :]).ravel()] = np.tile(data.cost * eta_p / eta_c, T)

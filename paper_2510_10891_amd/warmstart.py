@@ -121,8 +121,10 @@ def targets(lp, x_red, y_red):
     return tg.astype(np.float32), (y_parent[srows] / meta["eta_p"]).astype(np.float32)
 
 
-def predict_start(gen_net: MLP, line_net: MLP, lp):
-    """Warm start (x0, y0) of a reduced LP from the two networks (original space of the LP)."""
+def predict_start(gen_net: MLP, line_net: MLP, lp, dual_threshold: float = 0.0):
+    """Warm start (x0, y0) of a reduced LP from the two networks (original space of the LP).
+    Security-row duals whose magnitude is below `dual_threshold` times the largest predicted
+    magnitude of the LP are set to 0 (most of these rows are slack at the optimum)."""
     meta = lp.meta
     d = meta["data"]
     G, T = d.cfg.n_gen, d.cfg.T
@@ -140,23 +142,36 @@ def predict_start(gen_net: MLP, line_net: MLP, lp):
     Fl, srows = line_features(meta, dispatch)
     y_parent = np.zeros(len(meta["row_sec"]))
     if len(srows):
-        y_parent[srows] = line_net.forward(Fl)[:, 0] * meta["eta_p"]
+        yp = line_net.forward(Fl)[:, 0].astype(np.float64)
+        if dual_threshold > 0 and len(yp):
+            yp[np.abs(yp) < dual_threshold * np.abs(yp).max()] = 0.0
+        y_parent[srows] = yp * meta["eta_p"]
     y0 = y_parent[meta["rows"]]
     return x0, y0
 
 
-def training_set(lps, solutions):
-    """Stacked (X_gen, T_gen, X_line, T_line) from solved reduced LPs [(x, y)]."""
+def training_set(lps, solutions, max_rows: int = 4000, seed: int = 0):
+    """Stacked (X_gen, T_gen, X_line, T_line) from solved reduced LPs [(x, y)]; at most
+    `max_rows` unit-hours and security rows per LP (a seeded sample), so that large parents do
+    not crowd out small ones."""
+    rng = np.random.default_rng(seed)
     xg, tg, xl, tl = [], [], [], []
+
+    def pick(k):
+        return np.arange(k) if k <= max_rows else np.sort(rng.choice(k, max_rows, replace=False))
+
     for lp, (x, y) in zip(lps, solutions):
         a, b = targets(lp, x, y)
-        xg.append(gen_features(lp.meta))
-        tg.append(a)
+        Fg = gen_features(lp.meta)
+        sg = pick(len(Fg))
+        xg.append(Fg[sg])
+        tg.append(a[sg])
         d = lp.meta["data"]
         dispatch = (a[:, 3] * np.repeat(d.p_max, d.cfg.T)).reshape(d.cfg.n_gen, d.cfg.T).T
         F, _ = line_features(lp.meta, dispatch)
-        xl.append(F)
-        tl.append(b[:, None])
+        sl = pick(len(F))
+        xl.append(F[sl])
+        tl.append(b[sl, None])
     return np.concatenate(xg), np.concatenate(tg), np.concatenate(xl), np.concatenate(tl)
 
 
@@ -171,29 +186,42 @@ def train(sizes, X, T, steps=1500, batch=4096, lr=1e-3, seed=0, stream=None):
     return net, losses
 
 
+# parent size class of training LP i: 30 % 30-bus, 30 % 100-bus, 20 % 300-bus, 10 % 600-bus and
+# 10 % 1,000-bus parents, so every size of the evaluation batch is represented
+_TRAIN_CLASSES = (0, 1, 2, 0, 1, 2, 3, 0, 1, 4)
+
+
 def _train_lp(i):
     from . import fixing
-    return fixing.reduced_lp(fixing.BATCH_PARENTS[i % 2], 10000 + i, 0.2 + 0.7 * ((i * 37) % 64) / 63).lp
+    parent = fixing.BATCH_PARENTS[_TRAIN_CLASSES[i % len(_TRAIN_CLASSES)]]
+    return fixing.reduced_lp(parent, 10000 + i, 0.2 + 0.7 * ((i * 37) % 64) / 63).lp
 
 
 def training_lps(count: int, workers: int = 1):
-    """Training instances: reduced LPs of the two smallest parent classes with seeds
-    10000 + i (disjoint from the evaluation seeds 100-163), fixing targets spread over
+    """Training instances: reduced LPs of every parent size class (30 to 1,000 buses) with
+    seeds 10000 + i (disjoint from the evaluation seeds 100-163), fixing targets spread over
     20-90% of u."""
+    return training_lps_range(0, count, workers)
+
+
+def training_lps_range(first: int, stop: int, workers: int = 1):
+    """Training instances first .. stop - 1 (see training_lps)."""
     if workers <= 1:
-        return [_train_lp(i) for i in range(count)]
+        return [_train_lp(i) for i in range(first, stop)]
     import multiprocessing as mp
     with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_train_lp, range(count), chunksize=16)
+        return pool.map(_train_lp, range(first, stop), chunksize=4)
 
 
-def label(lps, opts, chunk: int = 500):
+def label(lps, opts, chunk: int = 200, log=None):
     """(x*, y*) of every training LP from batched solves; LPs that do not reach the
-    tolerance are left out (returned mask)."""
+    tolerance are left out (returned mask). `log(message)` after each batch, if given."""
     from . import hprlp
     sols, ok = [], []
     for k in range(0, len(lps), chunk):
         for info, x, y, z in hprlp.batch_solve(lps[k:k + chunk], opts):
             sols.append((x, y))
             ok.append(info.term == "solved")
+        if log is not None:
+            log(f"labelled {len(sols)} of {len(lps)} training LPs")
     return sols, np.array(ok)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2510_10891_amd import hprlp, scuc
+from paper_2510_10891_amd import fixing, hprlp, scuc
 from tests.helpers import highs, rel
 
 pytestmark = pytest.mark.gpu
@@ -323,11 +323,45 @@ def test_box_only_lp_without_rows():
     assert o.iters == info.iters
 
 
-def test_infeasible_lp_is_not_reported_solved():
-    lp = scuc.LP(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.array([1.0, 1.0]),
-                 np.array([3.0]), np.array([np.inf]), np.zeros(2), np.ones(2), np.ones(2))
-    info, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=5000))
-    assert info.term != "solved"
+def _infeasible_lps():
+    """(name, LP) of LPs without a feasible point (an independent solver agrees in the CPU
+    tests of the oracle's certificate)."""
+    out = [("box_too_small", scuc.LP(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32),
+                                     np.array([1.0, 1.0]), np.array([3.0]), np.array([np.inf]), np.zeros(2),
+                                     np.ones(2), np.ones(2)))]
+    for seed in range(3):
+        rng = np.random.default_rng(seed)
+        base = scuc.random_lp(rng, 6, 5)
+        a = rng.standard_normal(5)
+        reach = np.where(a > 0, a * base.col_hi, a * base.col_lo).sum()
+        import scipy.sparse as sp
+        A = sp.vstack([base.to_scipy(), sp.csr_matrix(a[None, :])]).tocsr()
+        A.sort_indices()
+        out.append((f"random_{seed}", scuc.LP(base.m + 1, base.n, A.indptr.astype(np.int64),
+                                              A.indices.astype(np.int32), A.data.copy(),
+                                              np.r_[base.row_lo, reach + 1.0], np.r_[base.row_hi, np.inf],
+                                              base.col_lo, base.col_hi, base.c)))
+    data, lp = scuc.make_instance("small", 3)
+    G, T = data.cfg.n_gen, data.cfg.T
+    r1 = oracle.solve(lp, oracle.Options(tol=1e-6, max_iter=200000))
+    u, v, w = fixing.gather_binaries(r1.x, G, T)
+    fixed, ur, vr, wr = fixing.fixing_strategy(u, v, w, 0.1)
+    lo, hi = fixing.fix_bounds(lp, G, T, fixed, ur, vr, wr)
+    out.append(("scuc30_fixed", lp.replace(col_lo=lo, col_hi=hi)))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_infeasible_lps_are_certified_at_the_oracles_check(case):
+    """The primal infeasibility certificate fires at the same check as in the oracle (FP64),
+    and with FP32 storage after the FP64 confirmation."""
+    name, lp = _infeasible_lps()[case]
+    o = oracle.solve(lp, oracle.Options(tol=1e-6, max_iter=200000))
+    assert o.term == "primal_infeasible", name
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000))
+    assert info.term == "primal_infeasible" and info.iters == o.iters, (name, info.iters, o.iters)
+    info32, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000, precision=hprlp.HPR_FP32))
+    assert info32.term == "primal_infeasible", name
 
 
 def test_single_iteration_and_short_final_block():

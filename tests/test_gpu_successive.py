@@ -14,8 +14,8 @@ def test_rounds_fix_more_and_stay_consistent(seed):
     relaxed commitment is below tau for the whole horizon, which leaves too little capacity
     behind the line limits: the logic check of Algorithm 1 keeps eq.(status) consistent, not
     the balance and security rows (Section IV-A claims better feasibility, not a guarantee).
-    The loop must then stop at that round, and an independent solver must agree that the
-    round's LP is infeasible."""
+    The solver must certify that round's LP infeasible, the loop must stop there, and an
+    independent solver must agree."""
     data, lp = scuc.make_instance("small", seed)
     G, T = data.cfg.n_gen, data.cfg.T
     opts = hprlp.Options(tol=1e-6, max_iter=50000)
@@ -23,7 +23,7 @@ def test_rounds_fix_more_and_stay_consistent(seed):
     assert res.rounds[0].term == "solved"
     assert all(r.term == "solved" for r in res.rounds[:-1])
     if res.rounds[-1].term != "solved":
-        assert res.rounds[-1].term == "iter_limit"
+        assert res.rounds[-1].term == "primal_infeasible"
         with pytest.raises(AssertionError, match="nfeasible"):
             highs(lp.replace(col_lo=res.col_lo, col_hi=res.col_hi))
         res.rounds.pop()
