@@ -27,21 +27,89 @@ HBM_PEAK_GBS = 8000.0
 def recorded_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` measured by rocprofv3 counters
     (FETCH_SIZE + WRITE_SIZE, each scaled by the ratio a plain copy kernel of known size gives)
-    as recorded under profiles/, or None when no record exists or the kernel source has changed
-    since (the record holds the SHA-256 of the kernel source file it was taken with)."""
-    import hashlib
+    as recorded under profiles/, or None when no record exists or the kernel or schedule source
+    has changed since (the record holds the SHA-256 of kernels.hip followed by solver.hip)."""
     import re
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    src = os.path.join(ROOT, "paper_2510_10891_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    m_sha = re.search(r"kernels_sha256:\s*([0-9a-f]{64})", text)
+    sha = sources_sha256()
+    m_sha = re.search(r"sources_sha256:\s*([0-9a-f]{64})", text)
     m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_sha or not m_val or m_sha.group(1) != sha:
         return None
     return float(m_val.group(1))
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "solver.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2510_10891_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def write_traffic_record(fetch_dir, write_dir, workload="scuc-2000bus-500gen-T48"):
+    """The record recorded_traffic reads, from two rocprofv3 --pmc runs of this bench (FETCH_SIZE,
+    then WRITE_SIZE, `--max-iter 129 --precision fp32`): per-launch mean of the FP32 dual-step
+    kernel the solve used, each counter scaled by the ratio it gives for the stream probe's copy
+    kernel (1 GiB read and written per dispatch)."""
+    import csv
+    import glob
+    import re
+
+    def per_kernel(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("(anonymous namespace)::", ""))
+                    out.setdefault(name.replace("void ", "").replace("hpr::", ""), []).append(float(r["Counter_Value"]))
+        return out
+
+    f, w = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    mean = lambda v: sum(v) / len(v)
+    known = float(1 << 20)   # KiB in 1 GiB
+    cf, cw = known / mean(f["stream_copy_kernel"]), known / mean(w["stream_copy_kernel"])
+    dual = max((k for k in f if k.startswith("csr_kernel<DualOp<float>")), key=lambda k: len(f[k]))
+    if dual not in w:
+        raise SystemExit(f"{dual} is missing from the WRITE_SIZE run")
+    fk, wk = mean(f[dual]), mean(w[dual])
+    traffic = (fk * cf + wk * cw) * 1024
+    text = f"""# HBM traffic of the fused FP32 dual step on the 2,000-bus SCUC relaxation ({workload})
+
+Kernel: `{dual}`, one launch = one dual half-iteration over A~ (334,616 rows, 38,288,107 stored
+entries before padding), as scheduled by the solve of `bench.py --max-iter 129 --precision fp32`.
+
+Commands (repository root on the GPU box; each counter in a run of its own, then this record):
+
+```
+cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --max-iter 129 --precision fp32
+cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --max-iter 129 --precision fp32
+python bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write
+```
+
+Calibration: the stream probe's copy kernel reads and writes 1,048,576 KiB per dispatch; FETCH_SIZE
+reports {mean(f["stream_copy_kernel"]):,.1f} KiB for it (factor {cf:.4f}), WRITE_SIZE
+{mean(w["stream_copy_kernel"]):,.1f} KiB (factor {cw:.4f}).
+
+| counter | raw KiB per launch (mean of {len(f[dual])} / {len(w[dual])} launches) | calibrated bytes per launch |
+|---|---|---|
+| FETCH_SIZE | {fk:,.1f} | {fk * cf * 1024:,.0f} |
+| WRITE_SIZE | {wk:,.1f} | {wk * cw * 1024:,.0f} |
+
+traffic_bytes_per_launch: {traffic:.0f}
+sources_sha256: {sources_sha256()}   (SHA-256 of paper_2510_10891_amd/csrc/kernels.hip followed by solver.hip)
+
+The algorithmic bytes of a launch count 4-byte column indices (314,719,640); the kernel reads 16-bit
+offsets for every row of this matrix, so the measured traffic is below the algorithmic figure, with no
+re-reads of the matrix stream.
+"""
+    path = os.path.join(ROOT, "profiles", f"traffic_dual_step_fp32_{workload}.md")
+    with open(path, "w") as fh:
+        fh.write(text)
+    print(text)
 
 
 def log(*a):
@@ -132,8 +200,13 @@ def batch_leg(count, stream, parent="mixed"):
     del pre
     log(f"batch: {count} reduced LPs, n {min(lp.n for lp in lps)}..{max(lp.n for lp in lps)}, "
         f"nnz total {sum(lp.nnz for lp in lps)} ({time.perf_counter() - t:.1f} s)")
-    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream)
+    # the 2,000-bus batch is one long library call: a time limit bounds it (members still running
+    # then end as time_limit and are counted as unsolved)
+    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream,
+                         time_limit_s=150.0 if big else 0.0)
+    t = time.perf_counter()
     b = hprlp.hpr_batch_create(lps, opts)
+    log(f"batch engine created in {time.perf_counter() - t:.1f} s")
     if not big:
         hprlp.hpr_batch_solve(b)                 # warm-up
     torch.cuda.synchronize()
@@ -309,7 +382,12 @@ def main():
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap (lower it only for profiler runs; the line is then not a tolerance time)")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM traffic record under profiles/ from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)

@@ -394,10 +394,14 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
 
 struct DevMatrix {
     DBuf start, col, col16, rows, sched, seg, val64, val32;
+    DBuf sched_act, seg_act;                 // compacted schedule: the blocks of running LPs only
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
     std::vector<int32_t> base_h;
     std::vector<uint8_t> wide_h;
-    int32_t nrows = 0, nblocks = 0, unroll = 4, nontemporal = 0;
+    std::vector<BlockDesc> sched_h;
+    std::vector<int32_t> seg_h;
+    int32_t nrows = 0, nblocks = 0, nblocks_act = 0, unroll = 4, nontemporal = 0;
+    bool use_act = false;
     int64_t padded = 0;
     void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, bool fp32, hipStream_t st) {
         nrows = (int32_t)L.start.size() - 1;
@@ -432,7 +436,29 @@ struct DevMatrix {
         upload(sched, sc, st);
         upload(seg, sg, st);
         HIP_OK(hipStreamSynchronize(st));
+        sched_h = std::move(sc);
+        seg_h = std::move(sg);
+        use_act = false;
     }
+    // Launch only the blocks of the LPs with running[l] != 0 (each LP's blocks stay in their
+    // order, so per-block partial sums and their per-LP totals are unchanged).
+    void compact(const std::vector<int32_t>& running, hipStream_t st) {
+        const int L = (int)seg_h.size() - 1;
+        std::vector<BlockDesc> sc;
+        std::vector<int32_t> sg((size_t)L + 1, 0);
+        for (int l = 0; l < L; ++l) {
+            sg[l] = (int32_t)sc.size();
+            if (running[l]) sc.insert(sc.end(), sched_h.begin() + seg_h[l], sched_h.begin() + seg_h[l + 1]);
+        }
+        sg[L] = (int32_t)sc.size();
+        nblocks_act = (int32_t)sc.size();
+        upload(sched_act, sc, st);
+        upload(seg_act, sg, st);
+        HIP_OK(hipStreamSynchronize(st));   // sc and sg are local
+        use_act = true;
+    }
+    void full() { use_act = false; }
+    const int32_t* seg_ptr() const { return use_act ? seg_act.as<int32_t>() : seg.as<int32_t>(); }
     template <typename T>
     DevCsr<T> view() const {
         DevCsr<T> d;
@@ -440,8 +466,8 @@ struct DevMatrix {
         d.col16 = col16.as<uint16_t>();
         d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
         d.rows = rows.as<RowRef>();
-        d.sched = sched.as<BlockDesc>();
-        d.nblocks = nblocks;
+        d.sched = use_act ? sched_act.as<BlockDesc>() : sched.as<BlockDesc>();
+        d.nblocks = use_act ? nblocks_act : nblocks;
         d.unroll = unroll;
         d.nontemporal = nontemporal;
         return d;
@@ -986,8 +1012,8 @@ void enqueue_check(Engine* e, double* out) {
     const DevIter<Tv> v = e->iter<Tv>();
     launch_check_rows<Tm, Tp, Tv>(A, p, v, e->ctrl.as<Ctrl>(), e->part_r.as<double>(), e->st);
     launch_check_cols<Tm, Tp, Tv>(At, p, v, e->ctrl.as<Ctrl>(), e->part_c.as<double>(), e->st);
-    launch_finish_sums(e->part_r.as<double>(), kRowQ, A.nblocks, e->A.seg.as<int32_t>(), e->L, out, 0, e->st);
-    launch_finish_sums(e->part_c.as<double>(), kColQ, At.nblocks, e->At.seg.as<int32_t>(), e->L, out, kColOff, e->st);
+    launch_finish_sums(e->part_r.as<double>(), kRowQ, A.nblocks, e->A.seg_ptr(), e->L, out, 0, e->st);
+    launch_finish_sums(e->part_c.as<double>(), kColQ, At.nblocks, e->At.seg_ptr(), e->L, out, kColOff, e->st);
 }
 
 // One block of nb iterations, the storage-precision check, the control (phase 1) and the
@@ -1084,14 +1110,34 @@ std::vector<double> probe_first_check(Engine* e, bool use_start) {
     return r;
 }
 
+// (Re)capture the graphs of a first block (one iteration) and of a full block for the
+// schedules the matrices use now.
+template <typename T>
+void build_graphs(Engine* e) {
+    e->drop_graphs();
+    e->g_first = capture_block<T>(e, 1);
+    e->g_block = capture_block<T>(e, e->opts.check_every);
+    e->graphs_built = true;
+}
+
+// Batches: when the running LPs have halved since the last change, later blocks launch only
+// their thread blocks (the finished LPs' blocks would return at once, but a launch over all of
+// them costs dispatch time for every iteration the slowest LP still needs).
+template <typename T>
+void compact_schedules(Engine* e) {
+    HIP_OK(hipMemcpyAsync(e->ctrl_h.data(), e->ctrl.p, sizeof(Ctrl) * e->L, hipMemcpyDeviceToHost, e->st));
+    e->sync();
+    std::vector<int32_t> running(e->L);
+    for (int l = 0; l < e->L; ++l) running[l] = e->ctrl_h[l].active;
+    e->A.compact(running, e->st);
+    e->At.compact(running, e->st);
+    if (e->opts.use_graph) build_graphs<T>(e);
+}
+
 template <typename T>
 void solve_loop(Engine* e, double t0) {
     const hpr_opts& o = e->opts;
-    if (o.use_graph && !e->graphs_built) {
-        e->g_first = capture_block<T>(e, 1);
-        e->g_block = capture_block<T>(e, o.check_every);
-        e->graphs_built = true;
-    }
+    if (o.use_graph && !e->graphs_built) build_graphs<T>(e);
     // Warm starts fall back to the cold start (zero) for every LP whose first check from the
     // warm point is not finite or worse than warm_fallback_ratio times the first check from zero.
     e->warm_used.assign(e->L, 0);
@@ -1116,6 +1162,7 @@ void solve_loop(Engine* e, double t0) {
     if (o.profile && !e->ev[0])
         for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
     int64_t it = 0, blocks = 0;
+    int32_t launched = e->L;   // LPs whose blocks the current schedules launch
     while (true) {
         const int nb = (int)((it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it));
         const bool sample = o.profile && nb >= 2 && (blocks % 4 == 1);
@@ -1145,6 +1192,15 @@ void solve_loop(Engine* e, double t0) {
             running = read_stat(e, 0);
         }
         if (running == 0 || it >= o.max_iter) break;
+        if (e->L > 1 && 2 * running <= launched) {
+            compact_schedules<T>(e);
+            launched = running;
+        }
+    }
+    if (e->A.use_act || e->At.use_act) {   // the report and the solution cover every LP
+        e->A.full();
+        e->At.full();
+        e->drop_graphs();                  // captured for the compacted schedules
     }
     if (e->fp32) {
         // report the residuals of the returned points in FP64
