@@ -72,15 +72,21 @@ def write_traffic_record(fetch_dir, write_dir, workload="scuc-2000bus-500gen-T48
     mean = lambda v: sum(v) / len(v)
     known = float(1 << 20)   # KiB in 1 GiB
     cf, cw = known / mean(f["stream_copy_kernel"]), known / mean(w["stream_copy_kernel"])
-    dual = max((k for k in f if k.startswith("csr_kernel<DualOp<float>")), key=lambda k: len(f[k]))
-    if dual not in w:
-        raise SystemExit(f"{dual} is missing from the WRITE_SIZE run")
+    # the variant the solve used (most launches); the schedule tuner is timing-based and may pick
+    # another one in the other run, but it always times U = 1, 2, 4 with ordinary loads, so the
+    # record takes the ordinary-load variant with the solve's U from both runs (the variants move
+    # the same bytes: one pass over the matrix per launch)
+    used = max((k for k in f if k.startswith("csr_kernel<DualOp<float>")), key=lambda k: len(f[k]))
+    dual = re.sub(r", (true|false)>$", ", false>", used)
+    if dual not in f or dual not in w:
+        raise SystemExit(f"{dual} is missing from a counter run")
     fk, wk = mean(f[dual]), mean(w[dual])
     traffic = (fk * cf + wk * cw) * 1024
     text = f"""# HBM traffic of the fused FP32 dual step on the 2,000-bus SCUC relaxation ({workload})
 
-Kernel: `{dual}`, one launch = one dual half-iteration over A~ (334,616 rows, 38,288,107 stored
-entries before padding), as scheduled by the solve of `bench.py --max-iter 129 --precision fp32`.
+Kernel: `{dual}` (the solve of `bench.py --max-iter 129 --precision fp32` in the FETCH run used
+`{used}`), one launch = one dual half-iteration over A~ (334,616 rows, 38,288,107 stored entries
+before padding).
 
 Commands (repository root on the GPU box; each counter in a run of its own, then this record):
 
