@@ -171,7 +171,9 @@ def make_reduced_batch(count: int = 64, seed0: int = 100, classes: int | None = 
                 log(f"reduced LP {len(out)}/{count}: parent {j[0].name} seed {j[1]} nnz {out[-1].lp.nnz}")
         return out
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(workers) as pool:
+    # fresh interpreters: the caller may already hold a GPU context, which a forked child
+    # would inherit
+    with mp.get_context("spawn").Pool(workers) as pool:
         out = []
         for r in pool.imap(_batch_member, jobs):
             out.append(r)
