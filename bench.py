@@ -331,25 +331,33 @@ def warmstart_leg(n_train, n_eval, stream):
     return out
 
 
-def ablation_leg(data, rounds, stream):
+def ablation_leg(data, rounds, stream, formulation="compact"):
     """LP-side analogue of the paper's ablation (Section V): successive fixing with `rounds`
     rounds on the bench instance under three solver configurations, LP time only (creation
     with scaling and lambda, plus the rounds' solves). SF(FOM): Ruiz (10 passes) + Pock-
     Chambolle + b/c normalisation, no instance-aware scaling, FP64. SF(FOM+FP32): the same
-    with FP32 storage. SF: instance-aware scaling (Section III-A), Ruiz off, FP32."""
+    with FP32 storage. SF: instance-aware scaling (Section III-A), Ruiz off, FP32. A fourth run,
+    not in the paper, keeps Ruiz and instance-aware scaling off (FP32): what the instance-aware
+    scaling buys when it replaces Ruiz. On the full formulation every LP is first presolved
+    (cost variables substituted). Each solve is bounded by 150 s."""
     import torch
 
     from paper_2510_10891_amd import hprlp, scuc, successive
 
     full = hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_RUIZ | hprlp.HPR_SCALE_BC
     runs = [("SF(FOM)", False, full, hprlp.HPR_FP64), ("SF(FOM+FP32)", False, full, hprlp.HPR_FP32),
-            ("SF", True, hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_BC, hprlp.HPR_FP32)]
+            ("SF", True, hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_BC, hprlp.HPR_FP32),
+            ("PC only (FP32)", False, hprlp.HPR_SCALE_PC | hprlp.HPR_SCALE_BC, hprlp.HPR_FP32)]
     out = []
     for name, inst, scaling, prec in runs:
-        lp = scuc.build_lp(data, instance_scaling=inst)
+        if formulation == "full":
+            from paper_2510_10891_amd import fixing
+            lp = fixing.presolve_free_singletons(scuc.build_full_lp(data, instance_scaling=inst)).lp
+        else:
+            lp = scuc.build_lp(data, instance_scaling=inst)
         eta_c = lp.meta["eta_c"]
         opts = hprlp.Options(tol=1e-4, precision=prec, scaling=scaling, ruiz_iters=10, max_iter=200000,
-                             stream=stream)
+                             stream=stream, time_limit_s=150.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = successive.run(data, lp, rounds=rounds, tau=0.1, opts=opts)
@@ -372,6 +380,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="medium")
+    ap.add_argument("--formulation", choices=["compact", "full"], default="compact",
+                    help="SCUC model: u, v, w, p per unit-hour, or the full one with cost segments, "
+                         "no-load cost and unserved demand")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-limit", type=float, default=40.0,
                     help="wall-time bound (s) of the oracle solve in the cpu_baseline leg")
@@ -388,6 +399,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap (lower it only for profiler runs; the line is then not a tolerance time)")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="wall-time bound (s) of each timed solve (0: none); a solve that hits it "
+                         "ends as time_limit and the line reports all_solved false")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM traffic record under profiles/ from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -409,15 +423,28 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
 
     t = time.perf_counter()
-    data, lp = scuc.make_instance(args.config, args.seed)
-    log(f"instance {data.cfg.name}: m={lp.m} n={lp.n} nnz={lp.nnz} ({time.perf_counter() - t:.1f} s)")
+    data, lp = scuc.make_instance(args.config, args.seed, formulation=args.formulation)
+    workload = data.cfg.name + ("-full" if args.formulation == "full" else "")
+    log(f"instance {workload}: m={lp.m} n={lp.n} nnz={lp.nnz} ({time.perf_counter() - t:.1f} s)")
+    presolve = None
+    if args.formulation == "full":
+        from paper_2510_10891_amd import fixing
+        t = time.perf_counter()
+        sub = fixing.presolve_free_singletons(lp)
+        presolve = dict(step="implied-free column singletons substituted (cost variables)",
+                        removed_cols=int(len(sub.sub_c)), removed_rows=int(len(sub.sub_r)),
+                        host_s=round(time.perf_counter() - t, 2), m=lp.m, n=lp.n, nnz=lp.nnz)
+        lp = sub.lp
+        del sub
+        log(f"presolve: {presolve}; reduced m={lp.m} n={lp.n} nnz={lp.nnz}")
 
     res = {}
     legs = [("fp32", hprlp.HPR_FP32), ("fp64", hprlp.HPR_FP64)]
     if args.precision != "both":
         legs = [l for l in legs if l[0] == args.precision]
     for name, prec in legs:
-        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=args.max_iter, profile=1, stream=stream)
+        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=args.max_iter, profile=1, stream=stream,
+                             time_limit_s=args.time_limit)
         h = hprlp.hpr_create(lp, opts)
         infos, sec = run_solves(hprlp, h, args.steps, args.warmup, torch)
         ks = hprlp.hpr_get_kernel_stats(h)
@@ -444,7 +471,7 @@ def main():
         kname, kbytes, kms = "primal_step_fp32", pb, ks["primal_ms"]
     achieved = kbytes / (kms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, data.cfg.name),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
                 schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
@@ -463,7 +490,7 @@ def main():
                    objective=x.objective, fixed_u=round(x.fixed_u, 4), newly_fixed=x.newly_fixed) for x in r.rounds]
         log(f"successive fixing: {sf}")
 
-    abl = ablation_leg(data, args.ablation, stream) if args.ablation > 0 else None
+    abl = ablation_leg(data, args.ablation, stream, args.formulation) if args.ablation > 0 else None
 
     cpu = None
     if not args.no_cpu:
@@ -485,8 +512,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 storage, f64 reductions",
         "data": "synthetic",
-        "config": {"workload": data.cfg.name, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "tol": 1e-4,
-                   "seed": args.seed},
+        "config": {"workload": workload, "m": lp.m, "n": lp.n, "nnz": lp.nnz, "tol": 1e-4,
+                   "seed": args.seed, **({"presolve": presolve} if presolve else {})},
         "iters": f32["info"].iters,
         "iters_per_s": round(f32["info"].iters / f32["sec"], 1),
         "setup_s": round(f32["info"].setup_s, 3),

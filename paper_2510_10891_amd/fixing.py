@@ -1,5 +1,6 @@
 """Successive fixing around the LP solver (Section IV): Round, the logic-driven
-Fixing-Strategy of Algorithm 1, a minimal LP presolve, and the batch of reduced LPs that
+Fixing-Strategy of Algorithm 1, a minimal LP presolve (fixed columns, implied-free column
+singletons), and the batch of reduced LPs that
 successive-fixing rounds hand to the solver.
 
 Host-side support code: it decides which binaries are fixed and rewrites the LP; it holds
@@ -104,6 +105,96 @@ def lift(pre: Presolved, x_red):
     x = pre.x_fixed.copy()
     x[pre.cols] = x_red
     return x
+
+
+@dataclass
+class Substituted:
+    lp: LP                 # the reduced LP
+    cols: np.ndarray       # kept original columns
+    rows: np.ndarray       # kept original rows
+    sub_c: np.ndarray      # substituted columns j ...
+    sub_r: np.ndarray      # ... each defined by its equality row i
+    orig: LP               # the LP before the substitution
+
+
+def presolve_free_singletons(lp: LP, tol: float = 1e-9) -> Substituted:
+    """LP presolve of implied-free column singletons: a column j whose only entry a_ij lies in
+    an equality row i (sum_k a_ik x_k = b_i), and whose bounds are implied by that row and the
+    bounds of the row's other columns, is substituted out, x_j = (b_i - sum_{k != j} a_ik x_k) / a_ij:
+    its cost moves onto the row's other columns (c_k -= c_j a_ik / a_ij, offset += c_j b_i / a_ij)
+    and row i and column j are dropped. At most one column per row. On SCUC models this removes
+    cost variables defined by an equality (c_gt = sum_h C_gh p_gth), through which alone the
+    objective would otherwise reach the segment outputs."""
+    A = lp.to_scipy()
+    cols = A.indices
+    eq = (lp.row_lo == lp.row_hi) & np.isfinite(lp.row_lo)
+    # singleton columns (one stored entry) in equality rows, the first one per row
+    cnt = np.bincount(cols, minlength=lp.n)
+    pos = np.nonzero(cnt[cols] == 1)[0]
+    i_s = np.searchsorted(A.indptr, pos, side="right") - 1
+    single, a_s = cols[pos], A.data[pos]
+    ok = eq[i_s] & (a_s != 0.0)
+    pos, i_s, single, a_s = pos[ok], i_s[ok], single[ok], a_s[ok]
+    _, first = np.unique(i_s, return_index=True)
+    pos, i_s, single, a_s = pos[first], i_s[first], single[first], a_s[first]
+    # range of sum_{k != j} a_ik x_k over the column bounds (infinite where a term is unbounded)
+    rest_lo, rest_hi = np.empty(len(i_s)), np.empty(len(i_s))
+    for q, i in enumerate(i_s):
+        seg = slice(A.indptr[i], A.indptr[i + 1])
+        v, cc = A.data[seg], cols[seg]
+        own = np.arange(seg.start, seg.stop) == pos[q]
+        v, cc = v[~own], cc[~own]
+        with np.errstate(invalid="ignore"):
+            lo_t = np.where(v > 0, v * lp.col_lo[cc], v * lp.col_hi[cc])
+            hi_t = np.where(v > 0, v * lp.col_hi[cc], v * lp.col_lo[cc])
+        rest_lo[q] = -np.inf if np.any(~np.isfinite(lo_t)) else lo_t.sum()
+        rest_hi[q] = np.inf if np.any(~np.isfinite(hi_t)) else hi_t.sum()
+    b = lp.row_lo[i_s]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        lo_j = np.where(a_s > 0, (b - rest_hi) / a_s, (b - rest_lo) / a_s)
+        hi_j = np.where(a_s > 0, (b - rest_lo) / a_s, (b - rest_hi) / a_s)
+    l, u = lp.col_lo[single], lp.col_hi[single]
+    ok_lo = ~np.isfinite(l) | (lo_j >= l - tol * (1 + np.abs(l)))
+    ok_hi = ~np.isfinite(u) | (hi_j <= u + tol * (1 + np.abs(u)))
+    take = ok_lo & ok_hi
+    sub_c, sub_r, a_sub = single[take].astype(np.int64), i_s[take].astype(np.int64), a_s[take]
+    order = np.argsort(sub_c)
+    sub_c, sub_r, a_sub = sub_c[order], sub_r[order], a_sub[order]
+    if len(sub_c):
+        f = lp.c[sub_c] / a_sub              # y_i of each dropped row
+        c = lp.c - A[sub_r].T @ f
+        offset = float(lp.obj_offset + f @ lp.row_lo[sub_r])
+    else:
+        c, offset = lp.c.copy(), float(lp.obj_offset)
+    keep_c = np.setdiff1d(np.arange(lp.n), sub_c)
+    keep_r = np.setdiff1d(np.arange(lp.m), sub_r)
+    Ak = A[keep_r][:, keep_c].tocsr()
+    Ak.sort_indices()
+    red = LP(len(keep_r), len(keep_c), Ak.indptr.astype(np.int64), Ak.indices.astype(np.int32),
+             Ak.data.astype(np.float64), lp.row_lo[keep_r], lp.row_hi[keep_r], lp.col_lo[keep_c],
+             lp.col_hi[keep_c], c[keep_c], offset, dict(lp.meta))
+    return Substituted(red, keep_c, keep_r, sub_c, sub_r, lp)
+
+
+def postsolve_free_singletons(s: Substituted, x_red, y_red, z_red):
+    """(x, y, z) of the original LP from a reduced solution: x_j from its defining row,
+    y_i = c_j / a_ij for the dropped row (column j's reduced cost is 0, it is free), the
+    other multipliers and reduced costs as computed on the reduced LP."""
+    lp = s.orig
+    A = lp.to_scipy()
+    x = np.zeros(lp.n)
+    x[s.cols] = x_red
+    y = np.zeros(lp.m)
+    y[s.rows] = y_red
+    z = np.zeros(lp.n)
+    z[s.cols] = z_red
+    if len(s.sub_c) == 0:
+        return x, y, z
+    a = np.asarray(A[s.sub_r, s.sub_c]).ravel()
+    rest = A[s.sub_r] @ x            # x_j is still 0 and appears in no other dropped row
+    x[s.sub_c] = (lp.row_lo[s.sub_r] - rest) / a
+    y[s.sub_r] = lp.c[s.sub_c] / a
+    return x, y, z
 
 
 # ----------------------------------------------------------------------------- the reduced batch

@@ -179,6 +179,8 @@ class SCUCData:
     sec_const: np.ndarray     # [S] sum_b delta_lb * share_b (multiplied by D_t per hour)
     sec_limit: np.ndarray     # [S] F_l^c
     sec_label: np.ndarray     # [S, 2] (monitored line, outage line or -1)
+    seed: int = 0
+    sec_bus: sp.csr_matrix | None = None   # [S, n_bus] bus-level coefficients (full formulation)
 
 
 def _draw_generators(rng, cfg: SCUCConfig):
@@ -192,8 +194,10 @@ def _draw_generators(rng, cfg: SCUCConfig):
     return gen_bus, p_max, cost, startup_cost, min_up, min_down
 
 
-def make_scuc_data(cfg: SCUCConfig, seed: int) -> SCUCData:
+def make_scuc_data(cfg: SCUCConfig, seed: int, bus_rows: bool = False) -> SCUCData:
     """Draw the network, generators, demand and the security rows of one instance.
+    With ``bus_rows`` the bus-level coefficients of the kept security rows are stored as
+    well (the full formulation puts the demand-penalty slack of every bus in them).
 
     Readings of details the recipe leaves open:
       * min production 0.3 p_max, ramp 0.5 p_max per hour, start-up and shut-down
@@ -235,7 +239,7 @@ def make_scuc_data(cfg: SCUCConfig, seed: int) -> SCUCData:
 
     G = cfg.n_gen
     P_total = p_max.sum()
-    coef_blocks, const_blocks, label_blocks, q_blocks = [], [], [], []
+    coef_blocks, const_blocks, label_blocks, q_blocks, bus_blocks = [], [], [], [], []
     chunk = 256
     drop = max(cfg.ptdf_drop, 1e-10)   # entries that are zero in exact arithmetic come out as ~1e-17
 
@@ -249,6 +253,8 @@ def make_scuc_data(cfg: SCUCConfig, seed: int) -> SCUCData:
         const_blocks.append(const[keep])
         label_blocks.append(lab[keep])
         q_blocks.append(q[keep])
+        if bus_rows:
+            bus_blocks.append(sp.csr_matrix(D[keep]))
 
     for s0 in range(0, len(monitored), chunk):
         mon = monitored[s0:s0 + chunk]
@@ -274,8 +280,11 @@ def make_scuc_data(cfg: SCUCConfig, seed: int) -> SCUCData:
     p_min = 0.3 * p_max
     ramp = 0.5 * p_max
     su = np.maximum(p_min, ramp)
+    sec_bus = None
+    if bus_rows:
+        sec_bus = sp.vstack(bus_blocks, format="csr") if bus_blocks else sp.csr_matrix((0, cfg.n_bus))
     return SCUCData(cfg, gen_bus, p_max, p_min, ramp, su, cost, startup_cost, min_up, min_down,
-                    demand, share, sec_coef, sec_const, F, sec_label)
+                    demand, share, sec_coef, sec_const, F, sec_label, seed, sec_bus)
 
 
 def col_index(G: int, t: int | np.ndarray, var: int, g: int | np.ndarray):
@@ -289,6 +298,50 @@ def _csr_from_coo(nrows, r, cidx, v):
     ptr = np.zeros(nrows + 1, np.int64)
     np.cumsum(np.bincount(r, minlength=nrows), out=ptr[1:])
     return ptr, cidx.astype(np.int32), v.astype(np.float64)
+
+
+def _status_rows(add, data: SCUCData, t: int, nrow: int, lo, hi, kind, KIND) -> int:
+    """Rows of hour t on the commitment variables only, appended from local row `nrow` on:
+    logic u_t - u_{t-1} - v_t + w_t = 0 (u_0 = 1 moves to the rhs at t = 1) and
+    v_t + w_t <= 1 (eq.(status)), minimum up sum_{tau=max(1,t-UT+1)}^{t} v_tau - u_t <= 0 and
+    minimum down sum w_tau + u_t <= 1 (eq.(minup/down)). Returns the next free local row."""
+    G = data.cfg.n_gen
+    g = np.arange(G)
+    inf = np.inf
+    # logic
+    rr = nrow + g
+    add(rr, col_index(G, t, U, g), np.ones(G))
+    add(rr, col_index(G, t, V, g), -np.ones(G))
+    add(rr, col_index(G, t, W, g), np.ones(G))
+    if t >= 1:
+        add(rr, col_index(G, t - 1, U, g), -np.ones(G))
+        rhs = np.zeros(G)
+    else:
+        rhs = np.ones(G)
+    lo.append(rhs); hi.append(rhs.copy()); kind.append(np.full(G, KIND["logic"]))
+    nrow += G
+    # v_t + w_t <= 1
+    rr = nrow + g
+    add(rr, col_index(G, t, V, g), np.ones(G))
+    add(rr, col_index(G, t, W, g), np.ones(G))
+    lo.append(np.full(G, -inf)); hi.append(np.ones(G)); kind.append(np.full(G, KIND["vw"]))
+    nrow += G
+    # min up
+    rr = nrow + g
+    add(rr, col_index(G, t, U, g), -np.ones(G))
+    for d in range(int(data.min_up.max())):
+        sel = (d < data.min_up) & (t - d >= 0)
+        add(rr[sel], col_index(G, t - d, V, g[sel]), np.ones(int(sel.sum())))
+    lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["min_up"]))
+    nrow += G
+    # min down
+    rr = nrow + g
+    add(rr, col_index(G, t, U, g), np.ones(G))
+    for d in range(int(data.min_down.max())):
+        sel = (d < data.min_down) & (t - d >= 0)
+        add(rr[sel], col_index(G, t - d, W, g[sel]), np.ones(int(sel.sum())))
+    lo.append(np.full(G, -inf)); hi.append(np.ones(G)); kind.append(np.full(G, KIND["min_dn"]))
+    return nrow + G
 
 
 def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
@@ -386,40 +439,7 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
             add(rr, col_index(G, t, W, g), -su)
             lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["ramp_dn"]))
             nrow += G
-        # logic: u_t - u_{t-1} - v_t + w_t = 0   (u_0 = 1 moves to the rhs at t = 1)
-        rr = nrow + g
-        add(rr, col_index(G, t, U, g), np.ones(G))
-        add(rr, col_index(G, t, V, g), -np.ones(G))
-        add(rr, col_index(G, t, W, g), np.ones(G))
-        if t >= 1:
-            add(rr, col_index(G, t - 1, U, g), -np.ones(G))
-            rhs = np.zeros(G)
-        else:
-            rhs = np.ones(G)
-        lo.append(rhs); hi.append(rhs.copy()); kind.append(np.full(G, KIND["logic"]))
-        nrow += G
-        # v_t + w_t <= 1
-        rr = nrow + g
-        add(rr, col_index(G, t, V, g), np.ones(G))
-        add(rr, col_index(G, t, W, g), np.ones(G))
-        lo.append(np.full(G, -inf)); hi.append(np.ones(G)); kind.append(np.full(G, KIND["vw"]))
-        nrow += G
-        # min up: sum_{tau=max(1,t-UT+1)}^{t} v_tau - u_t <= 0
-        rr = nrow + g
-        add(rr, col_index(G, t, U, g), -np.ones(G))
-        for d in range(int(data.min_up.max())):
-            sel = (d < data.min_up) & (t - d >= 0)
-            add(rr[sel], col_index(G, t - d, V, g[sel]), np.ones(int(sel.sum())))
-        lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["min_up"]))
-        nrow += G
-        # min down: sum_{tau=max(1,t-DT+1)}^{t} w_tau + u_t <= 1
-        rr = nrow + g
-        add(rr, col_index(G, t, U, g), np.ones(G))
-        for d in range(int(data.min_down.max())):
-            sel = (d < data.min_down) & (t - d >= 0)
-            add(rr[sel], col_index(G, t - d, W, g[sel]), np.ones(int(sel.sum())))
-        lo.append(np.full(G, -inf)); hi.append(np.ones(G)); kind.append(np.full(G, KIND["min_dn"]))
-        nrow += G
+        nrow = _status_rows(add, data, t, nrow, lo, hi, kind, KIND)
 
         bptr, bcol, bval = _csr_from_coo(nrow, np.concatenate(r_list), np.concatenate(c_list),
                                          np.concatenate(v_list))
@@ -457,6 +477,244 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
     return LP(len(lens), n, row_ptr, col_idx, val, row_lo, row_hi, col_lo, col_hi, c, 0.0, meta)
 
 
+# ----------------------------------------------------------------------------- full formulation
+
+# Unserved-demand penalty C^pen ($/MWh): well above every marginal cost of the recipe.
+PEN_COST = 1000.0
+
+
+def full_col_index(G: int, H: int, t: int | np.ndarray, slot: int, g: int | np.ndarray, T: int):
+    """Column of an extra generator variable of the full formulation: slot 0 = p' (output
+    above minimum), 1..H = segment outputs p_{gth}, H + 1 = production cost c_{gt}. The extras
+    follow the 4 G T columns of the compact layout, which keep their positions, hour-major as
+    [t][p', p_1..p_H, c][g]."""
+    return 4 * G * T + (np.asarray(t) * (H + 2) + slot) * G + np.asarray(g)
+
+
+def pen_col_index(G: int, H: int, T: int, n_bus: int, t: int | np.ndarray, b: int | np.ndarray):
+    """Column of the unserved demand d^pen of bus b in hour t (after every generator column)."""
+    return 4 * G * T + T * (H + 2) * G + np.asarray(t) * n_bus + np.asarray(b)
+
+
+def segment_data(data: SCUCData, H: int):
+    """Piecewise-linear production cost of eq.(prod_cost) (recipe readings): H segments of
+    equal width splitting [P^L, P^U]; the first priced at the unit's cost, each next one dearer
+    by a seeded factor U[1.05, 1.3] (a convex cost curve); no-load cost C^L = cost * P^L, the
+    cost of running at P^L at the first segment's rate. Returns (width [G, H] MW,
+    cost [G, H] $/MWh, no-load cost [G] $/h)."""
+    rng = np.random.default_rng([data.seed, 1])
+    G = data.cfg.n_gen
+    width = np.repeat(((data.p_max - data.p_min) / H)[:, None], H, 1)
+    steps = rng.uniform(1.05, 1.3, size=(G, H - 1))
+    cost = data.cost[:, None] * np.concatenate([np.ones((G, 1)), np.cumprod(steps, 1)], 1)
+    return width, cost, data.cost * data.p_min
+
+
+def build_full_lp(data: SCUCData, instance_scaling: bool = True, segments: int = 3,
+                  pen_cost: float = PEN_COST) -> LP:
+    """The LP relaxation of the full model of Section II: output above minimum p', piecewise
+    cost segments and cost variables (eq.(prod_cost)), no-load cost C^L u and unserved demand
+    d^pen with penalty C^pen in the balance and security rows (eq.(security), eq.(obj)).
+
+    The generator output p_gt of the balance and security rows is kept as a column, tied to
+    the rest by p - p' - P^L u = 0 (so the security rows keep their PTDF coefficients);
+    production limits, ramping (written in p' and u as in eq.(ramp up/down)) and the cost rows
+    carry the capacity and cost parameters. Rows of hour t, in order: balance; security; per
+    generator: definition of p, p' - (P^U - P^L) u <= 0, ramp up / down (t >= 2), H segment
+    limits p_h - (P^U_h - P^U_{h-1}) u <= 0, sum_h p_h - p' = 0, sum_h C_h p_h - c = 0, then the
+    commitment rows of the compact form. Start-up costs stay on v as in the compact form.
+    Instance-aware scaling divides production data by eta^P = max P^U and multiplies costs by
+    eta^P / eta^C with eta^C = the largest segment cost (Section III-A).
+    """
+    cfg = data.cfg
+    G, T, B, H = cfg.n_gen, cfg.T, cfg.n_bus, segments
+    S = data.sec_coef.shape[0]
+    if S and data.sec_bus is None:
+        raise ValueError("the full formulation needs the bus-level security rows "
+                         "(make_scuc_data(..., bus_rows=True))")
+    width, seg_cost, noload = segment_data(data, H)
+    if instance_scaling:
+        eta_p = float(data.p_max.max())
+        eta_c = float(seg_cost.max())
+    else:
+        eta_p = eta_c = 1.0
+    pmin = data.p_min / eta_p
+    pmax = data.p_max / eta_p
+    ru = data.ramp / eta_p
+    su = data.startup_cap / eta_p
+    wd = width / eta_p
+    cs = seg_cost * eta_p / eta_c
+    dem = data.demand / eta_p
+    F = data.sec_limit / eta_p
+    n = 4 * G * T + T * (H + 2) * G + T * B
+    g = np.arange(G)
+    bus = np.arange(B)
+
+    # security rows over [generators | buses], hour-invariant
+    sec = sp.hstack([sp.csr_matrix(data.sec_coef), data.sec_bus if S else sp.csr_matrix((0, B))],
+                    format="csr")
+    sec.sort_indices()
+    sec_is_gen = sec.indices < G
+
+    ptr_parts, col_parts, val_parts, lo_parts, hi_parts = [], [], [], [], []
+    row_kind_parts, row_hour_parts, row_sec_parts = [], [], []
+    KIND = {"balance": 0, "security": 1, "lim_lo": 2, "lim_hi": 3, "ramp_up": 4,
+            "ramp_dn": 5, "logic": 6, "vw": 7, "min_up": 8, "min_dn": 9,
+            "define_p": 10, "segment": 11, "segment_sum": 12, "cost_def": 13}
+    inf = np.inf
+    for t in range(T):
+        # balance: sum_g p + sum_b d^pen = D_t
+        ptr_parts.append(np.array([G + B], np.int64))
+        col_parts.append(np.concatenate([col_index(G, t, P, g), pen_col_index(G, H, T, B, t, bus)]))
+        val_parts.append(np.ones(G + B))
+        lo_parts.append(np.array([dem[t]]))
+        hi_parts.append(np.array([dem[t]]))
+        row_kind_parts.append(np.array([KIND["balance"]], np.int8))
+        row_sec_parts.append(np.array([-1], np.int32))
+        if S:
+            # sum_b delta_lb (sum_{g at b} p_g + d^pen_b) within D-dependent mid +- F
+            ptr_parts.append(np.diff(sec.indptr).astype(np.int64))
+            col_parts.append(np.where(sec_is_gen, col_index(G, t, P, np.minimum(sec.indices, G - 1)),
+                                      pen_col_index(G, H, T, B, t, sec.indices - G)))
+            val_parts.append(sec.data.copy())
+            mid = data.sec_const * data.demand[t] / eta_p
+            lo_parts.append(mid - F)
+            hi_parts.append(mid + F)
+            row_kind_parts.append(np.full(S, KIND["security"], np.int8))
+            row_sec_parts.append(np.arange(S, dtype=np.int32))
+        r_list, c_list, v_list, lo, hi, kind = [], [], [], [], [], []
+        nrow = 0
+
+        def add(rows_local, cols, vals):
+            r_list.append(rows_local)
+            c_list.append(cols)
+            v_list.append(vals)
+
+        def pp(tt, slot):
+            return full_col_index(G, H, tt, slot, g, T)
+
+        # p - p' - P^L u = 0
+        rr = nrow + g
+        add(rr, col_index(G, t, P, g), np.ones(G))
+        add(rr, pp(t, 0), -np.ones(G))
+        add(rr, col_index(G, t, U, g), -pmin)
+        lo.append(np.zeros(G)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["define_p"]))
+        nrow += G
+        # p' - (P^U - P^L) u <= 0
+        rr = nrow + g
+        add(rr, pp(t, 0), np.ones(G))
+        add(rr, col_index(G, t, U, g), -(pmax - pmin))
+        lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["lim_hi"]))
+        nrow += G
+        if t >= 1:
+            # (p'_t + P^L u_t) - (p'_{t-1} + P^L u_{t-1}) - RU u_{t-1} - SU v_t <= 0
+            rr = nrow + g
+            add(rr, pp(t, 0), np.ones(G))
+            add(rr, col_index(G, t, U, g), pmin)
+            add(rr, pp(t - 1, 0), -np.ones(G))
+            add(rr, col_index(G, t - 1, U, g), -(pmin + ru))
+            add(rr, col_index(G, t, V, g), -su)
+            lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["ramp_up"]))
+            nrow += G
+            # (p'_{t-1} + P^L u_{t-1}) - (p'_t + P^L u_t) - RD u_t - SD w_t <= 0
+            rr = nrow + g
+            add(rr, pp(t - 1, 0), np.ones(G))
+            add(rr, col_index(G, t - 1, U, g), pmin)
+            add(rr, pp(t, 0), -np.ones(G))
+            add(rr, col_index(G, t, U, g), -(pmin + ru))
+            add(rr, col_index(G, t, W, g), -su)
+            lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["ramp_dn"]))
+            nrow += G
+        # p_h - (P^U_h - P^U_{h-1}) u <= 0
+        for h in range(H):
+            rr = nrow + g
+            add(rr, pp(t, 1 + h), np.ones(G))
+            add(rr, col_index(G, t, U, g), -wd[:, h])
+            lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["segment"]))
+            nrow += G
+        # sum_h p_h - p' = 0
+        rr = nrow + g
+        add(rr, pp(t, 0), -np.ones(G))
+        for h in range(H):
+            add(rr, pp(t, 1 + h), np.ones(G))
+        lo.append(np.zeros(G)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["segment_sum"]))
+        nrow += G
+        # sum_h C_h p_h - c = 0
+        rr = nrow + g
+        for h in range(H):
+            add(rr, pp(t, 1 + h), cs[:, h])
+        add(rr, pp(t, H + 1), -np.ones(G))
+        lo.append(np.zeros(G)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["cost_def"]))
+        nrow += G
+        nrow = _status_rows(add, data, t, nrow, lo, hi, kind, KIND)
+
+        bptr, bcol, bval = _csr_from_coo(nrow, np.concatenate(r_list), np.concatenate(c_list),
+                                         np.concatenate(v_list))
+        ptr_parts.append(np.diff(bptr))
+        col_parts.append(bcol)
+        val_parts.append(bval)
+        lo_parts.append(np.concatenate(lo))
+        hi_parts.append(np.concatenate(hi))
+        row_kind_parts.append(np.concatenate(kind).astype(np.int8))
+        row_sec_parts.append(np.full(nrow, -1, np.int32))
+        row_hour_parts.append(np.full(1 + S + nrow, t, np.int16))
+
+    lens = np.concatenate(ptr_parts)
+    row_ptr = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    col_idx = np.concatenate(col_parts).astype(np.int32)
+    val = np.concatenate(val_parts).astype(np.float64)
+
+    tt = np.arange(T)[:, None]
+    gg = g[None, :]
+    col_lo = np.zeros(n)
+    col_hi = np.ones(n)
+    col_hi[col_index(G, tt, P, gg).ravel()] = np.tile(pmax, T)
+    col_hi[full_col_index(G, H, tt, 0, gg, T).ravel()] = np.tile(pmax - pmin, T)
+    for h in range(H):
+        col_hi[full_col_index(G, H, tt, 1 + h, gg, T).ravel()] = np.tile(wd[:, h], T)
+    col_hi[full_col_index(G, H, tt, H + 1, gg, T).ravel()] = np.tile((cs * wd).sum(1), T)
+    col_hi[pen_col_index(G, H, T, B, tt, bus[None, :]).ravel()] = (dem[:, None] * data.bus_share[None, :]).ravel()
+    c = np.zeros(n)
+    c[full_col_index(G, H, tt, H + 1, gg, T).ravel()] = 1.0
+    c[col_index(G, tt, U, gg).ravel()] = np.tile(noload / eta_c, T)
+    c[col_index(G, tt, V, gg).ravel()] = np.tile(data.startup_cost / eta_c, T)
+    c[pen_col_index(G, H, T, B, tt, bus[None, :]).ravel()] = pen_cost * eta_p / eta_c
+
+    meta = dict(config=cfg, G=G, T=T, eta_p=eta_p, eta_c=eta_c, formulation="full", segments=H,
+                n_bus=B, pen_cost=pen_cost,
+                row_kind=np.concatenate(row_kind_parts), row_kinds=KIND,
+                row_hour=np.concatenate(row_hour_parts), row_sec=np.concatenate(row_sec_parts))
+    return LP(len(lens), n, row_ptr, col_idx, val, np.concatenate(lo_parts), np.concatenate(hi_parts),
+              col_lo, col_hi, c, 0.0, meta)
+
+
+def feasible_point_full(data: SCUCData, lp: LP) -> np.ndarray:
+    """The all-units-on dispatch of feasible_point in the full formulation's variables:
+    segments filled cheapest first, no unserved demand."""
+    G, T, H = data.cfg.n_gen, data.cfg.T, lp.meta["segments"]
+    eta_p, eta_c = lp.meta["eta_p"], lp.meta["eta_c"]
+    width, seg_cost, _ = segment_data(data, H)
+    wd, cs = width / eta_p, seg_cost * eta_p / eta_c
+    x = np.zeros(lp.n)
+    g = np.arange(G)
+    for t in range(T):
+        p = data.demand[t] * data.p_max / data.p_max.sum() / eta_p
+        x[col_index(G, t, U, g)] = 1.0
+        x[col_index(G, t, P, g)] = p
+        above = p - data.p_min / eta_p
+        x[full_col_index(G, H, t, 0, g, T)] = above
+        left = above.copy()
+        cost = np.zeros(G)
+        for h in range(H):
+            s_h = np.clip(left, 0.0, wd[:, h])
+            x[full_col_index(G, H, t, 1 + h, g, T)] = s_h
+            cost += cs[:, h] * s_h
+            left -= s_h
+        x[full_col_index(G, H, t, H + 1, g, T)] = cost
+    return x
+
+
 def feasible_point(data: SCUCData, lp: LP) -> np.ndarray:
     """The all-units-on dispatch the line limits are built from (feasible by construction)."""
     G, T = data.cfg.n_gen, data.cfg.T
@@ -468,10 +726,17 @@ def feasible_point(data: SCUCData, lp: LP) -> np.ndarray:
     return x
 
 
-def make_instance(cfg: SCUCConfig | str, seed: int, instance_scaling: bool = True):
-    """Generate (data, lp) for a preset name or config and a seed."""
+def make_instance(cfg: SCUCConfig | str, seed: int, instance_scaling: bool = True,
+                  formulation: str = "compact", segments: int = 3):
+    """Generate (data, lp) for a preset name or config and a seed; `formulation` "compact"
+    (u, v, w, p per generator-hour) or "full" (build_full_lp)."""
     if isinstance(cfg, str):
         cfg = PRESETS[cfg]
+    if formulation == "full":
+        data = make_scuc_data(cfg, seed, bus_rows=True)
+        return data, build_full_lp(data, instance_scaling, segments)
+    if formulation != "compact":
+        raise ValueError(f"unknown formulation {formulation!r}")
     data = make_scuc_data(cfg, seed)
     return data, build_lp(data, instance_scaling)
 
