@@ -360,7 +360,7 @@ def ablation_leg(data, rounds, stream, formulation="compact"):
                              stream=stream, time_limit_s=150.0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = successive.run(data, lp, rounds=rounds, tau=0.1, opts=opts)
+        r = successive.run(data, lp, rounds=rounds, tau=0.1, opts=opts, log=lambda m: log(f"  {name} {m}"))
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         rec = dict(method=name, instance_scaling=inst, ruiz=bool(scaling & hprlp.HPR_SCALE_RUIZ),

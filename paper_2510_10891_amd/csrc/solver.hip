@@ -425,21 +425,35 @@ struct DevMatrix {
         }
         set_unroll(4, st);
     }
+    // host schedules already built for a U (kept while the tuner switches between them)
+    struct Built {
+        int U;
+        std::vector<RowRef> rows;
+        std::vector<BlockDesc> sched;
+        std::vector<int32_t> seg;
+    };
+    std::vector<Built> built;
     void set_unroll(int U, hipStream_t st) {
-        std::vector<RowRef> r;
-        std::vector<int32_t> sg;
-        std::vector<BlockDesc> sc;
-        make_schedule(start_h, base_h, wide_h, lp_rows, U, r, sc, sg);
+        const Built* b = nullptr;
+        for (const Built& x : built)
+            if (x.U == U) b = &x;
+        if (!b) {
+            built.push_back(Built{U, {}, {}, {}});
+            make_schedule(start_h, base_h, wide_h, lp_rows, U, built.back().rows, built.back().sched,
+                          built.back().seg);
+            b = &built.back();
+        }
         unroll = U;
-        nblocks = (int32_t)sc.size();
-        upload(rows, r, st);
-        upload(sched, sc, st);
-        upload(seg, sg, st);
+        nblocks = (int32_t)b->sched.size();
+        upload(rows, b->rows, st);
+        upload(sched, b->sched, st);
+        upload(seg, b->seg, st);
         HIP_OK(hipStreamSynchronize(st));
-        sched_h = std::move(sc);
-        seg_h = std::move(sg);
+        sched_h = b->sched;
+        seg_h = b->seg;
         use_act = false;
     }
+    void drop_built() { std::vector<Built>().swap(built); }
     // Launch only the blocks of the LPs with running[l] != 0 (each LP's blocks stay in their
     // order, so per-block partial sums and their per-LP totals are unchanged).
     void compact(const std::vector<int32_t>& running, hipStream_t st) {
@@ -667,6 +681,7 @@ static void autotune(Engine* e) {
         Mx.nontemporal = 0;
         if (fU || Mx.nrows == 0) {
             Mx.set_unroll(fU ? fU : 4, st);
+            Mx.drop_built();
             continue;
         }
         auto time_it = [&]() {
@@ -684,18 +699,29 @@ static void autotune(Engine* e) {
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
             return ms;
         };
-        int bestU = 4;
-        float best = 1e30f;
-        for (int U : {1, 2, 4}) {
-            Mx.set_unroll(U, st);
-            const float ms = time_it();
-            if (ms < best) best = ms, bestU = U;
-        }
+        // candidates timed in interleaved rounds, each keeping its fastest round, so that a
+        // clock ramp during the first rounds does not favour the later candidates
+        const int Us[3] = {1, 2, 4};
+        float t_u[3] = {1e30f, 1e30f, 1e30f};
+        for (int round = 0; round < 3; ++round)
+            for (int k = 0; k < 3; ++k) {
+                Mx.set_unroll(Us[k], st);
+                t_u[k] = std::min(t_u[k], time_it());
+            }
+        int bestU = Us[0];
+        float best = t_u[0];
+        for (int k = 1; k < 3; ++k)
+            if (t_u[k] < best) best = t_u[k], bestU = Us[k];
         Mx.set_unroll(bestU, st);
-        const float ms_plain = time_it();
-        Mx.nontemporal = 1;
-        const float ms_nt = time_it();
+        float ms_plain = 1e30f, ms_nt = 1e30f;
+        for (int round = 0; round < 3; ++round) {
+            Mx.nontemporal = 0;
+            ms_plain = std::min(ms_plain, time_it());
+            Mx.nontemporal = 1;
+            ms_nt = std::min(ms_nt, time_it());
+        }
         Mx.nontemporal = ms_nt < ms_plain ? 1 : 0;
+        Mx.drop_built();
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

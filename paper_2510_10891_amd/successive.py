@@ -38,7 +38,9 @@ class Result:
 
 
 def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
-        opts: hprlp.Options | None = None, warm: bool = True) -> Result:
+        opts: hprlp.Options | None = None, warm: bool = True, log=None) -> Result:
+    """Up to `rounds` rounds of solve, Algorithm 1 and Fix on one handle; `log` (optional)
+    receives one line per round."""
     G, T = data.cfg.n_gen, data.cfg.T
     opts = opts or hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32)
     h = hprlp.hpr_create(lp, opts)
@@ -66,6 +68,9 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
             hprlp.hpr_set_bounds(h, lo, hi)
             res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
                                     float(fixed.mean()), int(add.sum())))
+            if log is not None:
+                log(f"round {i}: {info.term}, {info.iters} iterations, {dt:.2f} s, "
+                    f"{fixed.mean():.3f} of u fixed")
     finally:
         hprlp.hpr_destroy(h)
     res.col_lo, res.col_hi, res.x = lo, hi, x
