@@ -22,13 +22,18 @@ constexpr int kChunk = 8192;     // entries per block of the segmented vector ke
 constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 
 // One thread block of a matrix product: rows list[first .. first + count) of bin `bin`
-// (2^bin lanes per row), all belonging to LP `lp`.
+// (2^bin lanes per row), all belonging to LP `lp`. When wlen > 0, every column the block's
+// rows use lies in [wlo, wlo + wlen) and the block first copies that window of the gathered
+// vector into LDS (products with one gathered vector).
 struct BlockDesc {
     int32_t bin;
     int32_t lp;
     int32_t first;
     int32_t count;
+    int32_t wlo;
+    int32_t wlen;
 };
+constexpr int kWinBytes = 16384;   // LDS per block for a staged window
 
 // One entry of a schedule's row list, fetched by one 16-byte load: the row, its number of
 // quads (4 stored entries; the top bit marks a "wide" row), the smallest column of the row

@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace hpr {
 
 // ---------------------------------------------------------------- loads
@@ -146,8 +148,11 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
 }
 
 // One block: each group of G lanes takes one row of the block's slice of the row list.
-template <int G, int U, bool NT, typename Op>
-__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d) {
+// STAGED: the gathered vector is read from the block's LDS window `win` (columns relative to
+// d.wlo; no wide rows in such a block), otherwise from global memory.
+template <int G, int U, bool NT, bool STAGED, typename Op, typename Tx>
+__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                        const Tx* win) {
     using Acc = typename Op::Acc;
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
@@ -159,12 +164,30 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     if constexpr (Op::NV > 0) {
         const int64_t b = (int64_t)kVec * rr.start4;
         const int64_t e = b + (int64_t)kVec * (rr.quads & ~kWide);
-        if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
-        else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
+        if constexpr (STAGED) {
+            group_dot<G, U, NT, false, 1>(A, b, e, rr.base - d.wlo, lane, win, win, s0, s1);
+        } else {
+            if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
+            else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
+        }
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
     }
     if (active && lane == 0) op.epi(row, s0, s1);
+}
+
+template <int U, bool NT, bool STAGED, typename Op, typename Tx>
+__device__ __forceinline__ void run_block(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                          const Tx* win) {
+    switch (d.bin) {
+        case 0: run_bin<1, U, NT, STAGED>(A, op, d, win); break;
+        case 1: run_bin<2, U, NT, STAGED>(A, op, d, win); break;
+        case 2: run_bin<4, U, NT, STAGED>(A, op, d, win); break;
+        case 3: run_bin<8, U, NT, STAGED>(A, op, d, win); break;
+        case 4: run_bin<16, U, NT, STAGED>(A, op, d, win); break;
+        case 5: run_bin<32, U, NT, STAGED>(A, op, d, win); break;
+        default: run_bin<64, U, NT, STAGED>(A, op, d, win); break;
+    }
 }
 
 template <int NQ>
@@ -185,21 +208,28 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
     }
 }
 
-// Ops with NQ > 0 (reductions) never skip a block: every block writes its partials.
+// Ops with NQ > 0 (reductions) never skip a block: every block writes its partials. A block
+// with a window (and an op with one gathered vector whose window fits kWinBytes) copies the
+// window into LDS with coalesced loads and gathers from there: the same values in the same
+// order, so the result does not depend on which path a block takes.
 template <typename Op, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
+    using Tx = typename std::remove_cv<typename std::remove_pointer<decltype(op_in.g0)>::type>::type;
     const BlockDesc d = A.sched[blockIdx.x];
     Op op = op_in;
-    if (!op.init(d)) return;
-    switch (d.bin) {
-        case 0: run_bin<1, U, NT>(A, op, d); break;
-        case 1: run_bin<2, U, NT>(A, op, d); break;
-        case 2: run_bin<4, U, NT>(A, op, d); break;
-        case 3: run_bin<8, U, NT>(A, op, d); break;
-        case 4: run_bin<16, U, NT>(A, op, d); break;
-        case 5: run_bin<32, U, NT>(A, op, d); break;
-        default: run_bin<64, U, NT>(A, op, d); break;
+    if (!op.init(d)) return;    // uniform over the block
+    bool done = false;
+    if constexpr (Op::NV == 1) {
+        constexpr int kWinElems = kWinBytes / (int)sizeof(Tx);
+        __shared__ __align__(16) Tx win[kWinElems];
+        if (d.wlen > 0 && d.wlen <= kWinElems) {
+            for (int t = threadIdx.x; t < d.wlen; t += kBlock) win[t] = op.g0[d.wlo + t];
+            __syncthreads();
+            run_block<U, NT, true>(A, op, d, win);
+            done = true;
+        }
     }
+    if (!done) run_block<U, NT, false>(A, op, d, static_cast<const Tx*>(nullptr));
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
 

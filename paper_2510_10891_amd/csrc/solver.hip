@@ -130,12 +130,14 @@ struct Layout {
 };
 
 // 16-bit offsets of every entry from its row's smallest column (rows spanning 65536 columns
-// or more are "wide": their offsets are unused and the 32-bit indices are read instead)
+// or more are "wide": their offsets are unused and the 32-bit indices are read instead);
+// base / top = smallest / largest column of each row
 static void short_indices(const Layout& L, std::vector<uint16_t>& col16, std::vector<int32_t>& base,
-                          std::vector<uint8_t>& wide) {
+                          std::vector<int32_t>& top, std::vector<uint8_t>& wide) {
     const int64_t R = (int64_t)L.start.size() - 1;
     col16.assign(L.col.size(), 0);
     base.assign(R, 0);
+    top.assign(R, 0);
     wide.assign(R, 0);
     for (int64_t i = 0; i < R; ++i) {
         const int64_t b = L.start[i], e = L.start[i + 1];
@@ -146,6 +148,7 @@ static void short_indices(const Layout& L, std::vector<uint16_t>& col16, std::ve
             hi = std::max(hi, L.col[k]);
         }
         base[i] = lo;
+        top[i] = hi;
         if ((int64_t)hi - lo >= 65536) {
             wide[i] = 1;
             continue;
@@ -355,8 +358,12 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
 // The work list of one pooled matrix for U quads per lane and pass: per LP, per bin (bin b:
 // rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
 // rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
+// A block gets an LDS window of the gathered vector when its rows' columns span at most
+// win_max entries, no row is wide, and the window is no larger than the block's number of
+// stored entries (so copying it reads less than gathering from global memory would).
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
-                          const std::vector<uint8_t>& wide, const std::vector<int64_t>& lp_rows, int U,
+                          const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
+                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max,
                           std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
     const int L = (int)lp_rows.size() - 1;
     rows.clear();
@@ -380,12 +387,25 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 d.lp = l;
                 d.first = (int32_t)rows.size();
                 d.count = (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k);
-                sched.push_back(d);
+                int64_t wlo = INT64_MAX, whi = -1, entries = 0;
+                bool any_wide = false;
                 for (int32_t r = 0; r < d.count; ++r) {
                     const int32_t i = by_bin[b][k + r];
                     const int32_t quads = (int32_t)((start[i + 1] - start[i]) / kVec);
                     rows.push_back(RowRef{i, quads | (wide[i] ? kWide : 0), base[i], (int32_t)(start[i] / kVec)});
+                    if (quads == 0) continue;
+                    any_wide = any_wide || wide[i];
+                    wlo = std::min<int64_t>(wlo, base[i]);
+                    whi = std::max<int64_t>(whi, top[i]);
+                    entries += (int64_t)quads * kVec;
                 }
+                d.wlo = 0;
+                d.wlen = 0;
+                if (!any_wide && whi >= 0 && whi - wlo + 1 <= win_max && whi - wlo + 1 <= entries) {
+                    d.wlo = (int32_t)wlo;
+                    d.wlen = (int32_t)(whi - wlo + 1);
+                }
+                sched.push_back(d);
             }
         }
     }
@@ -396,8 +416,9 @@ struct DevMatrix {
     DBuf start, col, col16, rows, sched, seg, val64, val32;
     DBuf sched_act, seg_act;                 // compacted schedule: the blocks of running LPs only
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
-    std::vector<int32_t> base_h;
+    std::vector<int32_t> base_h, top_h;
     std::vector<uint8_t> wide_h;
+    int32_t win_max = 0;                     // LDS window limit in vector entries (0: off)
     std::vector<BlockDesc> sched_h;
     std::vector<int32_t> seg_h;
     int32_t nrows = 0, nblocks = 0, nblocks_act = 0, unroll = 4, nontemporal = 0;
@@ -413,7 +434,8 @@ struct DevMatrix {
             throw HipError{HPR_ERR_INVALID};
         }
         std::vector<uint16_t> c16;
-        short_indices(L, c16, base_h, wide_h);
+        short_indices(L, c16, base_h, top_h, wide_h);
+        win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
         upload(start, L.start, st);
         upload(col, L.col, st);
         upload(col16, c16, st);
@@ -439,8 +461,8 @@ struct DevMatrix {
             if (x.U == U) b = &x;
         if (!b) {
             built.push_back(Built{U, {}, {}, {}});
-            make_schedule(start_h, base_h, wide_h, lp_rows, U, built.back().rows, built.back().sched,
-                          built.back().seg);
+            make_schedule(start_h, base_h, top_h, wide_h, lp_rows, U, win_max, built.back().rows,
+                          built.back().sched, built.back().seg);
             b = &built.back();
         }
         unroll = U;
