@@ -120,6 +120,14 @@ typedef struct {
                                    1, 2, 4 or 8; 0 (default) = pick per matrix by timing at
                                    hpr_create (U = 1, 2, 4; ordinary or non-temporal loads).
                                    The choice fixes the summation order. */
+    int32_t lds_windows;        /* LDS windows of the gathered vector in the matrix products:
+                                   0 = none; 1 = "full" windows only (a block whose rows use at
+                                   most 16 KB of vector entries copies them into LDS first);
+                                   2 = full and "split" windows (the two aligned 8 KB tiles
+                                   holding most of a block's entries, the rest read from global
+                                   memory); -1 (default) = full windows, split windows picked per
+                                   matrix by timing at hpr_create (on when unroll is given).
+                                   Results do not depend on it. */
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
                                    its check and its control step as one captured HIP graph;
                                    0: launch every kernel directly */
@@ -158,6 +166,12 @@ typedef struct {
     int32_t unroll_at;          /* schedule used for A^T (primal step) */
     int32_t nontemporal_a;      /* 1: A streamed with non-temporal loads */
     int32_t nontemporal_at;
+    int32_t full_blocks_a;      /* thread blocks of A's schedule with a full LDS window */
+    int32_t split_blocks_a;     /* ... with a split window */
+    int32_t full_blocks_at;     /* the same for A^T */
+    int32_t split_blocks_at;
+    int32_t blocks_a;           /* all thread blocks of A's schedule */
+    int32_t blocks_at;
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

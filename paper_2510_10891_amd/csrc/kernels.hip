@@ -111,13 +111,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Where a gathered entry comes from. Global: g[c]. Window: w[c] (c already relative to the
+// block's LDS window). Split: the LDS window for columns in [lo, lo + len), g elsewhere.
+template <typename Tx>
+struct FromGlobal {
+    const Tx* __restrict__ g;
+    __device__ __forceinline__ Tx operator()(int c) const { return g[c]; }
+};
+template <typename Tx>
+using LdsPtr = const __attribute__((address_space(3))) Tx*;
+template <typename Tx>
+struct FromWindow {
+    LdsPtr<Tx> w;
+    __device__ __forceinline__ Tx operator()(int c) const { return w[c]; }
+};
+template <typename Tx>
+struct FromSplit {
+    LdsPtr<Tx> w;
+    const Tx* __restrict__ g;
+    int lo, len;
+    __device__ __forceinline__ Tx operator()(int c) const {
+        // an LDS read for every entry (clamped index) and a global read only outside the
+        // window: two separate loads, which the compiler cannot merge into one flat load
+        const unsigned r = (unsigned)(c - lo);
+        const bool in = r < (unsigned)len;
+        Tx x = w[in ? r : 0u];
+        if (!in) x = g[c];
+        return x;
+    }
+};
+
 // Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
 // group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
 // before any gather so U 16-byte loads per array are in flight per lane.
-template <int G, int U, bool NT, bool WIDE, int NV, typename Tm, typename Tx, typename Acc>
+template <int G, int U, bool NT, bool WIDE, int NV, typename Tm, typename S0, typename S1, typename Acc>
 __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int base, int lane,
-                                          const Tx* __restrict__ g0, const Tx* __restrict__ g1,
-                                          Acc& s0, Acc& s1) {
+                                          const S0& g0, const S1& g1, Acc& s0, Acc& s1) {
     s0 = Acc(0);
     s1 = Acc(0);
     for (int64_t p = b + kVec * lane; p < e; p += (int64_t)kVec * G * U) {
@@ -136,11 +165,11 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
         for (int u = 0; u < U; ++u) {
             const int64_t q = p + (int64_t)kVec * G * u;
             if (q < e) {
-                s0 += Acc(v[u].a[0]) * Acc(g0[c[u].x]) + Acc(v[u].a[1]) * Acc(g0[c[u].y]) +
-                      Acc(v[u].a[2]) * Acc(g0[c[u].z]) + Acc(v[u].a[3]) * Acc(g0[c[u].w]);
+                s0 += Acc(v[u].a[0]) * Acc(g0(c[u].x)) + Acc(v[u].a[1]) * Acc(g0(c[u].y)) +
+                      Acc(v[u].a[2]) * Acc(g0(c[u].z)) + Acc(v[u].a[3]) * Acc(g0(c[u].w));
                 if constexpr (NV == 2) {
-                    s1 += Acc(v[u].a[0]) * Acc(g1[c[u].x]) + Acc(v[u].a[1]) * Acc(g1[c[u].y]) +
-                          Acc(v[u].a[2]) * Acc(g1[c[u].z]) + Acc(v[u].a[3]) * Acc(g1[c[u].w]);
+                    s1 += Acc(v[u].a[0]) * Acc(g1(c[u].x)) + Acc(v[u].a[1]) * Acc(g1(c[u].y)) +
+                          Acc(v[u].a[2]) * Acc(g1(c[u].z)) + Acc(v[u].a[3]) * Acc(g1(c[u].w));
                 }
             }
         }
@@ -148,9 +177,10 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
 }
 
 // One block: each group of G lanes takes one row of the block's slice of the row list.
-// STAGED: the gathered vector is read from the block's LDS window `win` (columns relative to
-// d.wlo; no wide rows in such a block), otherwise from global memory.
-template <int G, int U, bool NT, bool STAGED, typename Op, typename Tx>
+// MODE 0: the gathered vector is read from global memory; 1: from the block's LDS window
+// `win`, which holds every column the block uses (columns relative to d.wlo; no wide rows in
+// such a block); 2: from the window for the columns it holds, global memory for the rest.
+template <int G, int U, bool NT, int MODE, typename Op, typename Tx>
 __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
                                         const Tx* win) {
     using Acc = typename Op::Acc;
@@ -164,11 +194,17 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     if constexpr (Op::NV > 0) {
         const int64_t b = (int64_t)kVec * rr.start4;
         const int64_t e = b + (int64_t)kVec * (rr.quads & ~kWide);
-        if constexpr (STAGED) {
-            group_dot<G, U, NT, false, 1>(A, b, e, rr.base - d.wlo, lane, win, win, s0, s1);
+        if constexpr (MODE == 1) {
+            const FromWindow<Tx> w{(LdsPtr<Tx>)win};
+            group_dot<G, U, NT, false, 1>(A, b, e, rr.base - d.wlo, lane, w, w, s0, s1);
+        } else if constexpr (MODE == 2) {
+            const FromSplit<Tx> w{(LdsPtr<Tx>)win, op.g0, d.wlo, -d.wlen};
+            if (rr.quads & kWide) group_dot<G, U, NT, true, 1>(A, b, e, rr.base, lane, w, w, s0, s1);
+            else group_dot<G, U, NT, false, 1>(A, b, e, rr.base, lane, w, w, s0, s1);
         } else {
-            if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
-            else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, op.g0, op.g1, s0, s1);
+            const FromGlobal<Tx> g0{op.g0}, g1{op.g1};
+            if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, g0, g1, s0, s1);
+            else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, g0, g1, s0, s1);
         }
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
@@ -176,17 +212,17 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     if (active && lane == 0) op.epi(row, s0, s1);
 }
 
-template <int U, bool NT, bool STAGED, typename Op, typename Tx>
+template <int U, bool NT, int MODE, typename Op, typename Tx>
 __device__ __forceinline__ void run_block(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
                                           const Tx* win) {
     switch (d.bin) {
-        case 0: run_bin<1, U, NT, STAGED>(A, op, d, win); break;
-        case 1: run_bin<2, U, NT, STAGED>(A, op, d, win); break;
-        case 2: run_bin<4, U, NT, STAGED>(A, op, d, win); break;
-        case 3: run_bin<8, U, NT, STAGED>(A, op, d, win); break;
-        case 4: run_bin<16, U, NT, STAGED>(A, op, d, win); break;
-        case 5: run_bin<32, U, NT, STAGED>(A, op, d, win); break;
-        default: run_bin<64, U, NT, STAGED>(A, op, d, win); break;
+        case 0: run_bin<1, U, NT, MODE>(A, op, d, win); break;
+        case 1: run_bin<2, U, NT, MODE>(A, op, d, win); break;
+        case 2: run_bin<4, U, NT, MODE>(A, op, d, win); break;
+        case 3: run_bin<8, U, NT, MODE>(A, op, d, win); break;
+        case 4: run_bin<16, U, NT, MODE>(A, op, d, win); break;
+        case 5: run_bin<32, U, NT, MODE>(A, op, d, win); break;
+        default: run_bin<64, U, NT, MODE>(A, op, d, win); break;
     }
 }
 
@@ -209,8 +245,9 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
 }
 
 // Ops with NQ > 0 (reductions) never skip a block: every block writes its partials. A block
-// with a window (and an op with one gathered vector whose window fits kWinBytes) copies the
-// window into LDS with coalesced loads and gathers from there: the same values in the same
+// with a window (wlen > 0: every column it uses; wlen < 0: a window of -wlen columns holding
+// most of them), for an op with one gathered vector and a window that fits kWinBytes, copies
+// the window into LDS with coalesced loads and gathers from there: the same values in the same
 // order, so the result does not depend on which path a block takes.
 template <typename Op, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
@@ -222,14 +259,25 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
     if constexpr (Op::NV == 1) {
         constexpr int kWinElems = kWinBytes / (int)sizeof(Tx);
         __shared__ __align__(16) Tx win[kWinElems];
-        if (d.wlen > 0 && d.wlen <= kWinElems) {
-            for (int t = threadIdx.x; t < d.wlen; t += kBlock) win[t] = op.g0[d.wlo + t];
+        const int len = d.wlen < 0 ? -d.wlen : d.wlen;
+        if (len > 0 && len <= kWinElems) {
+            constexpr int kPer = 16 / (int)sizeof(Tx);   // entries per 16-byte load
+            int t0 = 0;
+            if (d.wlo % kPer == 0) {   // 16-byte copies (the vector's base is 256-byte aligned)
+                const int n16 = len / kPer;
+                const int4* src = reinterpret_cast<const int4*>(op.g0 + d.wlo);
+                int4* dst = reinterpret_cast<int4*>(win);
+                for (int t = threadIdx.x; t < n16; t += kBlock) dst[t] = src[t];
+                t0 = n16 * kPer;
+            }
+            for (int t = t0 + threadIdx.x; t < len; t += kBlock) win[t] = op.g0[d.wlo + t];
             __syncthreads();
-            run_block<U, NT, true>(A, op, d, win);
+            if (d.wlen > 0) run_block<U, NT, 1>(A, op, d, win);
+            else run_block<U, NT, 2>(A, op, d, win);
             done = true;
         }
     }
-    if (!done) run_block<U, NT, false>(A, op, d, static_cast<const Tx*>(nullptr));
+    if (!done) run_block<U, NT, 0>(A, op, d, static_cast<const Tx*>(nullptr));
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
 

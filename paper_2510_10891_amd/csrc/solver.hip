@@ -240,6 +240,7 @@ static int validate_opts(const hpr_opts* o) {
         return fail(HPR_ERR_INVALID, "sigma_smoothing and sigma_smoothing_warm must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
+    if (o->lds_windows < -1 || o->lds_windows > 2) return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1 or 2");
     return HPR_OK;
 }
 
@@ -358,13 +359,26 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
 // The work list of one pooled matrix for U quads per lane and pass: per LP, per bin (bin b:
 // rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
 // rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
+// Per row, the number of stored entries in each aligned tile of `tile` columns it touches.
+struct TileCounts {
+    int32_t tile = 0;
+    std::vector<int64_t> ptr;     // [rows + 1]
+    std::vector<int32_t> id, cnt;
+};
+
 // A block gets an LDS window of the gathered vector when its rows' columns span at most
 // win_max entries, no row is wide, and the window is no larger than the block's number of
-// stored entries (so copying it reads less than gathering from global memory would).
+// stored entries (so copying it reads less than gathering from global memory would): the
+// "full" window, wlen > 0. Otherwise, the two consecutive aligned tiles (2 tiles = win_max
+// columns, clipped to the vector's ncols entries) holding most of the block's entries become
+// a "split" window (wlen < 0) when they hold at least half of the entries and no fewer
+// entries than the window has columns.
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
                           const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
-                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max,
+                          const TileCounts& tc, int64_t ncols,
+                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split,
                           std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
+    std::vector<std::pair<int32_t, int64_t>> tiles;
     const int L = (int)lp_rows.size() - 1;
     rows.clear();
     sched.clear();
@@ -401,9 +415,37 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 }
                 d.wlo = 0;
                 d.wlen = 0;
+                if (whi >= 0) wlo -= wlo % 4;   // 16-byte aligned start for the window copy
                 if (!any_wide && whi >= 0 && whi - wlo + 1 <= win_max && whi - wlo + 1 <= entries) {
                     d.wlo = (int32_t)wlo;
                     d.wlen = (int32_t)(whi - wlo + 1);
+                } else if (split && tc.tile > 0 && entries > 0) {
+                    tiles.clear();
+                    for (int32_t r = 0; r < d.count; ++r) {
+                        const int32_t i = by_bin[b][k + r];
+                        for (int64_t t = tc.ptr[i]; t < tc.ptr[i + 1]; ++t) tiles.emplace_back(tc.id[t], tc.cnt[t]);
+                    }
+                    std::sort(tiles.begin(), tiles.end());
+                    size_t w = 0;   // merge equal tiles
+                    for (size_t t = 0; t < tiles.size(); ++t) {
+                        if (w > 0 && tiles[w - 1].first == tiles[t].first) tiles[w - 1].second += tiles[t].second;
+                        else tiles[w++] = tiles[t];
+                    }
+                    tiles.resize(w);
+                    int64_t best = -1, best_in = 0;
+                    for (size_t t = 0; t < tiles.size(); ++t) {
+                        int64_t in = tiles[t].second;
+                        if (t + 1 < tiles.size() && tiles[t + 1].first == tiles[t].first + 1) in += tiles[t + 1].second;
+                        if (in > best_in) best_in = in, best = tiles[t].first;
+                    }
+                    if (best >= 0) {
+                        const int64_t lo = best * (int64_t)tc.tile;
+                        const int64_t len = std::min<int64_t>(2 * (int64_t)tc.tile, ncols - lo);
+                        if (len > 0 && 2 * best_in >= entries && best_in >= len) {
+                            d.wlo = (int32_t)lo;
+                            d.wlen = -(int32_t)len;
+                        }
+                    }
                 }
                 sched.push_back(d);
             }
@@ -418,14 +460,20 @@ struct DevMatrix {
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
     std::vector<int32_t> base_h, top_h;
     std::vector<uint8_t> wide_h;
-    int32_t win_max = 0;                     // LDS window limit in vector entries (0: off)
+    int32_t win_max = 0;                     // LDS window limit in vector entries
+    int32_t win_mode = 2;                    // 0: no windows, 1: full windows, 2: full and split
+    TileCounts tiles;
+    int64_t ncols = 0;                       // length of the gathered vector
     std::vector<BlockDesc> sched_h;
     std::vector<int32_t> seg_h;
     int32_t nrows = 0, nblocks = 0, nblocks_act = 0, unroll = 4, nontemporal = 0;
     bool use_act = false;
     int64_t padded = 0;
-    void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, bool fp32, hipStream_t st) {
+    void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, int64_t ncols_in, bool fp32,
+                     int lds_windows, hipStream_t st) {
         nrows = (int32_t)L.start.size() - 1;
+        ncols = ncols_in;
+        win_mode = lds_windows < 0 ? 2 : lds_windows;
         padded = (int64_t)L.col.size();
         start_h = L.start;
         lp_rows = lp_rows_in;
@@ -436,6 +484,7 @@ struct DevMatrix {
         std::vector<uint16_t> c16;
         short_indices(L, c16, base_h, top_h, wide_h);
         win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
+        count_tiles(L, win_max / 2);
         upload(start, L.start, st);
         upload(col, L.col, st);
         upload(col16, c16, st);
@@ -447,9 +496,25 @@ struct DevMatrix {
         }
         set_unroll(4, st);
     }
+    void count_tiles(const Layout& L, int32_t tile) {
+        tiles.tile = tile;
+        tiles.ptr.assign((size_t)nrows + 1, 0);
+        tiles.id.clear();
+        tiles.cnt.clear();
+        for (int32_t i = 0; i < nrows; ++i) {
+            tiles.ptr[i] = (int64_t)tiles.id.size();
+            const size_t first = tiles.id.size();
+            for (int64_t k = L.start[i]; k < L.start[i + 1]; ++k) {
+                const int32_t t = L.col[k] / tile;
+                if (tiles.id.size() > first && tiles.id.back() == t) ++tiles.cnt.back();
+                else tiles.id.push_back(t), tiles.cnt.push_back(1);
+            }
+        }
+        tiles.ptr[nrows] = (int64_t)tiles.id.size();
+    }
     // host schedules already built for a U (kept while the tuner switches between them)
     struct Built {
-        int U;
+        int U, mode;
         std::vector<RowRef> rows;
         std::vector<BlockDesc> sched;
         std::vector<int32_t> seg;
@@ -458,11 +523,11 @@ struct DevMatrix {
     void set_unroll(int U, hipStream_t st) {
         const Built* b = nullptr;
         for (const Built& x : built)
-            if (x.U == U) b = &x;
+            if (x.U == U && x.mode == win_mode) b = &x;
         if (!b) {
-            built.push_back(Built{U, {}, {}, {}});
-            make_schedule(start_h, base_h, top_h, wide_h, lp_rows, U, win_max, built.back().rows,
-                          built.back().sched, built.back().seg);
+            built.push_back(Built{U, win_mode, {}, {}, {}});
+            make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, U, win_mode >= 1 ? win_max : 0,
+                          win_mode == 2, built.back().rows, built.back().sched, built.back().seg);
             b = &built.back();
         }
         unroll = U;
@@ -475,7 +540,19 @@ struct DevMatrix {
         seg_h = b->seg;
         use_act = false;
     }
-    void drop_built() { std::vector<Built>().swap(built); }
+    void window_counts(int32_t& full, int32_t& split, int32_t& all) const {
+        full = split = 0;
+        for (const BlockDesc& d : sched_h) {
+            if (d.wlen > 0) ++full;
+            if (d.wlen < 0) ++split;
+        }
+        all = (int32_t)sched_h.size();
+    }
+    // after tuning: no further schedules are built
+    void drop_built() {
+        std::vector<Built>().swap(built);
+        tiles = TileCounts{};
+    }
     // Launch only the blocks of the LPs with running[l] != 0 (each LP's blocks stay in their
     // order, so per-block partial sums and their per-LP totals are unchanged).
     void compact(const std::vector<int32_t>& running, hipStream_t st) {
@@ -597,6 +674,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->power_tol = 1e-6;
     o->profile = 0;
     o->unroll = 0;
+    o->lds_windows = -1;
     o->use_graph = 1;
     o->warm_fallback = 1;
     o->warm_fallback_ratio = 1000.0;
@@ -721,20 +799,34 @@ static void autotune(Engine* e) {
             HIP_OK(hipEventElapsedTime(&ms, e0, e1));
             return ms;
         };
-        // candidates timed in interleaved rounds, each keeping its fastest round, so that a
-        // clock ramp during the first rounds does not favour the later candidates
-        const int Us[3] = {1, 2, 4};
-        float t_u[3] = {1e30f, 1e30f, 1e30f};
-        for (int round = 0; round < 3; ++round)
-            for (int k = 0; k < 3; ++k) {
-                Mx.set_unroll(Us[k], st);
-                t_u[k] = std::min(t_u[k], time_it());
+        // candidates (U, and split windows on/off when the option leaves that open) timed in
+        // interleaved rounds, each keeping its fastest round, so that a clock ramp during the
+        // first rounds does not favour the later candidates
+        const bool tune_split = e->opts.lds_windows < 0;
+        struct Cand {
+            int U, mode;
+            float ms;
+        };
+        std::vector<Cand> cand;
+        for (int U : {1, 2, 4}) {
+            if (tune_split) {
+                cand.push_back(Cand{U, 1, 1e30f});
+                cand.push_back(Cand{U, 2, 1e30f});
+            } else {
+                cand.push_back(Cand{U, Mx.win_mode, 1e30f});
             }
-        int bestU = Us[0];
-        float best = t_u[0];
-        for (int k = 1; k < 3; ++k)
-            if (t_u[k] < best) best = t_u[k], bestU = Us[k];
-        Mx.set_unroll(bestU, st);
+        }
+        for (int round = 0; round < 3; ++round)
+            for (Cand& c : cand) {
+                Mx.win_mode = c.mode;
+                Mx.set_unroll(c.U, st);
+                c.ms = std::min(c.ms, time_it());
+            }
+        const Cand* best = &cand[0];
+        for (const Cand& c : cand)
+            if (c.ms < best->ms) best = &c;
+        Mx.win_mode = best->mode;
+        Mx.set_unroll(best->U, st);
         float ms_plain = 1e30f, ms_nt = 1e30f;
         for (int round = 0; round < 3; ++round) {
             Mx.nontemporal = 0;
@@ -923,8 +1015,8 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
                 throw HipError{HPR_ERR_INVALID};
             }
         }
-        e->A.upload_from(PA, rows_a, e->fp32, e->st);
-        e->At.upload_from(PAt, rows_at, e->fp32, e->st);
+        e->A.upload_from(PA, rows_a, e->N, e->fp32, o.lds_windows, e->st);
+        e->At.upload_from(PAt, rows_at, e->M, e->fp32, o.lds_windows, e->st);
         e->sync();
         upload_vectors(e.get());
         alloc_iterates(e.get());
@@ -1333,6 +1425,8 @@ static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     out->unroll_at = e->At.unroll;
     out->nontemporal_a = e->A.nontemporal;
     out->nontemporal_at = e->At.nontemporal;
+    e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->blocks_a);
+    e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->blocks_at);
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;

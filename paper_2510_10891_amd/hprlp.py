@@ -40,14 +40,16 @@ class hpr_opts(C.Structure):
                 ("check_every", C.c_int32), ("sigma0", C.c_double), ("lambda_", C.c_double),
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("sigma_smoothing", C.c_double), ("sigma_smoothing_warm", C.c_double), ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
-                ("unroll", C.c_int32), ("use_graph", C.c_int32),
+                ("unroll", C.c_int32), ("lds_windows", C.c_int32), ("use_graph", C.c_int32),
                 ("warm_fallback", C.c_int32), ("warm_fallback_ratio", C.c_double), ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
     _fields_ = [("primal_ms", C.c_double), ("dual_ms", C.c_double), ("samples", C.c_int64),
                 ("unroll_a", C.c_int32), ("unroll_at", C.c_int32), ("nontemporal_a", C.c_int32),
-                ("nontemporal_at", C.c_int32)]
+                ("nontemporal_at", C.c_int32), ("full_blocks_a", C.c_int32), ("split_blocks_a", C.c_int32),
+                ("full_blocks_at", C.c_int32), ("split_blocks_at", C.c_int32), ("blocks_a", C.c_int32),
+                ("blocks_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -110,6 +112,7 @@ class Options:
     power_tol: float = 1e-6
     profile: int = 0
     unroll: int = 0
+    lds_windows: int = -1
     use_graph: int = 1
     warm_fallback: int = 1
     warm_fallback_ratio: float = 1000.0
@@ -121,6 +124,13 @@ class Options:
             setattr(o, f.name, getattr(self, f.name))
         o.stream = self.stream or None
         return o
+
+
+def _kstats(s: hpr_kernel_stats) -> dict:
+    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
+                unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at,
+                full_blocks_a=s.full_blocks_a, split_blocks_a=s.split_blocks_a, full_blocks_at=s.full_blocks_at,
+                split_blocks_at=s.split_blocks_at, blocks_a=s.blocks_a, blocks_at=s.blocks_at)
 
 
 def hpr_default_opts() -> hpr_opts:
@@ -226,8 +236,7 @@ def hpr_get_solution(h: Handle):
 def hpr_get_kernel_stats(h: Handle) -> dict:
     s = hpr_kernel_stats()
     _check(lib().hpr_get_kernel_stats(h.ptr, C.byref(s)))
-    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
-                unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at)
+    return _kstats(s)
 
 
 def solve(lp, opts: Options | None = None, x0=None, y0=None):
@@ -316,8 +325,7 @@ def hpr_batch_get_solution(b: Batch, i: int):
 def hpr_batch_get_kernel_stats(b: Batch) -> dict:
     s = hpr_kernel_stats()
     _check(lib().hpr_batch_get_kernel_stats(b.ptr, C.byref(s)))
-    return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
-                unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at)
+    return _kstats(s)
 
 
 def batch_solve(lps, opts: Options | None = None, starts=None):

@@ -37,7 +37,8 @@ def test_default_opts_match_python_mirror():
     p = hprlp.Options()
     for f in ("tol", "max_iter", "precision", "scaling", "ruiz_iters", "check_every", "sigma0",
               "restart", "sigma_update", "power_max_iter", "power_tol", "use_graph", "warm_fallback",
-              "warm_fallback_ratio", "unroll", "sigma_smoothing", "sigma_smoothing_warm", "profile"):
+              "warm_fallback_ratio", "unroll", "lds_windows", "sigma_smoothing", "sigma_smoothing_warm",
+              "profile"):
         assert getattr(o, f) == getattr(p, f), f
 
 
@@ -80,7 +81,7 @@ def test_create_rejects_no_columns():
 @pytest.mark.parametrize("opt", [dict(max_iter=0), dict(check_every=0), dict(sigma0=0.0), dict(sigma0=-1.0),
                                  dict(tol=-1.0), dict(precision=7), dict(power_max_iter=0),
                                  dict(lambda_=float("nan")), dict(warm_fallback_ratio=0.0),
-                                 dict(unroll=3),
+                                 dict(unroll=3), dict(lds_windows=3), dict(lds_windows=-2),
                                  dict(sigma_smoothing=0.0), dict(sigma_smoothing=1.5),
                                  dict(sigma_smoothing_warm=0.0)])
 def test_create_rejects_bad_options(opt):

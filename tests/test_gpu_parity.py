@@ -241,6 +241,42 @@ def test_medium_full_size_parity_and_tolerance():
         assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), ev
 
 
+@pytest.mark.parametrize("formulation", ["compact", "full"])
+def test_lds_window_modes_agree_bitwise(formulation):
+    """The three gather paths (global memory, full LDS windows, split windows) read the same
+    values in the same order: for a fixed lane schedule the iterates agree bitwise across
+    lds_windows = 0, 1, 2, and with the oracle to rounding (FP64). 2,000-bus matrices, where
+    every mode has blocks to act on (the schedule's block counts say which mode ran)."""
+    _, lp = scuc.make_instance("medium", 0, formulation=formulation)
+    if formulation == "full":
+        lp = fixing.presolve_free_singletons(lp).lp
+    precisions = (hprlp.HPR_FP64, hprlp.HPR_FP32) if formulation == "compact" else (hprlp.HPR_FP32,)
+    K = 65
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, lambda_in=1.0)) if formulation == "compact" else None
+    for precision in precisions:
+        runs = []
+        for mode in (0, 1, 2):
+            h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=K, unroll=2, lds_windows=mode, lambda_=1.0,
+                                                   precision=precision, profile=1))
+            try:
+                info = hprlp.hpr_solve(h)
+                x, y, z = hprlp.hpr_get_solution(h)
+                ks = hprlp.hpr_get_kernel_stats(h)
+            finally:
+                hprlp.hpr_destroy(h)
+            runs.append((info, x, y, z, ks))
+        k0, k1, k2 = (r[4] for r in runs)
+        assert k0["full_blocks_a"] == k0["split_blocks_a"] == k0["full_blocks_at"] == k0["split_blocks_at"] == 0
+        assert k1["split_blocks_a"] == k1["split_blocks_at"] == 0 and k1["full_blocks_a"] > 0
+        assert k2["split_blocks_a"] + k2["split_blocks_at"] > 0
+        for info, x, y, z, _ in runs[1:]:
+            assert info.iters == runs[0][0].iters
+            assert np.array_equal(x, runs[0][1]) and np.array_equal(y, runs[0][2]) and np.array_equal(z, runs[0][3])
+        if o is not None and precision == hprlp.HPR_FP64:
+            info, x, y, z, _ = runs[2]
+            assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
 def test_medium_objective_matches_interior_point_golden():
     """The 2,000-bus instance solved to 1e-6 in FP64 reaches the optimal objective that an
     independent interior-point solver (HiGHS, stored under tests/golden/) found for it."""
