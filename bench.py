@@ -249,6 +249,8 @@ def batch_leg(count, stream, parent="mixed"):
                seq_solved=int(sum(i.term == "solved" for i in seq)),
                worst_rel_kkt_fp64_eval=worst, setup_s=round(setup, 2),
                iters_min=int(iters.min()), iters_median=int(np.median(iters)), iters_max=int(iters.max()),
+               lp_time_to_stop_s=[round(float(q), 4) for q in np.percentile([i.solve_s for i in infos],
+                                                                            [0, 50, 90, 100])],
                iters_total=int(iters.sum()), warmed_up=not big)
     log(f"batch: {out}")
     return out

@@ -150,7 +150,9 @@ typedef struct {
     double rel_p, rel_d, rel_gap, rel_kkt;   /* relative KKT residuals, FP64 */
     double lambda, sigma;       /* step constant used and final sigma */
     double setup_s;             /* hpr_create: scaling, transfer, power method */
-    double solve_s;             /* hpr_solve wall time */
+    double solve_s;             /* hpr_solve wall time; for a member of a batch, the time from the
+                                   start of hpr_batch_solve to the check at which that LP stopped
+                                   (the whole call for members still running at its end) */
     int32_t warm_start;         /* 1: started from the point of hpr_set_start, 0: from zero */
 } hpr_info;
 
@@ -219,7 +221,8 @@ int hpr_batch_size(hpr_batch *b, int32_t *count);
 /* As hpr_set_bounds / hpr_set_start for LP i (0-based). */
 int hpr_batch_set_bounds(hpr_batch *b, int32_t i, const double *col_lo, const double *col_hi);
 int hpr_batch_set_start(hpr_batch *b, int32_t i, const double *x0, const double *y0);
-/* Solves every LP; infos has `count` entries (solve_s is the wall time of the batch). */
+/* Solves every LP; infos has `count` entries (solve_s: each LP's time to its stop, at the
+ * granularity of the checks). */
 int hpr_batch_solve(hpr_batch *b, hpr_info *infos);
 /* As hpr_get_solution for LP i. */
 int hpr_batch_get_solution(hpr_batch *b, int32_t i, double *x, double *y, double *z);

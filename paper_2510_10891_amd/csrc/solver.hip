@@ -12,6 +12,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <exception>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -454,6 +457,32 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
     seg[L] = (int32_t)sched.size();
 }
 
+// Runs f(0) .. f(n - 1) on up to `threads` threads; the first exception is rethrown here.
+template <typename F>
+static void parallel_for(int n, int threads, F f) {
+    if (n <= 0) return;
+    threads = std::max(1, std::min(threads, n));
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> errs((size_t)threads);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int i = next++; i < n; i = next++) f(i);
+            } catch (...) {
+                errs[t] = std::current_exception();
+            }
+        });
+    for (std::thread& th : pool) th.join();
+    for (std::exception_ptr& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
+static int host_threads() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(8u, hw ? hw : 1u));
+}
+
 struct DevMatrix {
     DBuf start, col, col16, rows, sched, seg, val64, val32;
     DBuf sched_act, seg_act;                 // compacted schedule: the blocks of running LPs only
@@ -469,26 +498,30 @@ struct DevMatrix {
     int32_t nrows = 0, nblocks = 0, nblocks_act = 0, unroll = 4, nontemporal = 0;
     bool use_act = false;
     int64_t padded = 0;
-    void upload_from(const Layout& L, const std::vector<int64_t>& lp_rows_in, int64_t ncols_in, bool fp32,
-                     int lds_windows, hipStream_t st) {
+    std::vector<uint16_t> c16;               // 16-bit offsets between host preparation and upload
+    // host part of the upload (no HIP calls; A and A^T are prepared on two threads)
+    void prepare(const Layout& L, const std::vector<int64_t>& lp_rows_in, int64_t ncols_in, bool fp32,
+                 int lds_windows) {
         nrows = (int32_t)L.start.size() - 1;
         ncols = ncols_in;
         win_mode = lds_windows < 0 ? 2 : lds_windows;
         padded = (int64_t)L.col.size();
         start_h = L.start;
         lp_rows = lp_rows_in;
+        short_indices(L, c16, base_h, top_h, wide_h);
+        win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
+        count_tiles(L, win_max / 2);
+    }
+    void upload_from(const Layout& L, bool fp32, hipStream_t st) {
         if (padded / kVec >= INT32_MAX) {
             fail(HPR_ERR_INVALID, "matrix too large: more than 2^33 stored entries");
             throw HipError{HPR_ERR_INVALID};
         }
-        std::vector<uint16_t> c16;
-        short_indices(L, c16, base_h, top_h, wide_h);
-        win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
-        count_tiles(L, win_max / 2);
         upload(start, L.start, st);
         upload(col, L.col, st);
         upload(col16, c16, st);
-        sync_stream(st);   // c16 is local
+        sync_stream(st);
+        std::vector<uint16_t>().swap(c16);
         upload(val64, L.val, st);
         if (fp32) {
             val32.alloc(L.val.size() * sizeof(float));
@@ -520,6 +553,25 @@ struct DevMatrix {
         std::vector<int32_t> seg;
     };
     std::vector<Built> built;
+    // builds the host schedules of the given (U, window mode) pairs that are not built yet,
+    // on several threads (host only)
+    void prebuild(const std::vector<std::pair<int, int>>& cands, int threads) {
+        std::vector<size_t> todo;
+        for (const auto& c : cands) {
+            bool have = false;
+            for (const Built& x : built) have = have || (x.U == c.first && x.mode == c.second);
+            for (size_t t : todo) have = have || (built[t].U == c.first && built[t].mode == c.second);
+            if (!have) {
+                built.push_back(Built{c.first, c.second, {}, {}, {}});
+                todo.push_back(built.size() - 1);
+            }
+        }
+        parallel_for((int)todo.size(), threads, [&](int i) {
+            Built& b = built[todo[i]];
+            make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, b.U, b.mode >= 1 ? win_max : 0,
+                          b.mode == 2, b.rows, b.sched, b.seg);
+        });
+    }
     void set_unroll(int U, hipStream_t st) {
         const Built* b = nullptr;
         for (const Built& x : built)
@@ -614,6 +666,7 @@ struct Engine {
     hpr_kernel_stats kstats{};
     bool solved_once = false;
     double setup_s = 0, solve_s = 0;
+    std::vector<double> done_at;             // per LP: seconds into the solve when it stopped
     std::vector<int32_t> warm_used, use_start_mask;   // per LP: solve started from the caller's point
 
     ~Engine() {
@@ -816,6 +869,11 @@ static void autotune(Engine* e) {
                 cand.push_back(Cand{U, Mx.win_mode, 1e30f});
             }
         }
+        {
+            std::vector<std::pair<int, int>> pairs;
+            for (const Cand& c : cand) pairs.emplace_back(c.U, c.mode);
+            Mx.prebuild(pairs, host_threads());
+        }
         for (int round = 0; round < 3; ++round)
             for (Cand& c : cand) {
                 Mx.win_mode = c.mode;
@@ -927,6 +985,49 @@ static void power_method(Engine* e) {
     }
 }
 
+// Host preparation of one LP: scaling and the padded layouts of A~ and A~^T (independent per
+// LP, so a batch prepares several LPs at once; a single LP builds A~'s layout while the
+// transpose is formed).
+struct PrepLp {
+    LpHost h;
+    Layout la, lt;
+};
+
+static void prep_lp(const hpr_lp* lp, const hpr_opts& o, PrepLp& p, bool two_threads) {
+    HostCsr a;
+    a.rows = lp->m;
+    a.cols = lp->n;
+    if (lp->m > 0) a.ptr.assign(lp->row_ptr, lp->row_ptr + lp->m + 1);
+    else a.ptr.assign(1, 0);
+    a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
+    a.val.assign(lp->val, lp->val + lp->nnz);
+    scale_host(lp, o, a, p.h);
+    HostCsr at;
+    if (two_threads) {
+        std::exception_ptr err;
+        std::thread th([&] {
+            try {
+                p.la = make_layout(a);
+            } catch (...) {
+                err = std::current_exception();
+            }
+        });
+        try {
+            at = transpose(a);
+        } catch (...) {
+            th.join();
+            throw;
+        }
+        th.join();
+        if (err) std::rethrow_exception(err);
+    } else {
+        p.la = make_layout(a);
+        at = transpose(a);
+    }
+    a = HostCsr();            // free the scaled copy before the transpose's layout
+    p.lt = make_layout(at);
+}
+
 static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, Engine** out) {
     g_err.clear();
     if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
@@ -967,31 +1068,29 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
         PA.start.assign(1, 0);
         PAt.start.assign(1, 0);
         std::vector<int64_t> rows_a(1, 0), rows_at(1, 0);
-        for (int l = 0; l < count; ++l) {
-            const hpr_lp* lp = &lps[l];
-            LpHost& h = e->lps[l];
-            h.m = lp->m;
-            h.n = lp->n;
-            h.nnz = lp->nnz;
-            h.row_off = e->M;
-            h.col_off = e->N;
-            HostCsr a;
-            a.rows = lp->m;
-            a.cols = lp->n;
-            if (lp->m > 0) a.ptr.assign(lp->row_ptr, lp->row_ptr + lp->m + 1);
-            else a.ptr.assign(1, 0);
-            a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
-            a.val.assign(lp->val, lp->val + lp->nnz);
-            scale_host(lp, o, a, h);
-            Layout la = make_layout(a);
-            {
-                const HostCsr at = transpose(a);
-                a = HostCsr();            // free the scaled copy before the transpose's layout
-                Layout lt = make_layout(at);
+        const int threads = host_threads();
+        const int chunk = count == 1 ? 1 : threads;
+        for (int c0 = 0; c0 < count; c0 += chunk) {
+            const int c1 = std::min(count, c0 + chunk);
+            std::vector<PrepLp> prep((size_t)(c1 - c0));
+            if (count == 1) prep_lp(&lps[0], o, prep[0], threads > 1);
+            else parallel_for(c1 - c0, threads, [&](int i) { prep_lp(&lps[c0 + i], o, prep[i], false); });
+            for (int l = c0; l < c1; ++l) {
+                const hpr_lp* lp = &lps[l];
+                PrepLp& p = prep[l - c0];
+                LpHost& h = e->lps[l];
+                h = std::move(p.h);
+                h.m = lp->m;
+                h.n = lp->n;
+                h.nnz = lp->nnz;
+                h.row_off = e->M;
+                h.col_off = e->N;
                 if (count == 1) {         // one LP: the layouts are the pools
-                    PA = std::move(la);
-                    PAt = std::move(lt);
+                    PA = std::move(p.la);
+                    PAt = std::move(p.lt);
                 } else {                  // append with global column indices
+                    const Layout& la = p.la;
+                    const Layout& lt = p.lt;
                     const int64_t base_a = PA.start.back(), base_t = PAt.start.back();
                     PA.start.reserve(PA.start.size() + lp->m);
                     PAt.start.reserve(PAt.start.size() + lp->n);
@@ -1004,19 +1103,25 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
                     for (size_t k = 0; k < lt.col.size(); ++k) PAt.col[ct + k] = lt.col[k] + (int32_t)h.row_off;
                     PA.val.insert(PA.val.end(), la.val.begin(), la.val.end());
                     PAt.val.insert(PAt.val.end(), lt.val.begin(), lt.val.end());
+                    p.la = Layout();
+                    p.lt = Layout();
+                }
+                e->M += lp->m;
+                e->N += lp->n;
+                rows_a.push_back(e->M);
+                rows_at.push_back(e->N);
+                if (e->M > INT32_MAX || e->N > INT32_MAX) {
+                    fail(HPR_ERR_INVALID, "pooled rows or columns exceed 2^31");
+                    throw HipError{HPR_ERR_INVALID};
                 }
             }
-            e->M += lp->m;
-            e->N += lp->n;
-            rows_a.push_back(e->M);
-            rows_at.push_back(e->N);
-            if (e->M > INT32_MAX || e->N > INT32_MAX) {
-                fail(HPR_ERR_INVALID, "pooled rows or columns exceed 2^31");
-                throw HipError{HPR_ERR_INVALID};
-            }
         }
-        e->A.upload_from(PA, rows_a, e->N, e->fp32, o.lds_windows, e->st);
-        e->At.upload_from(PAt, rows_at, e->M, e->fp32, o.lds_windows, e->st);
+        parallel_for(2, threads, [&](int i) {
+            if (i == 0) e->A.prepare(PA, rows_a, e->N, e->fp32, o.lds_windows);
+            else e->At.prepare(PAt, rows_at, e->M, e->fp32, o.lds_windows);
+        });
+        e->A.upload_from(PA, e->fp32, e->st);
+        e->At.upload_from(PAt, e->fp32, e->st);
         e->sync();
         upload_vectors(e.get());
         alloc_iterates(e.get());
@@ -1303,6 +1408,8 @@ void solve_loop(Engine* e, double t0) {
         for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
     int64_t it = 0, blocks = 0;
     int32_t launched = e->L;   // LPs whose blocks the current schedules launch
+    int32_t seen_running = e->L;
+    e->done_at.assign(e->L, -1.0);
     while (true) {
         const int nb = (int)((it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it));
         const bool sample = o.profile && nb >= 2 && (blocks % 4 == 1);
@@ -1330,6 +1437,14 @@ void solve_loop(Engine* e, double t0) {
         if (running > 0 && o.time_limit_s > 0 && now_s() - t0 > o.time_limit_s) {
             launch_control(control_args(e, 4, 0), e->st);
             running = read_stat(e, 0);
+        }
+        if (e->L > 1 && running < seen_running) {   // per-LP time to its stop, at check granularity
+            HIP_OK(hipMemcpyAsync(e->ctrl_h.data(), e->ctrl.p, sizeof(Ctrl) * e->L, hipMemcpyDeviceToHost, e->st));
+            e->sync();
+            const double t = now_s() - t0;
+            for (int l = 0; l < e->L; ++l)
+                if (!e->ctrl_h[l].active && e->done_at[l] < 0) e->done_at[l] = t;
+            seen_running = running;
         }
         if (running == 0 || it >= o.max_iter) break;
         if (e->L > 1 && 2 * running <= launched) {
@@ -1386,7 +1501,7 @@ static int engine_solve(Engine* e, hpr_info* infos) {
         info.lambda = e->lps[l].lambda;
         info.sigma = e->ctrl_h[l].sigma;
         info.setup_s = e->setup_s;
-        info.solve_s = e->solve_s;
+        info.solve_s = (e->L > 1 && e->done_at[l] >= 0) ? e->done_at[l] : e->solve_s;
         info.warm_start = e->warm_used.empty() ? 0 : e->warm_used[l];
     }
     return HPR_OK;

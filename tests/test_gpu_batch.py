@@ -132,3 +132,27 @@ def test_warm_start_fallback_rejects_a_bad_start():
     assert ib.warm_start == 0 and ib.iters == cold.iters and np.array_equal(xb, xc)
     good, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-6, max_iter=200000, unroll=4), x0=xc, y0=yc)
     assert good.warm_start == 1 and good.iters < cold.iters
+
+
+def test_per_lp_time_to_stop_follows_the_checks():
+    """hpr_info.solve_s of a batch member is the time to the check at which it stopped: within
+    the call's wall time, equal for LPs that stop at the same check, and ordered like the
+    iteration counts otherwise."""
+    import time
+    lps = [scuc.make_instance("small", s)[1] for s in range(6)]
+    b = hprlp.hpr_batch_create(lps, hprlp.Options(tol=1e-4, max_iter=200000))
+    try:
+        t0 = time.perf_counter()
+        infos = hprlp.hpr_batch_solve(b)
+        wall = time.perf_counter() - t0
+    finally:
+        hprlp.hpr_batch_destroy(b)
+    assert all(i.term == "solved" for i in infos)
+    for i in infos:
+        assert 0.0 < i.solve_s <= wall
+    for a in infos:
+        for c in infos:
+            if a.iters == c.iters:
+                assert a.solve_s == c.solve_s
+            elif a.iters < c.iters:
+                assert a.solve_s <= c.solve_s
