@@ -34,6 +34,7 @@ struct BlockDesc {
     int32_t wlen;
 };
 constexpr int kWinBytes = 16384;   // LDS per block for a staged window
+constexpr int kXcds = 8;           // accelerator complex dies of the MI355X, each with its own L2
 
 // One entry of a schedule's row list, fetched by one 16-byte load: the row, its number of
 // quads (4 stored entries; the top bit marks a "wide" row), the smallest column of the row

@@ -362,6 +362,23 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
 // The work list of one pooled matrix for U quads per lane and pass: per LP, per bin (bin b:
 // rows of at most U * 2^b quads, 2^b lanes each; the last bin takes longer rows too), the
 // rows in index order cut into blocks of kBlock / 2^b rows. seg[l] = first block of LP l.
+// The hardware hands consecutive thread blocks to the XCDs in turn (block i to XCD i mod 8).
+// Reorders the blocks sched[first ..] (one bin of one LP, neighbouring rows in order) so that
+// each XCD receives one contiguous eighth of them: rows of one XCD then gather from one stretch
+// of the vector, which its own L2 holds, and every XCD still gets an equal share of the bin.
+static void deal_to_xcds(std::vector<BlockDesc>& sched, size_t first) {
+    const size_t n = sched.size() - first;
+    if (n < 2 * (size_t)kXcds) return;
+    std::vector<BlockDesc> part(sched.begin() + (std::ptrdiff_t)first, sched.end());
+    size_t out = first;
+    const size_t len = (n + kXcds - 1) / kXcds;      // blocks per eighth (the last may be short)
+    for (size_t k = 0; k < len; ++k)
+        for (size_t p = 0; p < (size_t)kXcds; ++p) {
+            const size_t i = p * len + k;
+            if (k < len && i < n && i < (p + 1) * len) sched[out++] = part[i];
+        }
+}
+
 // Per row, the number of stored entries in each aligned tile of `tile` columns it touches.
 struct TileCounts {
     int32_t tile = 0;
@@ -398,6 +415,7 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
         }
         for (int b = 0; b < kNumBins; ++b) {
             const int per_block = kBlock >> b;
+            const size_t bin_first = sched.size();
             for (size_t k = 0; k < by_bin[b].size(); k += per_block) {
                 BlockDesc d;
                 d.bin = b;
@@ -452,6 +470,7 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 }
                 sched.push_back(d);
             }
+            deal_to_xcds(sched, bin_first);
         }
     }
     seg[L] = (int32_t)sched.size();
