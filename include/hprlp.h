@@ -158,8 +158,9 @@ typedef struct {
 
 /* Kernel timings of the last hpr_solve with hpr_opts.profile = 1: average duration of
  * the fused primal step (A^T product, box projection, Halpern averaging) and of the
- * fused dual step (A product, row projection, Halpern averaging), measured with HIP
- * events on the solve's stream around sampled non-check iterations. */
+ * fused dual step (A product, row projection, Halpern averaging) in sampled non-check
+ * iterations (every fourth block), from HIP events that the launch stamps at each sampled
+ * kernel's own start and end (hipExtLaunchKernelGGL) on the solve's stream. */
 typedef struct {
     double primal_ms;
     double dual_ms;

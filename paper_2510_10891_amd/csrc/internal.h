@@ -102,13 +102,15 @@ struct DevIter {
     Tv *y, *y0, *yb, *dy;             // [m] iterate, anchor, bar point, y - ybar
 };
 
-// Launchers (kernels.hip). All run on `st` and may be captured into a graph.
+// Launchers (kernels.hip). All run on `st` and may be captured into a graph; the fused steps
+// take optional start/stop events stamped at the kernel's own start and end (timing runs only,
+// not under capture).
 template <typename T>
 void launch_primal_step(const DevCsr<T>& At, const DevProb<T>& p, const DevIter<T>& v, const Ctrl* ctrl,
-                        int j, bool check, hipStream_t st);
+                        int j, bool check, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 template <typename T>
 void launch_dual_step(const DevCsr<T>& A, const DevProb<T>& p, const DevIter<T>& v, const Ctrl* ctrl,
-                      int j, bool check, hipStream_t st);
+                      int j, bool check, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Check kernels: per-block FP64 partial sums into partials [quantity][nblocks].
 template <typename Tm, typename Tp, typename Tv>
 void launch_check_rows(const DevCsr<Tm>& A, const DevProb<Tp>& p, const DevIter<Tv>& v, const Ctrl* ctrl,

@@ -9,6 +9,8 @@
 // schedule (G per row and U per matrix).
 #include "internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 #include <type_traits>
@@ -281,23 +283,32 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
 
+// With start/stop events (timing runs only, never under capture) the kernel is launched through
+// hipExtLaunchKernelGGL, which stamps the events at the dispatch's own start and end.
+template <typename Op, int U, bool NT>
+static void launch_csr_variant(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start,
+                               hipEvent_t stop) {
+    if (start) hipExtLaunchKernelGGL((csr_kernel<Op, U, NT>), dim3(A.nblocks), dim3(kBlock), 0, st, start, stop, 0, A, op);
+    else hipLaunchKernelGGL((csr_kernel<Op, U, NT>), dim3(A.nblocks), dim3(kBlock), 0, st, A, op);
+}
+
 template <typename Op>
-static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st) {
-    const int nb = A.nblocks;
-    if (nb <= 0) return;
+static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr) {
+    if (A.nblocks <= 0) return;
     if (A.nontemporal) {
         switch (A.unroll) {
-            case 1: hipLaunchKernelGGL((csr_kernel<Op, 1, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            case 2: hipLaunchKernelGGL((csr_kernel<Op, 2, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            case 8: hipLaunchKernelGGL((csr_kernel<Op, 8, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            default: hipLaunchKernelGGL((csr_kernel<Op, 4, true>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 1: launch_csr_variant<Op, 1, true>(A, op, st, start, stop); break;
+            case 2: launch_csr_variant<Op, 2, true>(A, op, st, start, stop); break;
+            case 8: launch_csr_variant<Op, 8, true>(A, op, st, start, stop); break;
+            default: launch_csr_variant<Op, 4, true>(A, op, st, start, stop); break;
         }
     } else {
         switch (A.unroll) {
-            case 1: hipLaunchKernelGGL((csr_kernel<Op, 1, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            case 2: hipLaunchKernelGGL((csr_kernel<Op, 2, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            case 8: hipLaunchKernelGGL((csr_kernel<Op, 8, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
-            default: hipLaunchKernelGGL((csr_kernel<Op, 4, false>), dim3(nb), dim3(kBlock), 0, st, A, op); break;
+            case 1: launch_csr_variant<Op, 1, false>(A, op, st, start, stop); break;
+            case 2: launch_csr_variant<Op, 2, false>(A, op, st, start, stop); break;
+            case 8: launch_csr_variant<Op, 8, false>(A, op, st, start, stop); break;
+            default: launch_csr_variant<Op, 4, false>(A, op, st, start, stop); break;
         }
     }
 }
@@ -849,7 +860,7 @@ __global__ void cast_kernel(const double* s, T* d, int64_t n) {
 
 template <typename T>
 void launch_primal_step(const DevCsr<T>& At, const DevProb<T>& p, const DevIter<T>& v, const Ctrl* ctrl,
-                        int j, bool check, hipStream_t st) {
+                        int j, bool check, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
     PrimalOp<T> op{};
     op.g0 = v.y;
     op.p = p;
@@ -857,12 +868,12 @@ void launch_primal_step(const DevCsr<T>& At, const DevProb<T>& p, const DevIter<
     op.ctrl = ctrl;
     op.j = j;
     op.check = check ? 1 : 0;
-    launch_csr(At, op, st);
+    launch_csr(At, op, st, start, stop);
 }
 
 template <typename T>
 void launch_dual_step(const DevCsr<T>& A, const DevProb<T>& p, const DevIter<T>& v, const Ctrl* ctrl,
-                      int j, bool check, hipStream_t st) {
+                      int j, bool check, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
     DualOp<T> op{};
     op.g0 = v.xh;
     op.p = p;
@@ -870,7 +881,7 @@ void launch_dual_step(const DevCsr<T>& A, const DevProb<T>& p, const DevIter<T>&
     op.ctrl = ctrl;
     op.j = j;
     op.check = check ? 1 : 0;
-    launch_csr(A, op, st);
+    launch_csr(A, op, st, start, stop);
 }
 
 template <typename Tm, typename Tp, typename Tv>
@@ -978,9 +989,9 @@ void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st) {
 
 #define HPR_INST(T)                                                                                          \
     template void launch_primal_step<T>(const DevCsr<T>&, const DevProb<T>&, const DevIter<T>&, const Ctrl*, \
-                                        int, bool, hipStream_t);                                             \
+                                        int, bool, hipStream_t, hipEvent_t, hipEvent_t);                     \
     template void launch_dual_step<T>(const DevCsr<T>&, const DevProb<T>&, const DevIter<T>&, const Ctrl*,   \
-                                      int, bool, hipStream_t);                                               \
+                                      int, bool, hipStream_t, hipEvent_t, hipEvent_t);                       \
     template void launch_spmv<T>(const DevCsr<T>&, const T*, T*, hipStream_t);                              \
     template void launch_restart<T>(const DevCsr<T>&, const DevCsr<T>&, const DevIter<T>&, const Ctrl*,      \
                                     hipStream_t);                                                            \
