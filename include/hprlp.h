@@ -125,9 +125,12 @@ typedef struct {
                                    most 16 KB of vector entries copies them into LDS first);
                                    2 = full and "split" windows (the two aligned 8 KB tiles
                                    holding most of a block's entries, the rest read from global
-                                   memory); -1 (default) = full windows, split windows picked per
-                                   matrix by timing at hpr_create (on when unroll is given).
-                                   Results do not depend on it. */
+                                   memory); 3 = full, split and "sliced" windows (a block walks
+                                   up to 8 consecutive 16 KB windows one at a time, entries
+                                   outside them read from global memory); -1 (default) = the
+                                   mode 1, 2 or 3 picked per matrix by timing at hpr_create
+                                   (2 when unroll is given). Results agree to rounding across
+                                   modes; modes 0, 1 and 2 sum in the same order. */
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
                                    its check and its control step as one captured HIP graph;
                                    0: launch every kernel directly */
@@ -175,6 +178,8 @@ typedef struct {
     int32_t split_blocks_at;
     int32_t blocks_a;           /* all thread blocks of A's schedule */
     int32_t blocks_at;
+    int32_t sliced_blocks_a;    /* thread blocks of A's schedule with sliced windows */
+    int32_t sliced_blocks_at;
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

@@ -22,9 +22,16 @@ constexpr int kChunk = 8192;     // entries per block of the segmented vector ke
 constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 
 // One thread block of a matrix product: rows list[first .. first + count) of bin `bin`
-// (2^bin lanes per row), all belonging to LP `lp`. When wlen > 0, every column the block's
-// rows use lies in [wlo, wlo + wlen) and the block first copies that window of the gathered
-// vector into LDS (products with one gathered vector).
+// (2^bin lanes per row), all belonging to LP `lp`. LDS windows of the gathered vector (products
+// with one gathered vector):
+//   wlen > 0: "full", every column the block's rows use lies in [wlo, wlo + wlen);
+//   wlen < 0: "split", the window [wlo, wlo - wlen) holds most of them, the rest are read from
+//             global memory;
+//   ns > 0:   "sliced", the block walks ns consecutive windows of slice_w columns from wlo, one
+//             at a time in LDS; row r of the block has its entries below the k-th window's first
+//             column counted in slice_cum[cum_first + r * (ns + 1) + k] (k = 0 .. ns; the rows'
+//             entries are in column order), entries outside all windows are read from global
+//             memory.
 struct BlockDesc {
     int32_t bin;
     int32_t lp;
@@ -32,7 +39,10 @@ struct BlockDesc {
     int32_t count;
     int32_t wlo;
     int32_t wlen;
+    int32_t ns;
+    int32_t cum_first;
 };
+constexpr int kMaxSlices = 8;       // windows per sliced block
 constexpr int kWinBytes = 16384;   // LDS per block for a staged window
 constexpr int kXcds = 8;           // accelerator complex dies of the MI355X, each with its own L2
 
@@ -59,6 +69,10 @@ struct DevCsr {
     const Tm* val;             // [padded nnz]
     const RowRef* rows;        // row list in schedule order
     const BlockDesc* sched;    // [nblocks]
+    const int32_t* slice_cum;  // per sliced block and row: entries below each window (BlockDesc)
+    int32_t slice_w;           // columns per window of a sliced block
+    int32_t ncols;             // length of the gathered vector
+    int32_t has_sliced;        // 1: some block of the schedule is sliced
     int32_t nblocks;
     int32_t unroll;            // U: 1, 2, 4 or 8 quads per lane and pass
     int32_t nontemporal;       // 1: stream the matrix with non-temporal loads

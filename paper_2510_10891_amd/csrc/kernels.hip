@@ -143,6 +143,46 @@ struct FromSplit {
     }
 };
 
+// Copies src[lo, lo + len) into the block's LDS window (16-byte copies when lo allows it; the
+// vector's base is 256-byte aligned).
+template <typename Tx>
+__device__ __forceinline__ void copy_window(Tx* win, const Tx* src, int lo, int len) {
+    constexpr int kPer = 16 / (int)sizeof(Tx);   // entries per 16-byte load
+    int t0 = 0;
+    if (lo % kPer == 0) {
+        const int n16 = len / kPer;
+        const int4* s16 = reinterpret_cast<const int4*>(src + lo);
+        int4* d16 = reinterpret_cast<int4*>(win);
+        for (int t = threadIdx.x; t < n16; t += kBlock) d16[t] = s16[t];
+        t0 = n16 * kPer;
+    }
+    for (int t = t0 + threadIdx.x; t < len; t += kBlock) win[t] = src[lo + t];
+}
+
+// Sliced blocks: one window [lo, lo + len) in LDS, entries of other columns count 0 in this
+// pass; and the pass over the entries outside all windows, read from global memory.
+template <typename Tx>
+struct FromSlice {
+    LdsPtr<Tx> w;
+    int lo, len;
+    __device__ __forceinline__ Tx operator()(int c) const {
+        const unsigned r = (unsigned)(c - lo);
+        const bool in = r < (unsigned)len;
+        const Tx x = w[in ? r : 0u];
+        return in ? x : Tx(0);
+    }
+};
+template <typename Tx>
+struct FromOutside {
+    const Tx* __restrict__ g;
+    int lo, hi;
+    __device__ __forceinline__ Tx operator()(int c) const {
+        Tx x = Tx(0);
+        if (c < lo || c >= hi) x = g[c];
+        return x;
+    }
+};
+
 // Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
 // group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
 // before any gather so U 16-byte loads per array are in flight per lane.
@@ -214,6 +254,76 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
     if (active && lane == 0) op.epi(row, s0, s1);
 }
 
+// Sliced block (BlockDesc.ns > 0): the block walks its windows one at a time (copy into LDS,
+// every row's entries of that window, which are a contiguous range of quads since the row is
+// in column order; a quad that straddles two windows is read in both passes and each entry
+// counted in its own), then one pass over the quads before and after all windows with the
+// entries outside them read from global memory.
+template <int G, int U, bool NT, typename Op, typename Tx>
+__device__ __forceinline__ void run_bin_sliced(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                               Tx* win) {
+    using Acc = typename Op::Acc;
+    const int lane = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const bool active = grp < d.count;
+    const RowRef rr = active ? A.rows[d.first + grp] : RowRef{0, 0, 0, 0};
+    const int row = rr.row;
+    const bool wide = (rr.quads & kWide) != 0;
+    const int quads = rr.quads & ~kWide;
+    const int64_t b = (int64_t)kVec * rr.start4;
+    const int32_t* cum = A.slice_cum + d.cum_first + (active ? grp : 0) * (d.ns + 1);
+    if (active && lane == 0) op.pre(row);
+    Acc s0 = Acc(0), part = Acc(0), unused = Acc(0);
+    const int W = A.slice_w;
+    for (int k = 0; k < d.ns; ++k) {
+        const int lo = d.wlo + k * W;
+        const int len = max(0, min(W, A.ncols - lo));
+        __syncthreads();                       // the previous window is no longer read
+        copy_window(win, op.g0, lo, len);
+        __syncthreads();
+        if (active) {
+            const int qa = cum[k] >> 2, qb = min(quads, (cum[k + 1] + 3) >> 2);
+            if (qb > qa) {
+                const FromSlice<Tx> src{(LdsPtr<Tx>)win, lo, len};
+                if (wide) group_dot<G, U, NT, true, 1>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
+                else group_dot<G, U, NT, false, 1>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
+                s0 += part;
+            }
+        }
+    }
+    if (active) {
+        const FromOutside<Tx> src{op.g0, d.wlo, d.wlo + d.ns * W};
+        const int q_low = min(quads, (cum[0] + 3) >> 2), q_high = cum[d.ns] >> 2;
+        if (q_low > 0) {
+            if (wide) group_dot<G, U, NT, true, 1>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
+            else group_dot<G, U, NT, false, 1>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
+            s0 += part;
+        }
+        if (q_high < quads) {
+            const int qa = max(q_high, q_low);   // a quad below every window is not read twice
+            if (wide) group_dot<G, U, NT, true, 1>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
+            else group_dot<G, U, NT, false, 1>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
+            s0 += part;
+        }
+    }
+    s0 = group_sum<G>(s0);
+    if (active && lane == 0) op.epi(row, s0, Acc(0));
+}
+
+template <int U, bool NT, typename Op, typename Tx>
+__device__ __forceinline__ void run_block_sliced(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                                 Tx* win) {
+    switch (d.bin) {
+        case 0: run_bin_sliced<1, U, NT>(A, op, d, win); break;
+        case 1: run_bin_sliced<2, U, NT>(A, op, d, win); break;
+        case 2: run_bin_sliced<4, U, NT>(A, op, d, win); break;
+        case 3: run_bin_sliced<8, U, NT>(A, op, d, win); break;
+        case 4: run_bin_sliced<16, U, NT>(A, op, d, win); break;
+        case 5: run_bin_sliced<32, U, NT>(A, op, d, win); break;
+        default: run_bin_sliced<64, U, NT>(A, op, d, win); break;
+    }
+}
+
 template <int U, bool NT, int MODE, typename Op, typename Tx>
 __device__ __forceinline__ void run_block(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
                                           const Tx* win) {
@@ -251,7 +361,9 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
 // most of them), for an op with one gathered vector and a window that fits kWinBytes, copies
 // the window into LDS with coalesced loads and gathers from there: the same values in the same
 // order, so the result does not depend on which path a block takes.
-template <typename Op, int U, bool NT>
+// SL: the schedule has sliced blocks. A separate instantiation, so that schedules without them
+// keep the register budget (and occupancy) of the simpler paths.
+template <typename Op, int U, bool NT, bool SL>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
     using Tx = typename std::remove_cv<typename std::remove_pointer<decltype(op_in.g0)>::type>::type;
     const BlockDesc d = A.sched[blockIdx.x];
@@ -262,17 +374,17 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
         constexpr int kWinElems = kWinBytes / (int)sizeof(Tx);
         __shared__ __align__(16) Tx win[kWinElems];
         const int len = d.wlen < 0 ? -d.wlen : d.wlen;
-        if (len > 0 && len <= kWinElems) {
-            constexpr int kPer = 16 / (int)sizeof(Tx);   // entries per 16-byte load
-            int t0 = 0;
-            if (d.wlo % kPer == 0) {   // 16-byte copies (the vector's base is 256-byte aligned)
-                const int n16 = len / kPer;
-                const int4* src = reinterpret_cast<const int4*>(op.g0 + d.wlo);
-                int4* dst = reinterpret_cast<int4*>(win);
-                for (int t = threadIdx.x; t < n16; t += kBlock) dst[t] = src[t];
-                t0 = n16 * kPer;
+        bool sliced = false;
+        if constexpr (SL) {
+            if (d.ns > 0 && A.slice_w <= kWinElems) {
+                run_block_sliced<U, NT>(A, op, d, win);
+                sliced = true;
             }
-            for (int t = t0 + threadIdx.x; t < len; t += kBlock) win[t] = op.g0[d.wlo + t];
+        }
+        if (sliced) {
+            done = true;
+        } else if (len > 0 && len <= kWinElems) {
+            copy_window(win, op.g0, d.wlo, len);
             __syncthreads();
             if (d.wlen > 0) run_block<U, NT, 1>(A, op, d, win);
             else run_block<U, NT, 2>(A, op, d, win);
@@ -285,11 +397,23 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
 
 // With start/stop events (timing runs only, never under capture) the kernel is launched through
 // hipExtLaunchKernelGGL, which stamps the events at the dispatch's own start and end.
+template <typename Op, int U, bool NT, bool SL>
+static void launch_csr_kernel(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start,
+                              hipEvent_t stop) {
+    if (start) hipExtLaunchKernelGGL((csr_kernel<Op, U, NT, SL>), dim3(A.nblocks), dim3(kBlock), 0, st, start, stop, 0, A, op);
+    else hipLaunchKernelGGL((csr_kernel<Op, U, NT, SL>), dim3(A.nblocks), dim3(kBlock), 0, st, A, op);
+}
+
 template <typename Op, int U, bool NT>
 static void launch_csr_variant(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start,
                                hipEvent_t stop) {
-    if (start) hipExtLaunchKernelGGL((csr_kernel<Op, U, NT>), dim3(A.nblocks), dim3(kBlock), 0, st, start, stop, 0, A, op);
-    else hipLaunchKernelGGL((csr_kernel<Op, U, NT>), dim3(A.nblocks), dim3(kBlock), 0, st, A, op);
+    if constexpr (Op::NV == 1) {
+        if (A.has_sliced) {
+            launch_csr_kernel<Op, U, NT, true>(A, op, st, start, stop);
+            return;
+        }
+    }
+    launch_csr_kernel<Op, U, NT, false>(A, op, st, start, stop);
 }
 
 template <typename Op>

@@ -173,15 +173,29 @@ static Layout make_layout(const HostCsr& a) {
     L.start[R] = off;
     L.col.resize(off);
     L.val.resize(off);
+    std::vector<std::pair<int32_t, double>> tmp;
     for (int32_t i = 0; i < R; ++i) {
         int64_t d = L.start[i];
         const int64_t b = a.ptr[i], e = a.ptr[i + 1];
-        for (int64_t k = b; k < e; ++k, ++d) {
-            L.col[d] = a.idx[k];
-            L.val[d] = a.val[k];
+        bool sorted = true;
+        for (int64_t k = b + 1; k < e; ++k) sorted = sorted && a.idx[k - 1] < a.idx[k];
+        if (sorted) {
+            for (int64_t k = b; k < e; ++k, ++d) {
+                L.col[d] = a.idx[k];
+                L.val[d] = a.val[k];
+            }
+        } else {   // entries in column order (the sliced windows rely on it)
+            tmp.clear();
+            for (int64_t k = b; k < e; ++k) tmp.emplace_back(a.idx[k], a.val[k]);
+            std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+            for (const auto& t : tmp) {
+                L.col[d] = t.first;
+                L.val[d] = t.second;
+                ++d;
+            }
         }
-        for (; d < L.start[i + 1]; ++d) {   // padding: value 0 at a column the row uses
-            L.col[d] = a.idx[e - 1];
+        for (; d < L.start[i + 1]; ++d) {   // padding: value 0 at the row's largest column
+            L.col[d] = L.col[d - 1];
             L.val[d] = 0.0;
         }
     }
@@ -243,7 +257,8 @@ static int validate_opts(const hpr_opts* o) {
         return fail(HPR_ERR_INVALID, "sigma_smoothing and sigma_smoothing_warm must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
-    if (o->lds_windows < -1 || o->lds_windows > 2) return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1 or 2");
+    if (o->lds_windows < -1 || o->lds_windows > 3)
+        return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1, 2 or 3");
     return HPR_OK;
 }
 
@@ -386,6 +401,55 @@ struct TileCounts {
     std::vector<int32_t> id, cnt;
 };
 
+// Sliced windows for a block that no single window serves: consecutive aligned windows of
+// win_max columns (two tiles each), walked one at a time. Picks the run of at most kMaxSlices
+// windows that saves the most (entries inside minus a quarter of the columns copied: a copied
+// entry is one lane of a coalesced 16-byte load, a gathered one a scattered 4-byte access), if
+// it holds at least half of the block's entries; then stores, per row, the number of its
+// entries below each window boundary (rows are in column order, padding at the row's largest
+// column).
+static void slice_block(BlockDesc& d, const int32_t* rows_of_block,
+                        const std::vector<std::pair<int32_t, int64_t>>& tiles, const TileCounts& tc, int64_t ncols,
+                        int64_t entries, int32_t win_max, std::vector<int32_t>& cum) {
+    if (tiles.empty() || win_max <= 0) return;
+    const int64_t W = win_max;
+    // entries per window id (tile / 2), windows in increasing order
+    std::vector<std::pair<int64_t, int64_t>> win;
+    for (const auto& t : tiles) {
+        const int64_t j = t.first / 2;
+        if (!win.empty() && win.back().first == j) win.back().second += t.second;
+        else win.emplace_back(j, t.second);
+    }
+    double best_gain = 0.0;
+    int64_t best_j0 = -1, best_ns = 0, best_in = 0;
+    for (size_t a = 0; a < win.size(); ++a) {
+        int64_t in = 0;
+        for (size_t z = a; z < win.size(); ++z) {
+            const int64_t ns = win[z].first - win[a].first + 1;
+            if (ns > kMaxSlices) break;
+            in += win[z].second;
+            const int64_t lo = win[a].first * W;
+            const int64_t copied = std::min<int64_t>(ns * W, ncols - lo);
+            const double gain = (double)in - 0.25 * (double)copied;
+            if (gain > best_gain) best_gain = gain, best_j0 = win[a].first, best_ns = ns, best_in = in;
+        }
+    }
+    if (best_j0 < 0 || 2 * best_in < entries) return;
+    d.wlo = (int32_t)(best_j0 * W);
+    d.ns = (int32_t)best_ns;
+    d.cum_first = (int32_t)cum.size();
+    for (int32_t r = 0; r < d.count; ++r) {
+        const int32_t i = rows_of_block[r];
+        int64_t below = 0;   // entries of row i in tiles before the current boundary
+        int64_t t = tc.ptr[i];
+        for (int64_t k = 0; k <= best_ns; ++k) {
+            const int64_t bound_tile = 2 * (best_j0 + k);
+            while (t < tc.ptr[i + 1] && tc.id[t] < bound_tile) below += tc.cnt[t++];
+            cum.push_back((int32_t)below);
+        }
+    }
+}
+
 // A block gets an LDS window of the gathered vector when its rows' columns span at most
 // win_max entries, no row is wide, and the window is no larger than the block's number of
 // stored entries (so copying it reads less than gathering from global memory would): the
@@ -396,9 +460,11 @@ struct TileCounts {
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
                           const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
                           const TileCounts& tc, int64_t ncols,
-                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split,
-                          std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg) {
+                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
+                          std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg,
+                          std::vector<int32_t>& cum) {
     std::vector<std::pair<int32_t, int64_t>> tiles;
+    cum.clear();
     const int L = (int)lp_rows.size() - 1;
     rows.clear();
     sched.clear();
@@ -436,6 +502,8 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                 }
                 d.wlo = 0;
                 d.wlen = 0;
+                d.ns = 0;
+                d.cum_first = 0;
                 if (whi >= 0) wlo -= wlo % 4;   // 16-byte aligned start for the window copy
                 if (!any_wide && whi >= 0 && whi - wlo + 1 <= win_max && whi - wlo + 1 <= entries) {
                     d.wlo = (int32_t)wlo;
@@ -467,6 +535,8 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
                             d.wlen = -(int32_t)len;
                         }
                     }
+                    if (d.wlen == 0 && sliced)
+                        slice_block(d, by_bin[b].data() + k, tiles, tc, ncols, entries, win_max, cum);
                 }
                 sched.push_back(d);
             }
@@ -503,13 +573,14 @@ static int host_threads() {
 }
 
 struct DevMatrix {
-    DBuf start, col, col16, rows, sched, seg, val64, val32;
+    DBuf start, col, col16, rows, sched, seg, val64, val32, slice_cum;
     DBuf sched_act, seg_act;                 // compacted schedule: the blocks of running LPs only
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
     std::vector<int32_t> base_h, top_h;
     std::vector<uint8_t> wide_h;
     int32_t win_max = 0;                     // LDS window limit in vector entries
-    int32_t win_mode = 2;                    // 0: no windows, 1: full windows, 2: full and split
+    int32_t win_mode = 2;                    // 0: no windows, 1: full, 2: full and split, 3: and sliced
+    int32_t has_sliced = 0;                  // the current schedule has sliced blocks
     TileCounts tiles;
     int64_t ncols = 0;                       // length of the gathered vector
     std::vector<BlockDesc> sched_h;
@@ -570,6 +641,7 @@ struct DevMatrix {
         std::vector<RowRef> rows;
         std::vector<BlockDesc> sched;
         std::vector<int32_t> seg;
+        std::vector<int32_t> cum;
     };
     std::vector<Built> built;
     // builds the host schedules of the given (U, window mode) pairs that are not built yet,
@@ -581,14 +653,14 @@ struct DevMatrix {
             for (const Built& x : built) have = have || (x.U == c.first && x.mode == c.second);
             for (size_t t : todo) have = have || (built[t].U == c.first && built[t].mode == c.second);
             if (!have) {
-                built.push_back(Built{c.first, c.second, {}, {}, {}});
+                built.push_back(Built{c.first, c.second, {}, {}, {}, {}});
                 todo.push_back(built.size() - 1);
             }
         }
         parallel_for((int)todo.size(), threads, [&](int i) {
             Built& b = built[todo[i]];
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, b.U, b.mode >= 1 ? win_max : 0,
-                          b.mode == 2, b.rows, b.sched, b.seg);
+                          b.mode >= 2, b.mode >= 3, b.rows, b.sched, b.seg, b.cum);
         });
     }
     void set_unroll(int U, hipStream_t st) {
@@ -596,9 +668,10 @@ struct DevMatrix {
         for (const Built& x : built)
             if (x.U == U && x.mode == win_mode) b = &x;
         if (!b) {
-            built.push_back(Built{U, win_mode, {}, {}, {}});
+            built.push_back(Built{U, win_mode, {}, {}, {}, {}});
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, U, win_mode >= 1 ? win_max : 0,
-                          win_mode == 2, built.back().rows, built.back().sched, built.back().seg);
+                          win_mode >= 2, win_mode >= 3, built.back().rows, built.back().sched, built.back().seg,
+                          built.back().cum);
             b = &built.back();
         }
         unroll = U;
@@ -606,16 +679,20 @@ struct DevMatrix {
         upload(rows, b->rows, st);
         upload(sched, b->sched, st);
         upload(seg, b->seg, st);
+        if (!b->cum.empty()) upload(slice_cum, b->cum, st);
         HIP_OK(hipStreamSynchronize(st));
         sched_h = b->sched;
         seg_h = b->seg;
+        has_sliced = 0;
+        for (const BlockDesc& d : sched_h) has_sliced |= d.ns > 0 ? 1 : 0;
         use_act = false;
     }
-    void window_counts(int32_t& full, int32_t& split, int32_t& all) const {
-        full = split = 0;
+    void window_counts(int32_t& full, int32_t& split, int32_t& sliced, int32_t& all) const {
+        full = split = sliced = 0;
         for (const BlockDesc& d : sched_h) {
             if (d.wlen > 0) ++full;
             if (d.wlen < 0) ++split;
+            if (d.ns > 0) ++sliced;
         }
         all = (int32_t)sched_h.size();
     }
@@ -654,6 +731,10 @@ struct DevMatrix {
         d.nblocks = use_act ? nblocks_act : nblocks;
         d.unroll = unroll;
         d.nontemporal = nontemporal;
+        d.slice_cum = slice_cum.as<int32_t>();
+        d.slice_w = win_max;
+        d.ncols = (int32_t)ncols;
+        d.has_sliced = has_sliced;
         return d;
     }
 };
@@ -882,8 +963,7 @@ static void autotune(Engine* e) {
         std::vector<Cand> cand;
         for (int U : {1, 2, 4}) {
             if (tune_split) {
-                cand.push_back(Cand{U, 1, 1e30f});
-                cand.push_back(Cand{U, 2, 1e30f});
+                for (int mode : {1, 2, 3}) cand.push_back(Cand{U, mode, 1e30f});
             } else {
                 cand.push_back(Cand{U, Mx.win_mode, 1e30f});
             }
@@ -1560,8 +1640,8 @@ static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     out->unroll_at = e->At.unroll;
     out->nontemporal_a = e->A.nontemporal;
     out->nontemporal_at = e->At.nontemporal;
-    e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->blocks_a);
-    e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->blocks_at);
+    e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->sliced_blocks_a, out->blocks_a);
+    e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->sliced_blocks_at, out->blocks_at);
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;

@@ -49,7 +49,7 @@ class hpr_kernel_stats(C.Structure):
                 ("unroll_a", C.c_int32), ("unroll_at", C.c_int32), ("nontemporal_a", C.c_int32),
                 ("nontemporal_at", C.c_int32), ("full_blocks_a", C.c_int32), ("split_blocks_a", C.c_int32),
                 ("full_blocks_at", C.c_int32), ("split_blocks_at", C.c_int32), ("blocks_a", C.c_int32),
-                ("blocks_at", C.c_int32)]
+                ("blocks_at", C.c_int32), ("sliced_blocks_a", C.c_int32), ("sliced_blocks_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -130,7 +130,8 @@ def _kstats(s: hpr_kernel_stats) -> dict:
     return dict(primal_ms=s.primal_ms, dual_ms=s.dual_ms, samples=s.samples, unroll_a=s.unroll_a,
                 unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at,
                 full_blocks_a=s.full_blocks_a, split_blocks_a=s.split_blocks_a, full_blocks_at=s.full_blocks_at,
-                split_blocks_at=s.split_blocks_at, blocks_a=s.blocks_a, blocks_at=s.blocks_at)
+                split_blocks_at=s.split_blocks_at, blocks_a=s.blocks_a, blocks_at=s.blocks_at,
+                sliced_blocks_a=s.sliced_blocks_a, sliced_blocks_at=s.sliced_blocks_at)
 
 
 def hpr_default_opts() -> hpr_opts:

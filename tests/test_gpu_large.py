@@ -31,6 +31,23 @@ def test_large_fp64_and_fp32_iterates_match_oracle(large):
     assert_close(y, o65.y, 2e-4, "y")
 
 
+def test_large_sliced_windows_match_oracle(large):
+    """The primal step of this instance reads y through sliced LDS windows (a unit's output
+    column meets the 21,000 security rows of its hour): 65 FP64 iterations with lds_windows = 3
+    against the oracle."""
+    lp = large
+    o65 = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=65, lambda_in=1.0))
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=65, lambda_=1.0, lds_windows=3, unroll=2))
+    try:
+        info = hprlp.hpr_solve(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+        ks = hprlp.hpr_get_kernel_stats(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    assert ks["sliced_blocks_at"] > 0
+    assert_parity(o65, info, x, y, z, FP64_RTOL)
+
+
 def test_large_fp32_solve_reaches_tolerance(large):
     lp = large
     info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=60000,

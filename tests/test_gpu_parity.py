@@ -241,30 +241,35 @@ def test_medium_full_size_parity_and_tolerance():
         assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), ev
 
 
+def _run_mode(lp, K, mode, precision):
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=K, unroll=2, lds_windows=mode, lambda_=1.0,
+                                           precision=precision, profile=1))
+    try:
+        info = hprlp.hpr_solve(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+        ks = hprlp.hpr_get_kernel_stats(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    return info, x, y, z, ks
+
+
 @pytest.mark.parametrize("formulation", ["compact", "full"])
 def test_lds_window_modes_agree_bitwise(formulation):
-    """The three gather paths (global memory, full LDS windows, split windows) read the same
-    values in the same order: for a fixed lane schedule the iterates agree bitwise across
-    lds_windows = 0, 1, 2, and with the oracle to rounding (FP64). 2,000-bus matrices, where
-    every mode has blocks to act on (the schedule's block counts say which mode ran)."""
+    """The gather paths global memory, full LDS windows and split windows read the same values
+    in the same order: for a fixed lane schedule the iterates agree bitwise across lds_windows =
+    0, 1, 2, and with the oracle to rounding (FP64). Sliced windows (mode 3) add a straddling
+    quad's entries in two passes, so they agree to rounding. 2,000-bus matrices, where every
+    mode has blocks to act on (the schedule's block counts say which mode ran)."""
     _, lp = scuc.make_instance("medium", 0, formulation=formulation)
     if formulation == "full":
         lp = fixing.presolve_free_singletons(lp).lp
-    precisions = (hprlp.HPR_FP64, hprlp.HPR_FP32) if formulation == "compact" else (hprlp.HPR_FP32,)
+    precisions = (hprlp.HPR_FP64, hprlp.HPR_FP32) if formulation == "compact" else (hprlp.HPR_FP64,)
     K = 65
     o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, lambda_in=1.0)) if formulation == "compact" else None
     for precision in precisions:
         runs = []
         for mode in (0, 1, 2):
-            h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=K, unroll=2, lds_windows=mode, lambda_=1.0,
-                                                   precision=precision, profile=1))
-            try:
-                info = hprlp.hpr_solve(h)
-                x, y, z = hprlp.hpr_get_solution(h)
-                ks = hprlp.hpr_get_kernel_stats(h)
-            finally:
-                hprlp.hpr_destroy(h)
-            runs.append((info, x, y, z, ks))
+            runs.append(_run_mode(lp, K, mode, precision))
         k0, k1, k2 = (r[4] for r in runs)
         assert k0["full_blocks_a"] == k0["split_blocks_a"] == k0["full_blocks_at"] == k0["split_blocks_at"] == 0
         assert k1["split_blocks_a"] == k1["split_blocks_at"] == 0 and k1["full_blocks_a"] > 0
@@ -275,6 +280,12 @@ def test_lds_window_modes_agree_bitwise(formulation):
         if o is not None and precision == hprlp.HPR_FP64:
             info, x, y, z, _ = runs[2]
             assert_parity(o, info, x, y, z, FP64_RTOL)
+        if formulation == "full":
+            info, x, y, z, k3 = _run_mode(lp, K, 3, precision)
+            assert k3["sliced_blocks_a"] > 0
+            assert info.iters == runs[0][0].iters
+            assert_close(x, runs[0][1], FP64_RTOL, "x")
+            assert_close(y, runs[0][2], FP64_RTOL, "y")
 
 
 def test_medium_objective_matches_interior_point_golden():
