@@ -72,12 +72,13 @@ def write_traffic_record(fetch_dir, write_dir, workload="scuc-2000bus-500gen-T48
     mean = lambda v: sum(v) / len(v)
     known = float(1 << 20)   # KiB in 1 GiB
     cf, cw = known / mean(f["stream_copy_kernel"]), known / mean(w["stream_copy_kernel"])
-    # the variant the solve used (most launches); the schedule tuner is timing-based and may pick
-    # another one in the other run, but it always times U = 1, 2, 4 with ordinary loads, so the
-    # record takes the ordinary-load variant with the solve's U from both runs (the variants move
-    # the same bytes: one pass over the matrix per launch)
+    # the variant the solve used (most launches; template arguments: op, U, non-temporal loads,
+    # sliced windows); the schedule tuner is timing-based and may pick another one in the other
+    # run, but it always times U = 1, 2, 4 with ordinary loads, so the record takes the
+    # ordinary-load variant with the solve's U from both runs (the variants move the same bytes:
+    # one pass over the matrix per launch)
     used = max((k for k in f if k.startswith("csr_kernel<DualOp<float>")), key=lambda k: len(f[k]))
-    dual = re.sub(r", (true|false)>$", ", false>", used)
+    dual = re.sub(r", (true|false), (true|false)>$", r", false, \2>", used)
     if dual not in f or dual not in w:
         raise SystemExit(f"{dual} is missing from a counter run")
     fk, wk = mean(f[dual]), mean(w[dual])
