@@ -3,10 +3,12 @@
 // checks (restart, sigma, termination), and small helpers.
 //
 // Every matrix product walks one stored row per group of G lanes (G = 1..64 by row
-// length). A lane loads quads of 4 values and 4 column indices with 16-byte loads, U
-// quads at a time, gathers the vector entries, and the G partial sums are combined with
-// cross-lane shuffles in a fixed order, so results are bitwise repeatable for a given
-// schedule (G per row and U per matrix).
+// length). A lane loads quads of 4 values (one 16-byte load) and their column indices
+// (16-bit offsets from the row's smallest column, or 32-bit indices for rows spanning
+// 65,536 columns or more), U quads at a time, gathers the vector entries (from an LDS
+// window of the vector where the block has one, else from global memory), and the G
+// partial sums are combined with cross-lane moves in a fixed order, so results are bitwise
+// repeatable for a given schedule (G per row, U per matrix, window mode per block).
 #include "internal.h"
 
 #include <hip/hip_ext.h>

@@ -3,7 +3,8 @@
 // An Engine holds one LP or a batch pooled into one block-diagonal problem. Creation
 // validates each LP, scales it (Section III-A: optional Ruiz passes, Pock-Chambolle with
 // alpha = 1, bound/cost normalisation), builds the padded CSR layouts of A~ and A~^T and
-// their block schedules, tunes the schedule, and estimates every LP's
+// their block schedules (lane-group bins, LDS windows of the gathered vectors, XCD dealing;
+// host work on several threads), tunes the schedule by timing, and estimates every LP's
 // lambda = lambda_max(A~A~^T) with the power method on the device. A solve runs blocks of
 // iterations of eq.(hpr); the last iteration of a block writes the bar point, two check
 // kernels reduce the KKT residuals (Theorem 1's residual map, normalised) and the merit in
@@ -12,17 +13,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <exception>
 #include <atomic>
-#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hprlp.h"
