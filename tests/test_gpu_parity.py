@@ -288,6 +288,24 @@ def test_lds_window_modes_agree_bitwise(formulation):
             assert_close(y, runs[0][2], FP64_RTOL, "y")
 
 
+@pytest.mark.parametrize("mode", [0, 1, 3])
+def test_rows_given_out_of_column_order(mode):
+    """CSR rows whose entries are not in column order (allowed by the interface) are stored in
+    column order by the library, which the sliced windows rely on: the same iterates as the
+    oracle on the shuffled input, for every gather path."""
+    lp = wide_lp(1)
+    rng = np.random.default_rng(5)
+    idx, val = lp.col_idx.copy(), lp.val.copy()
+    for i in range(lp.m):
+        a, b = lp.row_ptr[i], lp.row_ptr[i + 1]
+        perm = a + rng.permutation(b - a)
+        idx[a:b], val[a:b] = idx[perm], val[perm]
+    shuffled = lp.replace(col_idx=idx, val=val)
+    o = oracle.solve(shuffled, oracle.Options(tol=0.0, max_iter=130))
+    info, x, y, z = hprlp.solve(shuffled, hprlp.Options(tol=0.0, max_iter=130, lds_windows=mode, unroll=2))
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
 def test_medium_objective_matches_interior_point_golden():
     """The 2,000-bus instance solved to 1e-6 in FP64 reaches the optimal objective that an
     independent interior-point solver (HiGHS, stored under tests/golden/) found for it."""
