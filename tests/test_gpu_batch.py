@@ -156,3 +156,38 @@ def test_per_lp_time_to_stop_follows_the_checks():
                 assert a.solve_s == c.solve_s
             elif a.iters < c.iters:
                 assert a.solve_s <= c.solve_s
+
+
+def spread_lp(seed, m=64, n=12000, row_len=2000):
+    """Rows of 2,000 entries spread over 12,000 columns: a block of 4 such rows (64 lanes each)
+    uses three 4,096-column windows, none of which holds half of its entries, so only sliced
+    windows serve it."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(m), row_len)
+    cols = np.concatenate([np.sort(rng.choice(n, row_len, replace=False)) for _ in range(m)])
+    A = sp.csr_matrix((rng.standard_normal(m * row_len) / np.sqrt(row_len), (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    xf = rng.uniform(-0.5, 0.5, n)
+    ax = A @ xf
+    return scuc.LP(m, n, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.copy(),
+                   ax - rng.uniform(0.1, 1, m), ax + rng.uniform(0.1, 1, m), -np.ones(n), np.ones(n),
+                   rng.standard_normal(n), 0.0)
+
+
+def test_batch_with_sliced_windows_matches_oracle_per_lp():
+    """A batch whose members' rows span many windows (sliced LDS windows, lds_windows = 3) and
+    narrow ones: each member's iterates against the oracle run on that LP alone."""
+    lps = [spread_lp(s) for s in range(3)] + [ragged_lp(s, m=200, n=400) for s in range(2)]
+    opts = hprlp.Options(tol=0.0, max_iter=130, lds_windows=3, unroll=2, profile=1)
+    b = hprlp.hpr_batch_create(lps, opts)
+    try:
+        infos = hprlp.hpr_batch_solve(b)
+        ks = hprlp.hpr_batch_get_kernel_stats(b)
+        sols = [hprlp.hpr_batch_get_solution(b, i) for i in range(len(lps))]
+    finally:
+        hprlp.hpr_batch_destroy(b)
+    assert ks["sliced_blocks_a"] + ks["sliced_blocks_at"] > 0, ks
+    for lp, info, (x, y, z) in zip(lps, infos, sols):
+        o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=130))
+        assert_parity(o, info, x, y, z, FP64_RTOL)
