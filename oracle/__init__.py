@@ -79,6 +79,11 @@ def _load():
         _lib.orc_num_threads.restype = C.c_int
         _lib.orc_start_value.restype = C.c_double
         _lib.orc_start_value.argtypes = [C.c_uint64, C.c_uint64]
+        _lib.orc_solve_trace.restype = C.c_int
+        _lib.orc_restart_rule.restype = C.c_int
+        _lib.orc_restart_rule.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_int64, C.c_int32]
+        _lib.orc_sigma_next.restype = C.c_double
+        _lib.orc_sigma_next.argtypes = [C.c_double] * 5
     return _lib
 
 
@@ -168,6 +173,77 @@ def solve(lp, opts: Options | None = None, x0=None, y0=None) -> Result:
     return Result(x, y[:lp.m], z, TERM[info.term], info.iters, info.restarts, info.pobj, info.dobj,
                   info.rel_p, info.rel_d, info.rel_gap, info.rel_kkt, info.lambda_, info.sigma,
                   info.setup_s, info.solve_s)
+
+
+TRACE_FIELDS = ("it", "k", "r", "r0", "r_prev", "restart", "sigma", "sigma_next", "ndx", "ndy")
+
+
+def solve_trace(lp, opts: Options | None = None, x0=None, y0=None, vec_check: int = -1,
+                cap: int = 100000):
+    """``solve`` that also returns its check trace (test use).
+
+    Returns (result, trace, vecs): trace is a dict of arrays, one entry per check that
+    reached the restart decision (fields TRACE_FIELDS: iteration index, steps since the
+    last restart, merit r, r0 and r_prev before the decision, the decision, sigma before
+    and after it, the norms of the anchor move). vecs is None, or for the check with
+    record index vec_check a dict of the scaled vectors the decision used: x (the
+    step's start), xbar, x0 (the anchor), y, ybar, y0.
+    """
+    lib = _load()
+    opts = opts or Options()
+    p = _Pinned(lp)
+    x0a = _f64(x0) if x0 is not None else None
+    y0a = _f64(y0) if y0 is not None else None
+    o = _opts(opts, x0a, y0a)
+    x, y, z = np.zeros(lp.n), np.zeros(max(lp.m, 1)), np.zeros(lp.n)
+    info = _Info()
+    tr = np.zeros((cap, len(TRACE_FIELDS)))
+    ntr = C.c_int64(0)
+    vecs = np.zeros(3 * (lp.n + lp.m)) if vec_check >= 0 else None
+    rc = lib.orc_solve_trace(C.byref(p.s), C.byref(o), x.ctypes.data_as(C.c_void_p),
+                             y.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p), C.byref(info),
+                             tr.ctypes.data_as(C.c_void_p), C.c_int64(cap), C.byref(ntr),
+                             C.c_int64(vec_check),
+                             vecs.ctypes.data_as(C.c_void_p) if vecs is not None else None)
+    if rc != 0:
+        raise ValueError("oracle rejected the problem or options")
+    res = Result(x, y[:lp.m], z, TERM[info.term], info.iters, info.restarts, info.pobj, info.dobj,
+                 info.rel_p, info.rel_d, info.rel_gap, info.rel_kkt, info.lambda_, info.sigma,
+                 info.setup_s, info.solve_s)
+    tr = tr[:ntr.value]
+    trace = {f: tr[:, i] for i, f in enumerate(TRACE_FIELDS)}
+    vd = None
+    if vecs is not None:
+        n, m = lp.n, lp.m
+        vd = dict(x=vecs[:n], xbar=vecs[n:2 * n], x0=vecs[2 * n:3 * n],
+                  y=vecs[3 * n:3 * n + m], ybar=vecs[3 * n + m:3 * n + 2 * m],
+                  y0=vecs[3 * n + 2 * m:3 * n + 3 * m])
+    return res, trace, vd
+
+
+class RestartRule:
+    """The oracle's restart rule as a state machine (test use): feed one check at a time."""
+
+    def __init__(self, enabled: bool = True):
+        self.state = np.zeros(3)
+        self.enabled = enabled
+
+    def __call__(self, r: float, k: int, done: int) -> bool:
+        return bool(_load().orc_restart_rule(self.state.ctypes.data_as(C.c_void_p), float(r),
+                                             int(k), int(done), int(self.enabled)))
+
+    @property
+    def r0(self) -> float:
+        return float(self.state[0])
+
+    @property
+    def r_prev(self) -> float:
+        return float(self.state[1])
+
+
+def sigma_next(sigma: float, ndx: float, ndy: float, lam: float, w: float = 1.0) -> float:
+    """The oracle's sigma update at a restart, from the norms of the anchor move."""
+    return float(_load().orc_sigma_next(sigma, ndx, ndy, lam, w))
 
 
 def validate(lp) -> bool:

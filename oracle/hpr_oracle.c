@@ -528,6 +528,78 @@ static int certifies_infeasibility(const double c[4]) {
     return c[0] > ORC_INFEAS_TOL * c[1] && c[2] <= ORC_INFEAS_TOL * c[3];
 }
 
+/* ---------------------------------------------------------------- restart and sigma rules */
+
+/*
+ * State of the restart rule between checks: r0 is the merit at the last restart (or at the
+ * first check), r_prev the merit of the previous check; seen = 0 before the first check.
+ */
+typedef struct { double r0, r_prev; int64_t seen; } restart_state;
+
+/*
+ * Restart decision at one check (the paper names restarts without giving the rule; this is
+ * the rule both solvers take). r: the merit of this check; k: steps since the last restart,
+ * counting this check's step; done: all steps so far. The first check only records
+ * r0 = r_prev = r. Later checks restart when
+ *     r <= 0.2 r0   (sufficient decay), or
+ *     r <= 0.8 r0 and r > r_prev   (necessary decay without progress), or
+ *     k >= 0.2 done   (the current run is a large share of the whole solve);
+ * enabled = 0 never restarts. Afterwards r_prev = r, and after a restart r0 = r.
+ */
+static int restart_decide(restart_state *st, double r, int64_t k, int64_t done, int enabled) {
+    if (!st->seen) {
+        st->seen = 1;
+        st->r0 = r;
+        st->r_prev = r;
+        return 0;
+    }
+    int restart = 0;
+    if (enabled) {
+        if (r <= 0.2 * st->r0) restart = 1;
+        else if (r <= 0.8 * st->r0 && r > st->r_prev) restart = 1;
+        else if ((double)k >= 0.2 * (double)done) restart = 1;
+    }
+    if (restart) st->r0 = r;
+    st->r_prev = r;
+    return restart;
+}
+
+/* Test entry: the rule above on a caller-held state [r0, r_prev, seen] (start from zeros). */
+int orc_restart_rule(double *state, double r, int64_t k, int64_t done, int32_t enabled) {
+    restart_state st = {state[0], state[1], (int64_t)state[2]};
+    int d = restart_decide(&st, r, k, done, enabled);
+    state[0] = st.r0;
+    state[1] = st.r_prev;
+    state[2] = (double)st.seen;
+    return d;
+}
+
+/*
+ * sigma at a restart. The bound of Theorem 1 grows with the start's distance in the metric
+ * M = [[I/sigma, A^T], [A, lambda sigma I]]; its diagonal part ||dx||^2/sigma + lambda sigma
+ * ||dy||^2 is smallest at sigma* = ||dx|| / (sqrt(lambda) ||dy||), with (dx, dy) the move of the
+ * anchor. The update follows sigma* in log space with weight w,
+ * log sigma <- (1 - w) log sigma + w log sigma* (w = 1 and 1/2 evaluated without exp/log),
+ * is skipped when either norm is below 1e-12, and is clamped to [1e-4, 1e4].
+ */
+static double sigma_next(double sigma, double ndx, double ndy, double lambda, double w) {
+    if (!(ndx > 1e-12 && ndy > 1e-12)) return sigma;
+    double star = ndx / (sqrt(lambda) * ndy);
+    double next = (w == 1.0)   ? star
+                  : (w == 0.5) ? sqrt(sigma * star)
+                               : exp((1.0 - w) * log(sigma) + w * log(star));
+    return clampd(next, 1e-4, 1e4);
+}
+
+/* Test entry for the sigma update. */
+double orc_sigma_next(double sigma, double ndx, double ndy, double lambda, double w) {
+    return sigma_next(sigma, ndx, ndy, lambda, w);
+}
+
+/* Fields of one trace record (one check that reached the restart decision). */
+enum { TR_IT, TR_K, TR_R, TR_R0, TR_RPREV, TR_RESTART, TR_SIGMA, TR_SIGMA_NEXT, TR_NDX, TR_NDY,
+       TR_FIELDS };
+
 /*
  * Full solve. Outputs the unscaled (x, y, z) of the last check and fills info.
  *
@@ -535,22 +607,29 @@ static int certifies_infeasibility(const double c[4]) {
  * it % check_every == 0, and the last allowed iteration is always a check
  * (without a restart decision). At a check:
  *   - KKT of the unscaled (xbar, ybar, zbar); stop if rel_kkt <= tol;
+ *   - the primal infeasibility certificate (stop if it holds);
  *   - merit r = || (x - xbar, y - ybar) ||_M with M = [[I/sigma, A~^T], [A~, lambda sigma I]]
  *     (x, y the iterate the step started from);
- *   - first check: r0 = r_prev = r, no restart;
- *   - restart when r <= 0.2 r0, or (r <= 0.8 r0 and r > r_prev), or when the
- *     iterations since the last restart are >= 0.2 of all iterations so far;
- *   - on restart: log sigma <- (1 - w) log sigma + w log sigma* (w = sigma_smoothing from a cold
- *     start, 1 by default: sigma <- sigma*; w = sigma_smoothing_warm when a start point is given,
- *     1/2 by default: sigma <- sqrt(sigma * sigma*); w = 1 and 1/2 evaluated without exp/log)
- *     with sigma* = ||dx|| / (sqrt(lambda) ||dy||),
- *     (dx, dy) = (xbar - x0, ybar - y0) the move of the anchor, skipped when either norm is
- *     below 1e-12, clamped to [1e-4, 1e4]; then anchor = current = (xbar, ybar), k = 0,
- *     r0 = r.
+ *   - the restart decision of restart_decide with k = steps since the last restart and
+ *     done = it + 1;
+ *   - on restart: sigma <- sigma_next(sigma, ||xbar - x0||, ||ybar - y0||, lambda, w) (w =
+ *     sigma_smoothing from a cold start, sigma_smoothing_warm when a start point is given;
+ *     (xbar - x0, ybar - y0) is the move of the anchor), then anchor = current = (xbar, ybar)
+ *     and k = 0.
+ *
+ * Tracing (tests only): when trace != NULL, each check that reaches the restart decision
+ * appends TR_FIELDS doubles (iteration index, k, r, r0 and r_prev before the decision, the
+ * decision, sigma before and after, the two anchor-move norms; the norms are 0 unless the
+ * check restarts with the sigma update on) while fewer than trace_cap records exist;
+ * *trace_len receives the count. When vecs != NULL, the check with record index vec_check
+ * writes the scaled vectors the decision used: x (the step's start), xbar, x0 (anchor),
+ * each n doubles, then y, ybar, y0, each m doubles.
  */
-int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out, double *z_out,
-              orc_info *info) {
+static int solve_impl(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out, double *z_out,
+                      orc_info *info, double *trace, int64_t trace_cap, int64_t *trace_len,
+                      int64_t vec_check, double *vecs) {
     memset(info, 0, sizeof(*info));
+    if (trace_len) *trace_len = 0;
     if (orc_validate(lp) || o->max_iter < 1 || o->check_every < 1 || !(o->sigma0 > 0)) return -1;
     double t0 = now_s();
     int32_t m = lp->m, n = lp->n;
@@ -583,10 +662,11 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
         y0[i] = ys;
         y[i] = ys;
     }
+    double w_sigma = (o->x0 || o->y0) ? o->sigma_smoothing_warm : o->sigma_smoothing;
 
     double sigma = o->sigma0;
-    int64_t k = 0, restarts = 0, it;
-    double r0 = 0.0, r_prev = 0.0;
+    int64_t k = 0, restarts = 0, it, nrec = 0;
+    restart_state rs = {0.0, 0.0, 0};
     double kk[8] = {0};
     int term = ORC_ITER_LIMIT;
     for (it = 0; it < o->max_iter; ++it) {
@@ -622,13 +702,24 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
         double r = sqrt(r2 > 0 ? r2 : 0.0);
         if (!isfinite(r)) { term = ORC_NUMERIC_FAIL; break; }
 
-        if (it == 0) { r0 = r; r_prev = r; continue; }
-        int do_restart = 0;
-        if (o->restart) {
-            if (r <= 0.2 * r0) do_restart = 1;
-            else if (r <= 0.8 * r0 && r > r_prev) do_restart = 1;
-            else if ((double)k >= 0.2 * (double)(it + 1)) do_restart = 1;
+        double *rec = (trace && nrec < trace_cap) ? trace + nrec * TR_FIELDS : NULL;
+        if (vecs && nrec == vec_check) {
+            memcpy(vecs, xprev, sizeof(double) * n);
+            memcpy(vecs + n, xb, sizeof(double) * n);
+            memcpy(vecs + 2 * (size_t)n, x0, sizeof(double) * n);
+            double *vy = vecs + 3 * (size_t)n;
+            if (m) {
+                memcpy(vy, yprev, sizeof(double) * m);
+                memcpy(vy + m, yb, sizeof(double) * m);
+                memcpy(vy + 2 * (size_t)m, y0, sizeof(double) * m);
+            }
         }
+        if (rec) {
+            rec[TR_IT] = (double)it; rec[TR_K] = (double)k; rec[TR_R] = r;
+            rec[TR_R0] = rs.r0; rec[TR_RPREV] = rs.r_prev; rec[TR_SIGMA] = sigma;
+            rec[TR_NDX] = 0.0; rec[TR_NDY] = 0.0;
+        }
+        int do_restart = restart_decide(&rs, r, k, it + 1, o->restart);
         if (do_restart) {
             if (o->sigma_update) {
                 double ddx = 0.0, ddy = 0.0;
@@ -636,25 +727,20 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
                 for (int32_t i = 0; i < m; ++i) { double d = yb[i] - y0[i]; ddy += d * d; }
                 ddx = sqrt(ddx);
                 ddy = sqrt(ddy);
-                if (ddx > 1e-12 && ddy > 1e-12) {
-                    double star = ddx / (sqrt(lambda) * ddy);
-                    double w = (o->x0 || o->y0) ? o->sigma_smoothing_warm : o->sigma_smoothing;
-                    double next = (w == 1.0)   ? star
-                                  : (w == 0.5) ? sqrt(sigma * star)
-                                               : exp((1.0 - w) * log(sigma) + w * log(star));
-                    sigma = clampd(next, 1e-4, 1e4);
-                }
+                if (rec) { rec[TR_NDX] = ddx; rec[TR_NDY] = ddy; }
+                sigma = sigma_next(sigma, ddx, ddy, lambda, w_sigma);
             }
             memcpy(x0, xb, sizeof(double) * n);
             memcpy(x, xb, sizeof(double) * n);
             if (m) { memcpy(y0, yb, sizeof(double) * m); memcpy(y, yb, sizeof(double) * m); }
             k = 0;
             restarts += 1;
-            r0 = r;
         }
-        r_prev = r;
+        if (rec) { rec[TR_RESTART] = (double)do_restart; rec[TR_SIGMA_NEXT] = sigma; }
+        if (trace || vecs) nrec += 1;
     }
     double t2 = now_s();
+    if (trace_len) *trace_len = nrec < trace_cap ? nrec : trace_cap;
     info->term = term;
     info->iters = (it < o->max_iter) ? it + 1 : o->max_iter;
     info->restarts = restarts;
@@ -668,6 +754,18 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     free(y); free(y0); free(yprev); free(yb); free(wm); free(dxv); free(adx); free(aty);
     free_scaled(&s);
     return 0;
+}
+
+int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out, double *z_out,
+              orc_info *info) {
+    return solve_impl(lp, o, x_out, y_out, z_out, info, NULL, 0, NULL, -1, NULL);
+}
+
+/* Test entry: orc_solve with the check trace described at solve_impl. */
+int orc_solve_trace(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out, double *z_out,
+                    orc_info *info, double *trace, int64_t trace_cap, int64_t *trace_len,
+                    int64_t vec_check, double *vecs) {
+    return solve_impl(lp, o, x_out, y_out, z_out, info, trace, trace_cap, trace_len, vec_check, vecs);
 }
 
 int orc_num_threads(void) {

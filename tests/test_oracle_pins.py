@@ -309,3 +309,23 @@ def test_infeasible_lp_is_not_reported_solved():
     lp = dense_lp([[1.0, 1.0]], [3.0], [np.inf], [0, 0], [1, 1], [1.0, 1.0])
     r = oracle.solve(lp, oracle.Options(tol=1e-6, max_iter=5000))
     assert r.term != "solved"
+
+
+# ----------------------------------------------------------------------------- SCUC structure
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_logic_identity_at_the_oracle_optimum(seed, small_instances):
+    """u_t - u_{t-1} = v_t - w_t (u_0 = 1) at the oracle's optimum of the compact model, read
+    from the columns (not from the LP's rows), within its primal residual."""
+    data, lp = small_instances[seed]
+    r = oracle.solve(lp, oracle.Options(tol=1e-8, max_iter=400000))
+    assert r.term == "solved"
+    G, T = data.cfg.n_gen, data.cfg.T
+    t = np.arange(T)[None, :]
+    g = np.arange(G)[:, None]
+    u, v, w = (r.x[scuc.col_index(G, t, var, g)] for var in (scuc.U, scuc.V, scuc.W))
+    prev = np.concatenate([np.ones((G, 1)), u[:, :-1]], axis=1)
+    viol = np.abs(u - prev - v + w)
+    b = np.where(np.isfinite(lp.row_lo), lp.row_lo, np.where(np.isfinite(lp.row_hi), lp.row_hi, 0.0))
+    assert viol.max() <= r.rel_p * (1 + np.linalg.norm(b)) + 1e-12
+    assert viol.max() <= 1e-6
