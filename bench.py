@@ -28,7 +28,7 @@ def recorded_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` measured by rocprofv3 counters
     (FETCH_SIZE + WRITE_SIZE, each scaled by the ratio a plain copy kernel of known size gives)
     as recorded under profiles/, or None when no record exists or the kernel or schedule source
-    has changed since (the record holds the SHA-256 of kernels.hip followed by solver.hip)."""
+    has changed since (the record holds sources_sha256() of the sources it was measured with)."""
     import re
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
@@ -42,10 +42,15 @@ def recorded_traffic(kernel, workload):
     return float(m_val.group(1))
 
 
+KERNEL_SOURCES = ("csr.h", "kernels_dual32.hip", "kernels_primal32.hip", "solver.hip")
+
+
 def sources_sha256():
+    """SHA-256 of the sources that decide what the fused FP32 steps move: the kernel template,
+    their instantiations and the runtime that builds the layouts and schedules."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "solver.hip"):
+    for name in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2510_10891_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -107,7 +112,7 @@ reports {mean(f["stream_copy_kernel"]):,.1f} KiB for it (factor {cf:.4f}), WRITE
 | WRITE_SIZE | {wk:,.1f} | {wk * cw * 1024:,.0f} |
 
 traffic_bytes_per_launch: {traffic:.0f}
-sources_sha256: {sources_sha256()}   (SHA-256 of paper_2510_10891_amd/csrc/kernels.hip followed by solver.hip)
+sources_sha256: {sources_sha256()}   (SHA-256 of {", ".join(KERNEL_SOURCES)} under paper_2510_10891_amd/csrc, in that order)
 
 The algorithmic bytes of a launch count 4-byte column indices (314,719,640); the kernel reads 16-bit
 offsets for every row of this matrix, so the measured traffic is below the algorithmic figure, with no
@@ -124,17 +129,47 @@ def log(*a):
 
 
 def algorithmic_bytes(lp, fp32: bool):
-    """Bytes one launch of each fused kernel must move (per the iteration of eq.(hpr)).
+    """Bytes one launch of each fused kernel must move with 4-byte column indices and row offsets
+    (the count of the iteration of eq.(hpr) for a plain CSR matrix).
 
     Dual step (rows of A): nnz values + nnz column indices + row offsets, reads y, y0, lo, hi,
     writes y, gathers each entry of xhat once.  Primal step (rows of A^T): nnz values + indices
     + offsets, reads x, x0, c, l, u, writes xhat and x, gathers each entry of y once.
-    Index width 4 bytes; value width 4 (FP32 storage) or 8 (FP64).
+    Value width 4 (FP32 storage) or 8 (FP64).
     """
     sv = 4 if fp32 else 8
     nnz, m, n = lp.nnz, lp.m, lp.n
     dual = nnz * (sv + 4) + 4 * m + sv * (5 * m) + sv * n
     primal = nnz * (sv + 4) + 4 * n + sv * (7 * n) + sv * m
+    return primal, dual
+
+
+def layout_bytes(lp, fp32: bool):
+    """Bytes one launch of each fused kernel must move in the layout the library streams (the
+    figure the roofline fraction is computed from): every row padded to a multiple of 4 entries,
+    each stored entry a value plus a 16-bit column offset (4-byte index for rows spanning 65,536
+    columns or more), one 16-byte row descriptor per row, and the same vector traffic as
+    algorithmic_bytes (each gathered entry read once). Returns (primal, dual)."""
+    import numpy as np
+    sv = 4 if fp32 else 8
+    A = lp.to_scipy().tocsr()
+
+    def matrix_bytes(M):
+        M = M.tocsr()
+        M.sort_indices()
+        lens = np.diff(M.indptr)
+        padded = (lens + 3) // 4 * 4
+        lo = np.full(M.shape[0], 0, np.int64)
+        hi = np.full(M.shape[0], 0, np.int64)
+        nz = lens > 0
+        lo[nz] = M.indices[M.indptr[:-1][nz]]
+        hi[nz] = M.indices[M.indptr[1:][nz] - 1]
+        wide = (hi - lo) >= 65536
+        return int((padded * (sv + np.where(wide, 4, 2))).sum() + 16 * M.shape[0])
+
+    m, n = lp.m, lp.n
+    dual = matrix_bytes(A) + sv * (5 * m) + sv * n
+    primal = matrix_bytes(A.T) + sv * (7 * n) + sv * m
     return primal, dual
 
 
@@ -377,6 +412,30 @@ def ablation_leg(data, rounds, stream, formulation="compact"):
     return out
 
 
+def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
+    """Roofline record of the dominant fused kernel (the slower of the two steps, event-timed):
+    the bytes its layout makes it move per launch (layout_bytes) over its average launch time,
+    against 8 TB/s; the plain-CSR count (4-byte indices and offsets) beside it."""
+    pb, db = layout_bytes(lp, fp32)
+    pa, da = algorithmic_bytes(lp, fp32)
+    tag = "fp32" if fp32 else "fp64"
+    if ks["dual_ms"] >= ks["primal_ms"]:
+        kname, kbytes, kalg, kms, other = f"dual_step_{tag}", db, da, ks["dual_ms"], ks["primal_ms"]
+    else:
+        kname, kbytes, kalg, kms, other = f"primal_step_{tag}", pb, pa, ks["primal_ms"], ks["dual_ms"]
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
+                bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
+                other_kernel_us=round(other * 1e3, 2),
+                plain_csr_bytes_per_launch=int(kalg),
+                plain_csr_gbs=round(kalg / (kms * 1e-3) / 1e9, 1),
+                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
+                          "nontemporal_A": ks["nt_a"], "nontemporal_At": ks["nt_at"]},
+                stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
+                frac_of_stream_read=round(achieved / read_gbs, 4))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,21 +525,8 @@ def main():
         log("single-precision leg only (profiler run): no JSON line")
         return
     f32, f64 = res["fp32"], res["fp64"]
-    pb, db = algorithmic_bytes(lp, fp32=True)
-    ks = f32["ks"]
-    if ks["dual_ms"] >= ks["primal_ms"]:
-        kname, kbytes, kms = "dual_step_fp32", db, ks["dual_ms"]
-    else:
-        kname, kbytes, kms = "primal_step_fp32", pb, ks["primal_ms"]
-    achieved = kbytes / (kms * 1e-3) / 1e9
-    roof = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
-                bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
-                other_kernel_us=round((ks["primal_ms"] if kname.startswith("dual") else ks["dual_ms"]) * 1e3, 2),
-                schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
-                          "nontemporal_A": ks["nt_a"], "nontemporal_At": ks["nt_at"]},
-                stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
-                frac_of_stream_read=round(achieved / read_gbs, 4))
+    roof = roofline(lp, f32["ks"], workload, read_gbs, copy_gbs)
+
 
     batch = batch_leg(args.batch, stream, args.batch_parent) if args.batch > 0 else None
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None

@@ -168,8 +168,16 @@ class _LPArrays:
         self.v = f64(lp.val)
         self.lo, self.hi = f64(lp.row_lo), f64(lp.row_hi)
         self.l, self.u, self.c = f64(lp.col_lo), f64(lp.col_hi), f64(lp.c)
+        m, n = int(lp.m), int(lp.n)
         if len(self.v) != len(self.ci):
             raise ValueError("col_idx and val differ in length")
+        if m > 0 and len(self.rp) != m + 1:
+            raise ValueError(f"row_ptr has {len(self.rp)} entries, expected m + 1 = {m + 1}")
+        if len(self.lo) != m or len(self.hi) != m:
+            raise ValueError(f"row_lo / row_hi have {len(self.lo)} / {len(self.hi)} entries, expected m = {m}")
+        if not (len(self.l) == len(self.u) == len(self.c) == n):
+            raise ValueError(f"col_lo / col_hi / c have {len(self.l)} / {len(self.u)} / {len(self.c)} entries, "
+                             f"expected n = {n}")
         nnz = len(self.ci)   # the library checks row_ptr[m] == nnz
         ptr = lambda a: a.ctypes.data if a.size else None
         self.s = hpr_lp(lp.m, lp.n, nnz, ptr(self.rp), ptr(self.ci), ptr(self.v), ptr(self.lo),
@@ -205,16 +213,24 @@ def hpr_destroy(h: Handle) -> None:
         h.ptr = None
 
 
+def _vec(a, length: int, name: str):
+    """Contiguous FP64 copy of an optional vector whose length the library takes from m or n."""
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, np.float64)
+    if a.ndim != 1 or len(a) != length:
+        raise ValueError(f"{name} has shape {a.shape}, expected ({length},)")
+    return a
+
+
 def hpr_set_bounds(h: Handle, col_lo=None, col_hi=None) -> None:
-    lo = None if col_lo is None else np.ascontiguousarray(col_lo, np.float64)
-    hi = None if col_hi is None else np.ascontiguousarray(col_hi, np.float64)
+    lo, hi = _vec(col_lo, h.n, "col_lo"), _vec(col_hi, h.n, "col_hi")
     _check(lib().hpr_set_bounds(h.ptr, None if lo is None else lo.ctypes.data_as(C.c_void_p),
                                 None if hi is None else hi.ctypes.data_as(C.c_void_p)))
 
 
 def hpr_set_start(h: Handle, x0=None, y0=None) -> None:
-    xa = None if x0 is None else np.ascontiguousarray(x0, np.float64)
-    ya = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+    xa, ya = _vec(x0, h.n, "x0"), _vec(y0, h.m, "y0")
     _check(lib().hpr_set_start(h.ptr, None if xa is None else xa.ctypes.data_as(C.c_void_p),
                                None if ya is None else ya.ctypes.data_as(C.c_void_p)))
 
@@ -294,16 +310,16 @@ def hpr_batch_destroy(b: Batch) -> None:
 
 
 def hpr_batch_set_bounds(b: Batch, i: int, col_lo=None, col_hi=None) -> None:
-    lo = None if col_lo is None else np.ascontiguousarray(col_lo, np.float64)
-    hi = None if col_hi is None else np.ascontiguousarray(col_hi, np.float64)
+    n = b.sizes[i][1]
+    lo, hi = _vec(col_lo, n, "col_lo"), _vec(col_hi, n, "col_hi")
     _check(lib().hpr_batch_set_bounds(b.ptr, C.c_int32(i),
                                       None if lo is None else lo.ctypes.data_as(C.c_void_p),
                                       None if hi is None else hi.ctypes.data_as(C.c_void_p)))
 
 
 def hpr_batch_set_start(b: Batch, i: int, x0=None, y0=None) -> None:
-    xa = None if x0 is None else np.ascontiguousarray(x0, np.float64)
-    ya = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+    m, n = b.sizes[i]
+    xa, ya = _vec(x0, n, "x0"), _vec(y0, m, "y0")
     _check(lib().hpr_batch_set_start(b.ptr, C.c_int32(i),
                                      None if xa is None else xa.ctypes.data_as(C.c_void_p),
                                      None if ya is None else ya.ctypes.data_as(C.c_void_p)))

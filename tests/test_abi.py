@@ -117,3 +117,25 @@ def test_batch_create_rejects_bad_member_and_counts():
     assert L.hpr_batch_solve(None, None) == hprlp.HPR_ERR_INVALID
     assert L.hpr_batch_get_solution(None, 0, None, None, None) == hprlp.HPR_ERR_INVALID
     assert L.hpr_batch_destroy(None) == hprlp.HPR_OK
+
+
+@pytest.mark.parametrize("field,length", [("row_ptr", 2), ("row_lo", 0), ("row_hi", 3), ("col_lo", 1),
+                                          ("col_hi", 5), ("c", 1)])
+def test_binding_rejects_arrays_of_the_wrong_length(field, length):
+    """The library reads m + 1, m or n entries through raw pointers: short arrays are refused
+    before the call."""
+    good = _good()
+    arr = getattr(good, field)
+    bad = good.replace(**{field: np.resize(arr, length).astype(arr.dtype)})
+    with pytest.raises(ValueError):
+        hprlp._LPArrays(bad)
+
+
+def test_binding_rejects_start_and_bounds_of_the_wrong_length():
+    h = hprlp.Handle(None, 2, 3)
+    with pytest.raises(ValueError):
+        hprlp.hpr_set_start(h, np.zeros(2), None)
+    with pytest.raises(ValueError):
+        hprlp.hpr_set_start(h, None, np.zeros(3))
+    with pytest.raises(ValueError):
+        hprlp.hpr_set_bounds(h, np.zeros(4), None)
