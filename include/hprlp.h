@@ -49,14 +49,21 @@ enum {
     HPR_ITER_LIMIT = 2,
     HPR_TIME_LIMIT = 3,
     HPR_NUMERIC_FAIL = 4,   /* NaN or Inf appeared in a check */
-    HPR_PRIMAL_INFEASIBLE = 5   /* at a check, the dual bar point ybar certifies that no x
+    HPR_PRIMAL_INFEASIBLE = 5,  /* at a check, the dual bar point ybar certifies that no x
                                    satisfies the rows and bounds: with dz = -A^T ybar (scaled
                                    problem), h = sum lo_i ybar_i+ - hi_i ybar_i- + sum l_j dz_j+
                                    - u_j dz_j- exceeds 1e-6 times the sum of its terms'
                                    magnitudes (h <= 0 for every sign-feasible y of a feasible
                                    LP), and the sign violations of dz on infinite column bounds
-                                   sum to at most 1e-6 sum |ybar_i|; FP64-evaluated. Dual infeasibility
-                                   (an unbounded LP) is not detected: it runs to max_iter. */
+                                   sum to at most 1e-6 sum |ybar_i|; FP64-evaluated. */
+    HPR_DUAL_INFEASIBLE = 6     /* at a check, the step's primal move d = xbar - x (scaled
+                                   problem) is a ray: c~^T d < 0, and the distances of A~ d to
+                                   the rows' recession cone ((A~d)_i = 0 for two finite sides,
+                                   >= 0 with only lo_i finite, <= 0 with only hi_i finite) and of
+                                   d to the columns' cone (same rule for l_j, u_j) sum to at most
+                                   1e-6 (-c~^T d) / ||c~||: the dual has no feasible point, so the
+                                   LP has no finite optimum (unbounded when it is feasible).
+                                   Tested after the two above; FP64-evaluated. */
 };
 
 /* storage precision of A and of the iterates (hpr_opts.precision) */

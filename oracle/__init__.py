@@ -63,7 +63,8 @@ class _Info(C.Structure):
                 ("solve_s", C.c_double)]
 
 
-TERM = {1: "solved", 2: "iter_limit", 3: "time_limit", 4: "numeric_fail", 5: "primal_infeasible"}
+TERM = {1: "solved", 2: "iter_limit", 3: "time_limit", 4: "numeric_fail", 5: "primal_infeasible",
+        6: "dual_infeasible"}
 _lib = None
 
 

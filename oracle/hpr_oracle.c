@@ -74,12 +74,13 @@ typedef struct {
 
 typedef struct {
     int32_t term;            /* 1 solved, 2 iteration limit, 3 time limit, 4 numeric failure,
-                                5 primal infeasible */
+                                5 primal infeasible, 6 dual infeasible (no finite optimum) */
     int64_t iters, restarts;
     double pobj, dobj, rel_p, rel_d, rel_gap, rel_kkt, lambda, sigma, setup_s, solve_s;
 } orc_info;
 
-enum { ORC_SOLVED = 1, ORC_ITER_LIMIT = 2, ORC_TIME_LIMIT = 3, ORC_NUMERIC_FAIL = 4, ORC_PRIMAL_INFEASIBLE = 5 };
+enum { ORC_SOLVED = 1, ORC_ITER_LIMIT = 2, ORC_TIME_LIMIT = 3, ORC_NUMERIC_FAIL = 4, ORC_PRIMAL_INFEASIBLE = 5,
+       ORC_DUAL_INFEASIBLE = 6 };
 
 /* relative margin of the primal infeasibility certificate */
 #define ORC_INFEAS_TOL 1e-6
@@ -528,6 +529,47 @@ static int certifies_infeasibility(const double c[4]) {
     return c[0] > ORC_INFEAS_TOL * c[1] && c[2] <= ORC_INFEAS_TOL * c[3];
 }
 
+/* Dual infeasibility (an addition to the method, like the test above). A direction d with
+ * c^T d < 0 that the problem's recession cones admit, A d in the rows' cone ((A d)_i = 0 for
+ * two finite sides, >= 0 when only lo_i is finite, <= 0 when only hi_i is, free otherwise) and d
+ * in the columns' cone (the same rule with l_j, u_j), shows that the dual has no feasible point:
+ * the LP has no finite optimum. For such LPs the step's fixed-point residual converges to the
+ * operator's minimal displacement, whose primal part is such a ray, so the candidate is the
+ * primal move of the step, d = xbar - x (scaled problem; x the iterate the step started from).
+ * out: [0] g = c~^T d, [1] ||distance of A~ d to the rows' cone||, [2] ||distance of d to the
+ * columns' cone||, [3] ||c~||; work: m doubles. */
+static void ray_test(const scaled_lp *s, const double *xb, const double *xprev, double *d, double *ad,
+                     double out[4]) {
+    double g = 0.0, vr = 0.0, vc = 0.0, c2 = 0.0;
+    for (int32_t j = 0; j < s->n; ++j) {
+        d[j] = xb[j] - xprev[j];
+        g += s->c[j] * d[j];
+        c2 += s->c[j] * s->c[j];
+        double v = 0.0;
+        const int fl = isfinite(s->l[j]), fu = isfinite(s->u[j]);
+        if (fl && fu) v = fabs(d[j]);
+        else if (fl) v = d[j] < 0.0 ? -d[j] : 0.0;
+        else if (fu) v = d[j] > 0.0 ? d[j] : 0.0;
+        vc += v * v;
+    }
+    spmv(s->m, s->rp, s->ci, s->v, d, ad);
+    for (int32_t i = 0; i < s->m; ++i) {
+        double v = 0.0;
+        const int fl = isfinite(s->lo[i]), fh = isfinite(s->hi[i]);
+        if (fl && fh) v = fabs(ad[i]);
+        else if (fl) v = ad[i] < 0.0 ? -ad[i] : 0.0;
+        else if (fh) v = ad[i] > 0.0 ? ad[i] : 0.0;
+        vr += v * v;
+    }
+    out[0] = g; out[1] = sqrt(vr); out[2] = sqrt(vc); out[3] = sqrt(c2);
+}
+
+/* d certifies dual infeasibility when it lowers the cost and its cone violations are at most
+ * 1e-6 of the cost decrease measured in units of d (-g / ||c~|| <= ||d||). */
+static int certifies_unboundedness(const double r[4]) {
+    return r[0] < 0.0 && r[3] > 0.0 && r[1] + r[2] <= ORC_INFEAS_TOL * (-r[0] / r[3]);
+}
+
 /* ---------------------------------------------------------------- restart and sigma rules */
 
 /*
@@ -607,7 +649,8 @@ enum { TR_IT, TR_K, TR_R, TR_R0, TR_RPREV, TR_RESTART, TR_SIGMA, TR_SIGMA_NEXT, 
  * it % check_every == 0, and the last allowed iteration is always a check
  * (without a restart decision). At a check:
  *   - KKT of the unscaled (xbar, ybar, zbar); stop if rel_kkt <= tol;
- *   - the primal infeasibility certificate (stop if it holds);
+ *   - the primal infeasibility certificate, then the dual infeasibility test of the step's
+ *     primal move (stop if either holds);
  *   - merit r = || (x - xbar, y - ybar) ||_M with M = [[I/sigma, A~^T], [A~, lambda sigma I]]
  *     (x, y the iterate the step started from);
  *   - the restart decision of restart_decide with k = steps since the last restart and
@@ -647,7 +690,7 @@ static int solve_impl(const orc_lp *lp, const orc_opts *o, double *x_out, double
     double *yprev = (double *)malloc(sizeof(double) * mm);
     double *yb = (double *)malloc(sizeof(double) * mm), *wm = (double *)malloc(sizeof(double) * mm);
     double *dxv = (double *)malloc(sizeof(double) * n), *adx = (double *)malloc(sizeof(double) * mm);
-    double *aty = (double *)malloc(sizeof(double) * n), cert[4];
+    double *aty = (double *)malloc(sizeof(double) * n), cert[4], ray[4];
 
     /* start point: projections of the (scaled) warm start, or of zero */
     for (int32_t j = 0; j < n; ++j) {
@@ -686,6 +729,8 @@ static int solve_impl(const orc_lp *lp, const orc_opts *o, double *x_out, double
         if (kk[3] <= o->tol) { term = ORC_SOLVED; break; }
         certificate(&s, yb, aty, cert);
         if (certifies_infeasibility(cert)) { term = ORC_PRIMAL_INFEASIBLE; break; }
+        ray_test(&s, xb, xprev, dxv, adx, ray);
+        if (certifies_unboundedness(ray)) { term = ORC_DUAL_INFEASIBLE; break; }
         if (last) { term = ORC_ITER_LIMIT; break; }
         if (timed_out) { term = ORC_TIME_LIMIT; break; }
 

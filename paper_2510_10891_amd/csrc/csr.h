@@ -568,6 +568,9 @@ struct DualOp {
 //   q5 = number of non-finite values
 //   q6 = sum |lo_i| ybar_i+ + |hi_i| ybar_i-                  (magnitude of q3's terms)
 //   q7 = sum |ybar_i|                                         (size of ybar)
+//   q8 = sum dist((A d)_i, rows' recession cone)^2 with d = xbar - x = -dx (the step's primal
+//        move, a candidate ray of an LP without finite optimum): (A d)_i must be 0 for two
+//        finite sides, >= 0 with only lo_i finite, <= 0 with only hi_i finite
 template <typename M, typename P, typename V>
 struct CheckRowsOp {
     using Tm = M;
@@ -609,6 +612,10 @@ struct CheckRowsOp {
         if (yb > 0.0) q[6] += fabs(lo) * yb;
         else if (yb < 0.0) q[6] -= fabs(hi) * yb;
         q[7] += fabs(yb);
+        const double ad = -double(adx);
+        const bool fl = isfinite(lo), fh = isfinite(hi);
+        const double vr = (fl && fh) ? fabs(ad) : fl ? (ad < 0.0 ? -ad : 0.0) : fh ? (ad > 0.0 ? ad : 0.0) : 0.0;
+        q[8] += vr * vr;
     }
 };
 
@@ -621,6 +628,9 @@ struct CheckRowsOp {
 // from ybar, which is sign-feasible by construction):
 //   q6 = sum l_j dz_j+ - u_j dz_j- over finite bounds,  q7 = the same with |l_j|, |u_j|,
 //   q8 = sum of dz_j+ with l_j = -inf and dz_j- with u_j = +inf (sign violations)
+// and, with d = -dx = xbar - x (the step's primal move, a candidate ray):
+//   q9 = sum c_j d_j,  q10 = sum dist(d_j, columns' recession cone)^2 (d_j must be 0 for two
+//   finite bounds, >= 0 with only l_j finite, <= 0 with only u_j finite),  q11 = sum c_j^2
 template <typename M, typename P, typename V>
 struct CheckColsOp {
     using Tm = M;
@@ -674,6 +684,12 @@ struct CheckColsOp {
                 q[8] -= dz;
             }
         }
+        const double d = -dx;
+        q[9] += c * d;
+        const bool fl = isfinite(l), fu = isfinite(u);
+        const double vc = (fl && fu) ? fabs(d) : fl ? (d < 0.0 ? -d : 0.0) : fu ? (d > 0.0 ? d : 0.0) : 0.0;
+        q[10] += vc * vc;
+        q[11] += c * c;
     }
 };
 

@@ -13,11 +13,11 @@ namespace hpr {
 constexpr int kBlock = 256;      // threads per block: 4 wavefronts of 64 lanes
 constexpr int kNumBins = 7;      // lanes per row: 1, 2, 4, 8, 16, 32, 64
 constexpr int kVec = 4;          // every stored row is padded to a multiple of 4 entries
-constexpr int kRowQ = 8;         // FP64 quantities of the row check
-constexpr int kColQ = 9;         // FP64 quantities of the column check
-constexpr int kColOff = 8;       // per-LP sums: [0, kRowQ) rows, [kColOff, kColOff + kColQ) columns
+constexpr int kRowQ = 9;         // FP64 quantities of the row check
+constexpr int kColQ = 12;        // FP64 quantities of the column check
+constexpr int kColOff = 9;       // per-LP sums: [0, kRowQ) rows, [kColOff, kColOff + kColQ) columns
 constexpr int kSumStride = 24;
-constexpr double kInfeasTol = 1e-6;   // relative margin of the primal infeasibility certificate
+constexpr double kInfeasTol = 1e-6;   // relative margin of the infeasibility certificates
 constexpr int kChunk = 8192;     // entries per block of the segmented vector kernels
 constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 

@@ -30,6 +30,7 @@ struct CheckValues {
     double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit, move_x, move_y;
     bool bad;
     bool infeasible;   // ybar is a primal infeasibility certificate
+    bool unbounded;    // the step's primal move is a ray: the LP has no finite optimum
 };
 
 // The relative KKT residuals of the original problem and the merit from the check sums
@@ -58,6 +59,11 @@ __device__ CheckValues check_values(const double* s, const Ctrl& c, const LpStat
     // h(ybar) > 0 certifies primal infeasibility; margins relative to the terms' magnitude.
     const double h = r[3] + k[6], mag = r[6] + k[7];
     v.infeasible = h > kInfeasTol * mag && k[8] <= kInfeasTol * r[7];
+    // A direction d with c~'d < 0 inside the rows' and columns' recession cones shows that the
+    // dual has no feasible point; d = the step's primal move, accepted when its cone violations
+    // are at most 1e-6 of the cost decrease in units of d.
+    const double g = k[9], vr = sqrt(r[8]), vc = sqrt(k[10]), nc = sqrt(k[11]);
+    v.unbounded = g < 0.0 && nc > 0.0 && vr + vc <= kInfeasTol * (-g / nc);
     return v;
 }
 
@@ -139,9 +145,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
                 if (v.bad) {
                     S.term = 4;   // HPR_NUMERIC_FAIL
                     c.active = 0;
-                } else if (v.rel_kkt <= a.tol || v.infeasible) {
-                    if (!a.fp32) {
-                        S.term = v.rel_kkt <= a.tol ? 1 : 5;   // HPR_SOLVED, HPR_PRIMAL_INFEASIBLE
+                } else if (v.rel_kkt <= a.tol || v.infeasible || v.unbounded) {
+                    if (!a.fp32) {   // HPR_SOLVED, HPR_PRIMAL_INFEASIBLE, HPR_DUAL_INFEASIBLE
+                        S.term = v.rel_kkt <= a.tol ? 1 : (v.infeasible ? 5 : 6);
                         c.active = 0;
                     } else {   // FP32 storage: confirmed (or not) by the FP64 re-evaluation
                         S.candidate = 1;
@@ -158,9 +164,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
             if (c.active && S.candidate) {
                 S.candidate = 0;
                 const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
-                if (!v.bad && (v.rel_kkt <= a.tol || v.infeasible)) {
+                if (!v.bad && (v.rel_kkt <= a.tol || v.infeasible || v.unbounded)) {
                     store_values(S, v);
-                    S.term = v.rel_kkt <= a.tol ? 1 : 5;
+                    S.term = v.rel_kkt <= a.tol ? 1 : (v.infeasible ? 5 : 6);
                     c.active = 0;
                 } else {
                     decide(S, c, a, S.p32[0], S.p32[1], S.p32[2]);

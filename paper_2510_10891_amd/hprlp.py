@@ -15,10 +15,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhprlp.s
 
 HPR_OK, HPR_ERR_INVALID, HPR_ERR_NOMEM, HPR_ERR_HIP, HPR_ERR_STATE = 0, -1, -2, -3, -4
 HPR_SOLVED, HPR_ITER_LIMIT, HPR_TIME_LIMIT, HPR_NUMERIC_FAIL, HPR_PRIMAL_INFEASIBLE = 1, 2, 3, 4, 5
+HPR_DUAL_INFEASIBLE = 6
 HPR_FP64, HPR_FP32 = 0, 1
 HPR_SCALE_PC, HPR_SCALE_RUIZ, HPR_SCALE_BC = 1, 2, 4
 TERM_NAMES = {HPR_SOLVED: "solved", HPR_ITER_LIMIT: "iter_limit", HPR_TIME_LIMIT: "time_limit",
-              HPR_NUMERIC_FAIL: "numeric_fail", HPR_PRIMAL_INFEASIBLE: "primal_infeasible"}
+              HPR_NUMERIC_FAIL: "numeric_fail", HPR_PRIMAL_INFEASIBLE: "primal_infeasible",
+              HPR_DUAL_INFEASIBLE: "dual_infeasible"}
 
 
 class HprError(RuntimeError):

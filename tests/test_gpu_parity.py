@@ -435,3 +435,30 @@ def test_single_iteration_and_short_final_block():
         o, info, x, y, z = run_both(lp, K)
         assert info.term == "iter_limit" and info.iters == K
         assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+def _unbounded_lps():
+    from tests.test_oracle_unbounded import BOUNDED, UNBOUNDED
+    return sorted(UNBOUNDED.items()), sorted(BOUNDED.items())
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_unbounded_lps_are_certified_at_the_oracles_check(case):
+    """The dual infeasibility test (a ray from the step's primal move) fires at the same check
+    as in the oracle (FP64), and with FP32 storage after the FP64 confirmation."""
+    name, lp = _unbounded_lps()[0][case]
+    o = oracle.solve(lp, oracle.Options(tol=1e-8, max_iter=200000))
+    assert o.term == "dual_infeasible", name
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-8, max_iter=200000))
+    assert info.term == "dual_infeasible" and info.iters == o.iters, (name, info.iters, o.iters)
+    info32, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-8, max_iter=200000, precision=hprlp.HPR_FP32))
+    assert info32.term == "dual_infeasible", name
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_bounded_lps_with_unbounded_columns_match_the_oracle(case):
+    name, lp = _unbounded_lps()[1][case]
+    o = oracle.solve(lp, oracle.Options(tol=1e-9, max_iter=400000))
+    info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-9, max_iter=400000))
+    assert o.term == "solved" and info.term == "solved" and info.iters == o.iters, (name, info.iters, o.iters)
+    assert abs(info.pobj - o.pobj) <= 1e-8 * (1 + abs(o.pobj))
