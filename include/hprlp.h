@@ -260,6 +260,21 @@ int hpr_mlp_set_params(hpr_mlp *q, const float *params);
 int hpr_mlp_get_params(hpr_mlp *q, float *params);
 /* Y [n][sizes[nlayers]] = network(X [n][sizes[0]]). */
 int hpr_mlp_forward(hpr_mlp *q, const float *X, int64_t n, float *Y);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hpr_mlp_forward on device arrays, with
+ * no allocation of any kind. X [n][sizes[0]] and Y [n][sizes[nlayers]] are FP32 device
+ * pointers on the handle's device, row-major, owned by the caller; Y may not overlap X.
+ * The work is enqueued on the handle's stream and the call returns without waiting (order
+ * the caller's work with that stream, e.g. by creating the handle on it). Results equal
+ * hpr_mlp_forward's bit for bit. The BF16 activations live in a fixed 32 MiB device array
+ * of the library, one per GPU for the life of the process (its address is resolved at
+ * hpr_mlp_create); rows are processed in chunks that fit it (a multiple of 16 rows; each
+ * chunk's activations are written before they are read, so nothing needs clearing). Every
+ * call on one GPU shares that array: calls that overlap in time on one GPU (two streams,
+ * or two threads) race and give wrong results. HPR_ERR_INVALID when 16 rows of the input
+ * and of two hidden layers of the widest width do not fit the array (never for widths up
+ * to 4096 with up to 8 layers), or for NULL pointers with n > 0. */
+int hpr_mlp_forward_device(hpr_mlp *q, const float *X, int64_t n, float *Y);
 /* Loss and gradients (same layout as the parameters; grads may be NULL) for targets T. */
 int hpr_mlp_gradients(hpr_mlp *q, const float *X, const float *T, int64_t n, float *grads, float *loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) on the mini-batch (X, T). */

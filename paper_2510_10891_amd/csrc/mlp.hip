@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -166,6 +167,18 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+// Fixed device scratch of hpr_mlp_forward_device (BF16 input and hidden activations of a chunk
+// of rows), one copy per GPU for the life of the process. In host code `scratch` names a
+// host-side stand-in, never a device address: kernels receive the address that
+// hipGetSymbolAddress returns for the current device (scratch_address), resolved once per
+// device by hpr_mlp_create.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 #define MLP_HIP(expr)                                                                  \
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
@@ -174,10 +187,27 @@ int fail(int code, const char* fmt, ...) {
                         "%s failed: %s", #expr, hipGetErrorString(e_));                \
     } while (0)
 
+// The device address of `scratch` on device dev (resolved on the first call for that device,
+// with dev current).
+int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HPR_ERR_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HPR_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HPR_OK;
+}
+
 }  // namespace
 
 struct hpr_mlp {
     int L = 0;
+    void* scratch_dev = nullptr;                                      // this device's `scratch`
     int sizes[kMaxLayers + 1] = {0};
     int64_t woff[kMaxLayers] = {0}, boff[kMaxLayers] = {0}, nparams = 0;
     hipStream_t st = nullptr;
@@ -347,8 +377,14 @@ extern "C" int hpr_mlp_create(int32_t nlayers, const int32_t* sizes, const float
     if (nlayers < 1 || nlayers > kMaxLayers || !sizes) return fail(HPR_ERR_INVALID, "nlayers must be in [1, %d]", kMaxLayers);
     for (int i = 0; i <= nlayers; ++i)
         if (sizes[i] < 1 || sizes[i] > 4096) return fail(HPR_ERR_INVALID, "layer width %d out of [1, 4096]", sizes[i]);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(HPR_ERR_HIP, "hipGetDevice failed");
+    void* scr = nullptr;
+    const int src = scratch_address(dev, &scr);
+    if (src) return src;
     hpr_mlp* q = new hpr_mlp();
     q->L = nlayers;
+    q->scratch_dev = scr;
     int64_t off = 0;
     for (int i = 0; i <= nlayers; ++i) q->sizes[i] = sizes[i];
     for (int i = 0; i < nlayers; ++i) {
@@ -427,6 +463,62 @@ extern "C" int hpr_mlp_forward(hpr_mlp* q, const float* X, int64_t n, float* Y) 
     if (rc) return rc;
     MLP_HIP(hipMemcpyAsync(Y, q->z32[q->L - 1], sizeof(float) * n * q->sizes[q->L], hipMemcpyDeviceToHost, q->st));
     MLP_HIP(hipStreamSynchronize(q->st));
+    return HPR_OK;
+}
+
+// Rows per chunk of hpr_mlp_forward_device: the BF16 input row and two BF16 rows of the widest
+// hidden layer (ping-pong) per row, in kScratchBytes, a multiple of the 16-row tile; 0 if even
+// 16 rows do not fit.
+static int64_t device_chunk_rows(const hpr_mlp* q, int64_t* in_bytes, int64_t* hid_bytes) {
+    int hmax = 0;
+    for (int i = 1; i < q->L; ++i) hmax = q->sizes[i] > hmax ? q->sizes[i] : hmax;
+    const int64_t per_row = 2 * ((int64_t)q->sizes[0] + 2 * (int64_t)hmax) + 16;   // + alignment slack
+    int64_t rows = (int64_t)(kScratchBytes - 3 * 256) / per_row;
+    rows -= rows % kTile;
+    *in_bytes = (2 * rows * q->sizes[0] + 255) / 256 * 256;
+    *hid_bytes = (2 * rows * hmax + 255) / 256 * 256;
+    return rows >= kTile ? rows : 0;
+}
+
+extern "C" int hpr_mlp_forward_device(hpr_mlp* q, const float* X, int64_t n, float* Y) {
+    g_err.clear();
+    if (!q || n < 0 || (n > 0 && (!X || !Y))) return fail(HPR_ERR_INVALID, "bad argument");
+    if (n == 0) return HPR_OK;
+    int64_t in_bytes = 0, hid_bytes = 0;
+    const int64_t R = device_chunk_rows(q, &in_bytes, &hid_bytes);
+    if (R == 0)
+        return fail(HPR_ERR_INVALID, "layers too wide for the %zu-byte device scratch (16 rows of the input and two "
+                    "hidden layers must fit)", kScratchBytes);
+    unsigned char* base = static_cast<unsigned char*>(q->scratch_dev);
+    uint16_t* x16 = reinterpret_cast<uint16_t*>(base);
+    uint16_t* hbuf[2] = {reinterpret_cast<uint16_t*>(base + in_bytes),
+                         reinterpret_cast<uint16_t*>(base + in_bytes + hid_bytes)};
+    const int L = q->L;
+    for (int64_t r0 = 0; r0 < n; r0 += R) {
+        const int64_t rows = n - r0 < R ? n - r0 : R;
+        hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks_for(rows * q->sizes[0])), dim3(kThreads), 0, q->st,
+                           X + r0 * q->sizes[0], x16, rows * q->sizes[0]);
+        const uint16_t* h = x16;
+        for (int i = 0; i < L; ++i) {
+            GemmArgs g{};
+            g.A = h;
+            g.sa0 = q->sizes[i];
+            g.sa1 = 1;
+            g.B = q->w16 + q->woff[i];
+            g.sb0 = q->sizes[i + 1];
+            g.sb1 = 1;
+            g.M = (int)rows;
+            g.N = q->sizes[i + 1];
+            g.K = q->sizes[i];
+            g.bias = q->w + q->boff[i];
+            g.relu = i < L - 1;
+            g.C32 = i == L - 1 ? Y + r0 * q->sizes[L] : nullptr;
+            g.C16 = i < L - 1 ? hbuf[i & 1] : nullptr;
+            gemm(g, q->st);
+            h = hbuf[i & 1];
+        }
+    }
+    MLP_HIP(hipGetLastError());
     return HPR_OK;
 }
 

@@ -18,7 +18,8 @@ def _setup():
     if not getattr(L, "_mlp_ready", False):
         L.hpr_mlp_last_error.restype = C.c_char_p
         for name in ("hpr_mlp_create", "hpr_mlp_num_params", "hpr_mlp_set_params", "hpr_mlp_get_params",
-                     "hpr_mlp_forward", "hpr_mlp_gradients", "hpr_mlp_train_step", "hpr_mlp_destroy"):
+                     "hpr_mlp_forward", "hpr_mlp_forward_device", "hpr_mlp_gradients", "hpr_mlp_train_step",
+                     "hpr_mlp_destroy"):
             getattr(L, name).restype = C.c_int
         L._mlp_ready = True
     return L
@@ -99,6 +100,11 @@ class MLP:
         _check(_setup().hpr_mlp_forward(self.ptr, X.ctypes.data_as(_F32P), C.c_int64(X.shape[0]),
                                         Y.ctypes.data_as(_F32P)))
         return Y
+
+    def forward_device(self, x_ptr: int, n: int, y_ptr: int):
+        """hpr_mlp_forward_device on caller-owned FP32 device arrays (e.g. torch tensors' data_ptr());
+        enqueued on the handle's stream, no wait, no allocation."""
+        _check(_setup().hpr_mlp_forward_device(self.ptr, C.c_void_p(x_ptr), C.c_int64(n), C.c_void_p(y_ptr)))
 
     def gradients(self, X, T):
         X, T = _f32(X), _f32(T)
