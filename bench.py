@@ -55,70 +55,72 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def write_traffic_record(fetch_dir, write_dir, workload="scuc-2000bus-500gen-T48"):
+def write_traffic_record(fetch_dir, write_dir, kernel="dual_step_fp32", workload="scuc-2000bus-500gen-T48",
+                         config="medium"):
     """The record recorded_traffic reads, from two rocprofv3 --pmc runs of this bench (FETCH_SIZE,
-    then WRITE_SIZE, `--max-iter 129 --precision fp32`): per-launch mean of the FP32 dual-step
-    kernel the solve used, each counter scaled by the ratio it gives for the stream probe's copy
-    kernel (1 GiB read and written per dispatch)."""
+    then WRITE_SIZE, `--max-iter 129 --precision fp32 --config <config>`): per-launch mean of the
+    fused FP32 step `kernel` over the solve's own last 64 launches (the schedule tuner's timing
+    launches come before the solve), each counter scaled by the ratio it gives for the stream
+    probe's copy kernel (1 GiB read and written per dispatch)."""
     import csv
     import glob
     import re
 
-    def per_kernel(d, counter):
-        out = {}
+    op = "DualOp<float>" if kernel.startswith("dual") else "PrimalOp<float>"
+
+    def load(d, counter):
+        rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] == counter:
                     name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("(anonymous namespace)::", ""))
-                    out.setdefault(name.replace("void ", "").replace("hpr::", ""), []).append(float(r["Counter_Value"]))
-        return out
+                    name = name.replace("void ", "").replace("hpr::", "")
+                    rows.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"])))
+        rows.sort()
+        return rows
 
-    f, w = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
-    mean = lambda v: sum(v) / len(v)
+    def solve_mean(rows):
+        mine = [r for r in rows if r[1].startswith(f"csr_kernel<{op}")][-64:]
+        names = sorted({r[1] for r in mine})
+        return sum(r[2] for r in mine) / len(mine), names, len(mine)
+
+    def copy_mean(rows):
+        v = [r[2] for r in rows if r[1].startswith("stream_copy_kernel")]
+        return sum(v) / len(v)
+
+    fr, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
     known = float(1 << 20)   # KiB in 1 GiB
-    cf, cw = known / mean(f["stream_copy_kernel"]), known / mean(w["stream_copy_kernel"])
-    # the variant the solve used (most launches; template arguments: op, U, non-temporal loads,
-    # sliced windows); the schedule tuner is timing-based and may pick another one in the other
-    # run, but it always times U = 1, 2, 4 with ordinary loads, so the record takes the
-    # ordinary-load variant with the solve's U from both runs (the variants move the same bytes:
-    # one pass over the matrix per launch)
-    used = max((k for k in f if k.startswith("csr_kernel<DualOp<float>")), key=lambda k: len(f[k]))
-    dual = re.sub(r", (true|false), (true|false)>$", r", false, \2>", used)
-    if dual not in f or dual not in w:
-        raise SystemExit(f"{dual} is missing from a counter run")
-    fk, wk = mean(f[dual]), mean(w[dual])
+    cfk, cwk = copy_mean(fr), copy_mean(wr)
+    cf, cw = known / cfk, known / cwk
+    fk, fnames, fn = solve_mean(fr)
+    wk, wnames, wn = solve_mean(wr)
     traffic = (fk * cf + wk * cw) * 1024
-    text = f"""# HBM traffic of the fused FP32 dual step on the 2,000-bus SCUC relaxation ({workload})
+    what = "dual half-iteration over A~" if op.startswith("Dual") else "primal half-iteration over A~^T"
+    text = f"""# HBM traffic of the fused FP32 {kernel.split('_')[0]} step on {workload}
 
-Kernel: `{dual}` (the solve of `bench.py --max-iter 129 --precision fp32` in the FETCH run used
-`{used}`), one launch = one dual half-iteration over A~ (334,616 rows, 38,288,107 stored entries
-before padding).
+Kernel: `csr_kernel<{op}, ...>`, one launch = one {what}; the solve's last {fn} / {wn} launches in the
+FETCH / WRITE runs (variants {", ".join(f"`{x}`" for x in fnames)} / {", ".join(f"`{x}`" for x in wnames)}).
 
 Commands (repository root on the GPU box; each counter in a run of its own, then this record):
 
 ```
-cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --max-iter 129 --precision fp32
-cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --max-iter 129 --precision fp32
-python bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write
+cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
+cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
+python bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write --traffic-kernel {kernel} --config {config}
 ```
 
 Calibration: the stream probe's copy kernel reads and writes 1,048,576 KiB per dispatch; FETCH_SIZE
-reports {mean(f["stream_copy_kernel"]):,.1f} KiB for it (factor {cf:.4f}), WRITE_SIZE
-{mean(w["stream_copy_kernel"]):,.1f} KiB (factor {cw:.4f}).
+reports {cfk:,.1f} KiB for it (factor {cf:.4f}), WRITE_SIZE {cwk:,.1f} KiB (factor {cw:.4f}).
 
-| counter | raw KiB per launch (mean of {len(f[dual])} / {len(w[dual])} launches) | calibrated bytes per launch |
+| counter | raw KiB per launch | calibrated bytes per launch |
 |---|---|---|
 | FETCH_SIZE | {fk:,.1f} | {fk * cf * 1024:,.0f} |
 | WRITE_SIZE | {wk:,.1f} | {wk * cw * 1024:,.0f} |
 
 traffic_bytes_per_launch: {traffic:.0f}
 sources_sha256: {sources_sha256()}   (SHA-256 of {", ".join(KERNEL_SOURCES)} under paper_2510_10891_amd/csrc, in that order)
-
-The algorithmic bytes of a launch count 4-byte column indices (314,719,640); the kernel reads 16-bit
-offsets for every row of this matrix, so the measured traffic is below the algorithmic figure, with no
-re-reads of the matrix stream.
 """
-    path = os.path.join(ROOT, "profiles", f"traffic_dual_step_fp32_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     with open(path, "w") as fh:
         fh.write(text)
     print(text)
@@ -199,7 +201,7 @@ def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
     r = oracle.solve(lp, oracle.Options(tol=1e-4, max_iter=1000000, time_limit=limit_s))
     its_per_s = r.iters / max(r.solve_s, 1e-9)
     out = dict(unit="s", cores=oracle.num_threads(), kind="oracle", iters=r.iters,
-               iters_per_s=round(its_per_s, 3), setup_s=round(r.setup_s, 3))
+               iters_per_s=round(its_per_s, 3), setup_s=round(r.setup_s, 3), host=host_info())
     if r.term == "solved":
         out["value"] = round(r.setup_s + r.solve_s, 3)
         out["sample"] = (f"full oracle solve of the same instance to 1e-4: {r.iters} iterations, "
@@ -223,7 +225,7 @@ def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
     return out
 
 
-def batch_leg(count, stream, parent="mixed"):
+def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000):
     """The reduced LPs of successive-fixing rounds (uneven sizes) solved as one batch with FP32
     storage, against the same LPs solved one after another with the same options. `parent`:
     "mixed" = parents of 30 to 1,000 buses; "medium" = 2,000-bus parents (seeds 100 + i), each
@@ -244,7 +246,7 @@ def batch_leg(count, stream, parent="mixed"):
         f"nnz total {sum(lp.nnz for lp in lps)} ({time.perf_counter() - t:.1f} s)")
     # the 2,000-bus batch is one long library call: a time limit bounds it (members still running
     # then end as time_limit and are counted as unsolved)
-    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stream=stream,
+    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=max_iter, stream=stream,
                          time_limit_s=150.0 if big else 0.0)
     t = time.perf_counter()
     b = hprlp.hpr_batch_create(lps, opts)
@@ -261,7 +263,7 @@ def batch_leg(count, stream, parent="mixed"):
     setup = infos[0].setup_s
     hprlp.hpr_batch_destroy(b)
     seq, t_seq = [], 0.0
-    for k in range(0, count, 16 if big else count):   # big members: 16 handles at a time
+    for k in range(0, count if sequential else 0, 16 if big else count):   # big members: 16 handles at a time
         handles = [hprlp.hpr_create(lp, opts) for lp in lps[k:k + (16 if big else count)]]
         if not big:
             for h in handles:
@@ -280,14 +282,21 @@ def batch_leg(count, stream, parent="mixed"):
                lps=count, nnz_total=int(sum(lp.nnz for lp in lps)),
                n_min=int(min(lp.n for lp in lps)), n_max=int(max(lp.n for lp in lps)),
                batch_s=round(t_batch, 4), lps_per_s=round(count / t_batch, 2),
-               sequential_s=round(t_seq, 4), speedup_vs_sequential=round(t_seq / t_batch, 3),
+               sequential_s=round(t_seq, 4) if sequential else None,
+               speedup_vs_sequential=round(t_seq / t_batch, 3) if sequential else None,
                solved=int(sum(i.term == "solved" for i in infos)),
                seq_solved=int(sum(i.term == "solved" for i in seq)),
                worst_rel_kkt_fp64_eval=worst, setup_s=round(setup, 2),
                iters_min=int(iters.min()), iters_median=int(np.median(iters)), iters_max=int(iters.max()),
                lp_time_to_stop_s=[round(float(q), 4) for q in np.percentile([i.solve_s for i in infos],
                                                                             [0, 50, 90, 100])],
-               iters_total=int(iters.sum()), warmed_up=not big)
+               iters_total=int(iters.sum()), warmed_up=not big,
+               unsolved=[dict(index=i, parent=lps[i].meta.get("parent"), seed=lps[i].meta.get("seed"),
+                              fixed_u=round(float(lps[i].meta.get("fixed_u", 0.0)), 4), n=lps[i].n, m=lps[i].m,
+                              nnz=int(lps[i].nnz), term=infos[i].term, iters=infos[i].iters,
+                              rel_kkt=infos[i].rel_kkt, rel_p=infos[i].rel_p, rel_d=infos[i].rel_d,
+                              rel_gap=infos[i].rel_gap, restarts=infos[i].restarts, sigma=infos[i].sigma)
+                         for i in range(count) if infos[i].term != "solved"])
     log(f"batch: {out}")
     return out
 
@@ -412,6 +421,63 @@ def ablation_leg(data, rounds, stream, formulation="compact"):
     return out
 
 
+def host_info():
+    """CPU model, logical cores and memory of the host (for the CPU baseline's context)."""
+    model, mem_gb = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return dict(cpu_model=model, logical_cpus=os.cpu_count(), mem_gib=mem_gb)
+
+
+def large_leg(steps, stream, read_gbs, copy_gbs):
+    """The 13,500-bus instance (1,000 monitored lines x (1 + 20 outages), T = 36): FP32 storage
+    against the plain FP64 solve of the same instance, `steps` timed cold solves each after one
+    warm-up, every solve to 1e-4 (FP64-evaluated), with the roofline of FP32's dominant kernel."""
+    from paper_2510_10891_amd import hprlp, scuc
+    import numpy as np
+    import torch
+
+    t = time.perf_counter()
+    data, lp = scuc.make_instance("large", 0)
+    gen_s = time.perf_counter() - t
+    log(f"large instance: m={lp.m} n={lp.n} nnz={lp.nnz} ({gen_s:.1f} s)")
+    out = dict(workload=data.cfg.name, m=lp.m, n=lp.n, nnz=lp.nnz, steps=steps)
+    res = {}
+    for name, prec in (("fp32", hprlp.HPR_FP32), ("fp64", hprlp.HPR_FP64)):
+        opts = hprlp.Options(tol=1e-4, precision=prec, max_iter=200000, profile=1, stream=stream,
+                             time_limit_s=60.0)
+        h = hprlp.hpr_create(lp, opts)
+        infos, sec = run_solves(hprlp, h, steps, 1, torch)
+        ks = hprlp.hpr_get_kernel_stats(h)
+        x, _, _ = hprlp.hpr_get_solution(h)
+        hprlp.hpr_destroy(h)
+        info = infos[-1]
+        res[name] = (info, sec, ks, x)
+        out[name] = dict(value=round(sec, 4), iters=info.iters, iters_per_s=round(info.iters / sec, 1),
+                         setup_s=round(info.setup_s, 3), setup_phases_s=ks["setup_phases_s"],
+                         solved=info.term == "solved", rel_kkt_fp64_eval=info.rel_kkt,
+                         primal_us=round(ks["primal_ms"] * 1e3, 2), dual_us=round(ks["dual_ms"] * 1e3, 2),
+                         schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
+                                   "sliced_blocks_At": ks["sliced_blocks_at"]})
+        log(f"large {name}: {info.term} iters={info.iters} solve={sec:.3f}s setup={info.setup_s:.2f}s "
+            f"primal={ks['primal_ms'] * 1e3:.1f}us dual={ks['dual_ms'] * 1e3:.1f}us {ks['setup_phases_s']}")
+    (i32, s32, k32, x32), (i64, s64, k64, x64) = res["fp32"], res["fp64"]
+    out["fp32_vs_fp64"] = dict(speedup=round(s64 / s32, 3),
+                               obj_rel_diff=abs(i32.pobj - i64.pobj) / max(1.0, abs(i64.pobj)),
+                               x_rel_diff=float(np.linalg.norm(x32 - x64) / max(1e-30, np.linalg.norm(x64))))
+    out["roofline"] = roofline(lp, k32, data.cfg.name, read_gbs, copy_gbs)
+    return out
+
+
 def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
     """Roofline record of the dominant fused kernel (the slower of the two steps, event-timed):
     the bytes its layout makes it move per launch (layout_bytes) over its average launch time,
@@ -452,8 +518,13 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="LPs in the batch leg (0: skip)")
     ap.add_argument("--batch-parent", choices=["mixed", "medium"], default="mixed",
                     help="parents of the batch's reduced LPs: 30-1,000 buses, or the 2,000-bus preset")
-    ap.add_argument("--successive", type=int, default=0,
+    ap.add_argument("--batch-no-seq", action="store_true",
+                    help="skip the one-by-one solves of the batch's LPs")
+    ap.add_argument("--batch-max-iter", type=int, default=100000)
+    ap.add_argument("--successive", type=int, default=4,
                     help="rounds of the successive-fixing leg on the bench instance (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=2,
+                    help="timed solves per precision of the 13,500-bus leg (0: skip the leg)")
     ap.add_argument("--ablation", type=int, default=0,
                     help="rounds of the scaling/precision ablation leg (successive fixing; 0: skip)")
     ap.add_argument("--warmstart", type=int, default=0,
@@ -466,9 +537,12 @@ def main():
                          "ends as time_limit and the line reports all_solved false")
     ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM traffic record under profiles/ from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--traffic-kernel", choices=["dual_step_fp32", "primal_step_fp32"], default="dual_step_fp32")
     args = ap.parse_args()
     if args.traffic_record:
-        write_traffic_record(*args.traffic_record)
+        from paper_2510_10891_amd import scuc
+        write_traffic_record(*args.traffic_record, kernel=args.traffic_kernel,
+                             workload=scuc.PRESETS[args.config].name, config=args.config)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
@@ -528,16 +602,27 @@ def main():
     roof = roofline(lp, f32["ks"], workload, read_gbs, copy_gbs)
 
 
-    batch = batch_leg(args.batch, stream, args.batch_parent) if args.batch > 0 else None
+    batch = (batch_leg(args.batch, stream, args.batch_parent, not args.batch_no_seq, args.batch_max_iter)
+             if args.batch > 0 else None)
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
     sf = None
-    if args.successive > 0:
+    if args.successive > 0 and args.formulation == "compact":
         from paper_2510_10891_amd import successive
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         r = successive.run(data, lp, rounds=args.successive, tau=0.1,
-                           opts=hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=200000, stream=stream))
-        sf = [dict(round=x.index, term=x.term, iters=x.iters, solve_s=round(x.solve_s, 3),
-                   objective=x.objective, fixed_u=round(x.fixed_u, 4), newly_fixed=x.newly_fixed) for x in r.rounds]
+                           opts=hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=200000, stream=stream),
+                           log=lambda m: log(f"successive fixing {m}"))
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        sf = dict(workload=f"{workload}: {args.successive} rounds of solve, Algorithm 1 on the device, Fix and "
+                           f"LP-Presolve (fixed columns substituted), warm-started re-solves, tau 0.1, FP32",
+                  total_s=round(total, 3),
+                  rounds=[dict(round=x.index, term=x.term, iters=x.iters, solve_s=round(x.solve_s, 3),
+                               setup_s=round(x.setup_s, 3), n=x.n, m=x.m, nnz=x.nnz, objective=x.objective,
+                               fixed_u=round(x.fixed_u, 4), newly_fixed=x.newly_fixed) for x in r.rounds])
         log(f"successive fixing: {sf}")
+    large = large_leg(args.large_steps, stream, read_gbs, copy_gbs) if args.large_steps > 0 else None
 
     abl = ablation_leg(data, args.ablation, stream, args.formulation) if args.ablation > 0 else None
 
@@ -566,6 +651,8 @@ def main():
         "iters": f32["info"].iters,
         "iters_per_s": round(f32["info"].iters / f32["sec"], 1),
         "setup_s": round(f32["info"].setup_s, 3),
+        "setup_phases_s": f32["ks"]["setup_phases_s"],
+        "setup_plus_solve_s": round(f32["info"].setup_s + f32["sec"], 3),
         "rel_kkt_fp64_eval": f32["info"].rel_kkt,
         "all_solved": all(i.term == "solved" for i in (f32["info"], f64["info"])),
         "fp64": {"value": round(f64["sec"], 5), "iters": f64["info"].iters,
@@ -580,6 +667,7 @@ def main():
         "batch": batch,
         "warm_start": warm,
         "successive_fixing": sf,
+        "large": large,
         "ablation": abl,
         "cpu_baseline": cpu,
     }

@@ -63,7 +63,9 @@ enum {
                                    d to the columns' cone (same rule for l_j, u_j) sum to at most
                                    1e-6 (-c~^T d) / ||c~||: the dual has no feasible point, so the
                                    LP has no finite optimum (unbounded when it is feasible).
-                                   Tested after the two above; FP64-evaluated. */
+                                   Tested after the two above; FP64-evaluated. With FP32 storage
+                                   the margin is 1e-3 instead of 1e-6: the iterates grow along
+                                   the ray and d carries their FP32 rounding. */
 };
 
 /* storage precision of A and of the iterates (hpr_opts.precision) */
@@ -80,9 +82,12 @@ enum {
     HPR_SCALE_BC = 4        /* divide bounds by 1 + ||b|| and the cost by 1 + ||c|| */
 };
 
-/* One LP in CSR form. Host pointers. col_idx entries lie in [0, n) with no column
- * repeated inside a row; val and c are finite; bounds may be +-INFINITY but not NaN,
- * row_lo <= row_hi, col_lo <= col_hi, a lower bound is never +inf and an upper bound
+/* One LP in CSR form. Host pointers, or device pointers of the current HIP device (e.g. torch
+ * tensors' data) when on_device = 1: the library then reads them on hpr_opts.stream (the
+ * caller's work that writes them must be ordered before the call on that stream) into host
+ * memory for the scaling and the layouts, and never keeps them. col_idx entries lie in [0, n)
+ * with no column repeated inside a row; val and c are finite; bounds may be +-INFINITY but not
+ * NaN, row_lo <= row_hi, col_lo <= col_hi, a lower bound is never +inf and an upper bound
  * never -inf. m may be 0 (row_ptr may then be NULL); n must be >= 1. */
 typedef struct {
     int32_t m, n;
@@ -96,6 +101,7 @@ typedef struct {
     const double *col_hi;       /* [n] */
     const double *c;            /* [n] */
     double obj_offset;
+    int32_t on_device;          /* 0: the arrays above are host memory; 1: device memory */
 } hpr_lp;
 
 typedef struct {
@@ -134,21 +140,30 @@ typedef struct {
                                    holding most of a block's entries, the rest read from global
                                    memory); 3 = full, split and "sliced" windows (a block walks
                                    up to 8 consecutive 16 KB windows one at a time, entries
-                                   outside them read from global memory); -1 (default) = the
-                                   mode 1, 2 or 3 picked per matrix by timing at hpr_create
+                                   outside them read from global memory); 4, 5 = as 3, with the
+                                   rows of sliced blocks regrouped to 16 (4) or 8 (5) lanes per
+                                   row, so that each window copy serves more rows; -1 (default) =
+                                   the mode 1 to 5 picked per matrix by timing at hpr_create
                                    (2 when unroll is given). Results agree to rounding across
                                    modes; modes 0, 1 and 2 sum in the same order. */
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,
                                    its check and its control step as one captured HIP graph;
                                    0: launch every kernel directly */
-    int32_t warm_fallback;      /* 1 (default): before a solve from a caller's start point, compare
-                                   the first check (one iteration) from that point with the one from
-                                   zero and start from zero when the given point's rel_kkt is not
-                                   finite or above warm_fallback_ratio times the cold one
-                                   (hpr_info.warm_start tells which start was used) */
-    double warm_fallback_ratio; /* default 1000: a guard against broken predictions; an early check
-                                   does not predict the iteration count, so a tighter race would
-                                   reject useful starts */
+    int32_t warm_fallback;      /* guard of a solve from a caller's start point (hpr_info.warm_start
+                                   tells which start each LP used): 0 = none; 1 = compare the
+                                   first check (one iteration) from that point with the one from
+                                   zero and start from zero when the point's rel_kkt is not finite
+                                   or above warm_fallback_ratio times the zero start's; 2 (default)
+                                   = run both starts to the second check (1 + check_every
+                                   iterations) and keep the point when it stopped there as solved
+                                   or its rel_kkt is finite and no higher than the zero start's
+                                   (which did not stop as solved); when every LP keeps its point
+                                   the solve continues from that run, otherwise all LPs start
+                                   again from the chosen points. The probe iterations are not
+                                   counted in hpr_info.iters; their time is in solve_s. */
+    double warm_fallback_ratio; /* mode 1's ratio, default 1000 (a guard against broken
+                                   predictions: an early check does not predict the iteration
+                                   count) */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 
@@ -187,6 +202,10 @@ typedef struct {
     int32_t blocks_at;
     int32_t sliced_blocks_a;    /* thread blocks of A's schedule with sliced windows */
     int32_t sliced_blocks_at;
+    double setup_prep_s;        /* hpr_create phases: validation, scaling, layouts, schedules (host) */
+    double setup_upload_s;      /* ... transfers, FP32 casts, allocation of the iterates */
+    double setup_tune_s;        /* ... schedule tuner */
+    double setup_power_s;       /* ... power method */
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;
@@ -213,6 +232,23 @@ int hpr_solve(hpr_handle *h, hpr_info *info);
 /* Copies the last check's point (xbar [n], ybar [m], zbar [n]) in the original space
  * to caller-owned host arrays; any may be NULL. HPR_ERR_STATE before a solve. */
 int hpr_get_solution(hpr_handle *h, double *x, double *y, double *z);
+
+/* Round and the Fixing-Strategy of Algorithm 1 (Section IV-A) on the device, for G units
+ * and T hours of binaries (u, v, w). cols [G][T][3] (host) gives the column of u (k = 0), v (1),
+ * w (2) of unit g at hour t; a negative entry means the column was removed by a presolve and
+ * its value is fixval[same index] (host, may be NULL when every entry names a column). The
+ * values are read from x [n] (host, original space) or, when x is NULL, from the bar point of
+ * the handle's last solve (unscaled on the device, the point hpr_get_solution returns). Each
+ * value is rounded with threshold tau in [0, 0.5): 1 if s >= 1 - tau, 0 if 0 <= s <= tau, -1
+ * otherwise, into rounded [G][T][3] (host int8). Then for each unit, from its second hour on,
+ * an hour is fixed while the rounded u_t, u_{t-1}, v_t, w_t are all confident and satisfy
+ * u_t - u_{t-1} = v_t - w_t and v_t + w_t <= 1; the first hour that fails ends that unit's loop
+ * (the first hour is never fixed). fixed [G][T] (host int8) receives 1 for the fixed hours.
+ * Applying the fixings (the paper's Fix operator) is the caller's: equal column bounds through
+ * hpr_set_bounds, or a presolved LP. HPR_ERR_INVALID for bad sizes, columns, values or tau;
+ * HPR_ERR_STATE when x is NULL before a solve. */
+int hpr_fix_binaries(hpr_handle *h, const double *x, int32_t G, int32_t T, const int32_t *cols,
+                     const double *fixval, double tau, int8_t *fixed, int8_t *rounded);
 
 /* Kernel timings of the last solve (zeros unless it ran with hpr_opts.profile = 1). */
 int hpr_get_kernel_stats(hpr_handle *h, hpr_kernel_stats *out);

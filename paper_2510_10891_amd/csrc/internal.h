@@ -18,6 +18,7 @@ constexpr int kColQ = 12;        // FP64 quantities of the column check
 constexpr int kColOff = 9;       // per-LP sums: [0, kRowQ) rows, [kColOff, kColOff + kColQ) columns
 constexpr int kSumStride = 24;
 constexpr double kInfeasTol = 1e-6;   // relative margin of the infeasibility certificates
+constexpr double kRayTol32 = 1e-3;    // ... of the dual infeasibility test with FP32 storage
 constexpr int kChunk = 8192;     // entries per block of the segmented vector kernels
 constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 
@@ -172,10 +173,16 @@ void launch_seg_start_vector(double* v, const int64_t* seg, int nlp, int max_chu
                              hipStream_t st);
 void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, const double* factor,
                       hipStream_t st);
+// hist[l] = sqrt(sums[l * kSumStride]), fac[l] = 1 / hist[l] (1 when it is 0), for l < nlp
+void launch_power_norms(const double* sums, int nlp, double* hist, double* fac, hipStream_t st);
 // original-space point: x = beta_b dc xb, y = beta_c dr yb, z = beta_c zb / dc (FP64 out)
 template <typename T>
 void launch_unscale(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v, const double* dr,
                     const double* dc, const Ctrl* ctrl, double* x, double* y, double* z, hipStream_t st);
+// Round and the Fixing-Strategy of Algorithm 1 for G units and T hours (one thread per unit):
+// cols, fixval, rounded [G][T][3] (col < 0: value fixval), fixed [G][T].
+void launch_fix_strategy(const double* x, const int32_t* cols, const double* fixval, int G, int T, double tau,
+                         int8_t* fixed, int8_t* rounded, hipStream_t st);
 // FP64 -> T copy
 template <typename T>
 void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st);

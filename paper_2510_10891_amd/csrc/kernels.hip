@@ -36,7 +36,7 @@ struct CheckValues {
 // The relative KKT residuals of the original problem and the merit from the check sums
 // (see CheckRowsOp / CheckColsOp). Written without FMA contraction so that the device
 // takes the same decisions as an IEEE host evaluation of the same formulas.
-__device__ CheckValues check_values(const double* s, const Ctrl& c, const LpState& S) {
+__device__ CheckValues check_values(const double* s, const Ctrl& c, const LpState& S, double ray_tol) {
 #pragma clang fp contract(off)
     const double* r = s;
     const double* k = s + kColOff;
@@ -61,9 +61,9 @@ __device__ CheckValues check_values(const double* s, const Ctrl& c, const LpStat
     v.infeasible = h > kInfeasTol * mag && k[8] <= kInfeasTol * r[7];
     // A direction d with c~'d < 0 inside the rows' and columns' recession cones shows that the
     // dual has no feasible point; d = the step's primal move, accepted when its cone violations
-    // are at most 1e-6 of the cost decrease in units of d.
+    // are at most ray_tol of the cost decrease in units of d.
     const double g = k[9], vr = sqrt(r[8]), vc = sqrt(k[10]), nc = sqrt(k[11]);
-    v.unbounded = g < 0.0 && nc > 0.0 && vr + vc <= kInfeasTol * (-g / nc);
+    v.unbounded = g < 0.0 && nc > 0.0 && vr + vc <= ray_tol * (-g / nc);
     return v;
 }
 
@@ -132,6 +132,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
     }
     __syncthreads();
     const int l = threadIdx.x;
+    // the ray of the dual infeasibility test is a difference of iterates that grow along it: in
+    // FP32 storage it carries their rounding (2^-24 of their size), so it is judged at 1e-3
+    const double ray_tol = a.fp32 ? kRayTol32 : kInfeasTol;
     if (l < a.nlp) {
         Ctrl c = a.ctrl[l];
         LpState S = a.st[l];
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
             if (c.active) {
                 S.it += a.nb;
                 S.k += a.nb;
-                const CheckValues v = check_values(a.sums + (size_t)l * kSumStride, c, S);
+                const CheckValues v = check_values(a.sums + (size_t)l * kSumStride, c, S, ray_tol);
                 store_values(S, v);
                 if (v.bad) {
                     S.term = 4;   // HPR_NUMERIC_FAIL
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
             c.restart = 0;
             if (c.active && S.candidate) {
                 S.candidate = 0;
-                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
+                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S, ray_tol);
                 if (!v.bad && (v.rel_kkt <= a.tol || v.infeasible || v.unbounded)) {
                     store_values(S, v);
                     S.term = v.rel_kkt <= a.tol ? 1 : (v.infeasible ? 5 : 6);
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
             }
         } else if (a.phase == 3) {
             if (S.term != 4) {
-                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S);
+                const CheckValues v = check_values(a.sums64 + (size_t)l * kSumStride, c, S, ray_tol);
                 S.rel_p = v.rel_p;
                 S.rel_d = v.rel_d;
                 S.rel_gap = v.rel_gap;
@@ -270,6 +273,66 @@ void launch_seg_start_vector(double* v, const int64_t* seg, int nlp, int max_chu
                              hipStream_t st) {
     if (nlp <= 0 || max_chunks <= 0) return;
     hipLaunchKernelGGL(seg_start_kernel, dim3(max_chunks, nlp), dim3(kBlock), 0, st, v, seg, seed);
+}
+
+// ---------------------------------------------------------------- fixing (Section IV)
+
+// Round (Section IV-A) and the Fixing-Strategy of Algorithm 1, one thread per unit g. Each
+// hour's (u, v, w) value, x[col] for a column of the LP or fixval[entry] for one that a presolve
+// removed (col < 0), is rounded with threshold tau: 1 if s >= 1 - tau, 0 if 0 <= s <= tau, else
+// -1. Then, from the second hour on, an hour is fixed while the four rounded values it reads
+// (u_t, u_{t-1}, v_t, w_t) are all confident and satisfy u_t - u_{t-1} = v_t - w_t and
+// v_t + w_t <= 1; the first hour that fails ends the unit's loop (the first hour is never fixed).
+// Layout: cols, fixval and rounded [G][T][3], fixed [G][T].
+__device__ __forceinline__ int8_t round_tau(double s, double tau) {
+    if (s >= 1.0 - tau) return 1;
+    if (s >= 0.0 && s <= tau) return 0;
+    return -1;
+}
+
+__global__ __launch_bounds__(kBlock) void fix_strategy_kernel(const double* x, const int32_t* cols,
+                                                              const double* fixval, int G, int T, double tau,
+                                                              int8_t* fixed, int8_t* rounded) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const int64_t base = (int64_t)g * T;
+    for (int t = 0; t < T; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const int64_t e = (base + t) * 3 + k;
+            const int32_t c = cols[e];
+            rounded[e] = round_tau(c >= 0 ? x[c] : fixval[e], tau);
+        }
+    fixed[base] = 0;
+    bool on = true;
+    for (int t = 1; t < T; ++t) {
+        const int8_t* r = rounded + (base + t) * 3;
+        const int u = r[0], v = r[1], w = r[2], u_prev = rounded[(base + t - 1) * 3];
+        on = on && u >= 0 && u_prev >= 0 && v >= 0 && w >= 0 && u - u_prev == v - w && v + w <= 1;
+        fixed[base + t] = on ? 1 : 0;
+    }
+}
+
+void launch_fix_strategy(const double* x, const int32_t* cols, const double* fixval, int G, int T, double tau,
+                         int8_t* fixed, int8_t* rounded, hipStream_t st) {
+    if (G <= 0 || T <= 0) return;
+    hipLaunchKernelGGL(fix_strategy_kernel, dim3((unsigned)((G + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, x,
+                       cols, fixval, G, T, tau, fixed, rounded);
+}
+
+// power method: per LP, the norm s = sqrt(sums[l * kSumStride]) into hist[l] and the factor 1 / s
+// (1 when s = 0) that normalises the vector, without a round trip to the host
+__global__ __launch_bounds__(kMaxBatch) void power_norms_kernel(const double* sums, int nlp, double* hist,
+                                                                double* fac) {
+    const int l = threadIdx.x;
+    if (l >= nlp) return;
+    const double s = sqrt(sums[(size_t)l * kSumStride]);
+    hist[l] = s;
+    fac[l] = s > 0.0 ? 1.0 / s : 1.0;
+}
+
+void launch_power_norms(const double* sums, int nlp, double* hist, double* fac, hipStream_t st) {
+    if (nlp <= 0) return;
+    hipLaunchKernelGGL(power_norms_kernel, dim3(1), dim3(kMaxBatch), 0, st, sums, nlp, hist, fac);
 }
 
 void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, const double* factor,

@@ -90,119 +90,51 @@ struct DBuf {
 
 static void sync_stream(hipStream_t st) { HIP_OK(hipStreamSynchronize(st)); }
 
+// Allocator whose resize leaves new elements uninitialised: the large host layouts are written
+// in full by several threads, so zero-filling them first on one thread would only cost time.
 template <typename T>
-static void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
+struct NoInit : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <typename U>
+    NoInit(const NoInit<U>&) noexcept {}
+    template <typename U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <typename U, typename... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <typename T>
+using HostVec = std::vector<T, NoInit<T>>;
+
+template <typename T, typename Al>
+static void upload(DBuf& d, const std::vector<T, Al>& h, hipStream_t st) {
     d.alloc(h.size() * sizeof(T));
     if (!h.empty()) HIP_OK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
-// ---------------------------------------------------------------- host-side CSR helpers
-
-struct HostCsr {
-    int32_t rows = 0, cols = 0;
-    std::vector<int64_t> ptr;
-    std::vector<int32_t> idx;
-    std::vector<double> val;
-};
-
-// stable counting-sort transpose: entries of a column keep increasing row order
-static HostCsr transpose(const HostCsr& a) {
-    HostCsr t;
-    t.rows = a.cols;
-    t.cols = a.rows;
-    const int64_t nnz = a.ptr[a.rows];
-    t.ptr.assign((size_t)a.cols + 1, 0);
-    for (int64_t k = 0; k < nnz; ++k) t.ptr[(size_t)a.idx[k] + 1]++;
-    for (int32_t j = 0; j < a.cols; ++j) t.ptr[j + 1] += t.ptr[j];
-    std::vector<int64_t> fill(t.ptr.begin(), t.ptr.end() - 1);
-    t.idx.resize(nnz);
-    t.val.resize(nnz);
-    for (int32_t i = 0; i < a.rows; ++i)
-        for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-            const int64_t d = fill[a.idx[k]]++;
-            t.idx[d] = i;
-            t.val[d] = a.val[k];
-        }
-    return t;
-}
+// ---------------------------------------------------------------- host-side layouts
 
 // Padded layout of one matrix (structure on the host, ready for upload).
 struct Layout {
-    std::vector<int64_t> start;
-    std::vector<int32_t> col;
-    std::vector<double> val;
+    HostVec<int64_t> start;
+    HostVec<int32_t> col;
+    HostVec<double> val;
 };
 
 // 16-bit offsets of every entry from its row's smallest column (rows spanning 65536 columns
-// or more are "wide": their offsets are unused and the 32-bit indices are read instead);
-// base / top = smallest / largest column of each row
-static void short_indices(const Layout& L, std::vector<uint16_t>& col16, std::vector<int32_t>& base,
-                          std::vector<int32_t>& top, std::vector<uint8_t>& wide) {
-    const int64_t R = (int64_t)L.start.size() - 1;
-    col16.assign(L.col.size(), 0);
-    base.assign(R, 0);
-    top.assign(R, 0);
-    wide.assign(R, 0);
-    for (int64_t i = 0; i < R; ++i) {
-        const int64_t b = L.start[i], e = L.start[i + 1];
-        if (b == e) continue;
-        int32_t lo = L.col[b], hi = L.col[b];
-        for (int64_t k = b; k < e; ++k) {
-            lo = std::min(lo, L.col[k]);
-            hi = std::max(hi, L.col[k]);
-        }
-        base[i] = lo;
-        top[i] = hi;
-        if ((int64_t)hi - lo >= 65536) {
-            wide[i] = 1;
-            continue;
-        }
-        for (int64_t k = b; k < e; ++k) col16[k] = (uint16_t)(L.col[k] - lo);
-    }
-}
+// or more are "wide": their offsets are 0 and unused, the 32-bit indices are read instead);
+// base / top = smallest / largest column of each row. Rows in ranges on several threads.
+static void short_indices(const Layout& L, HostVec<uint16_t>& col16, std::vector<int32_t>& base,
+                          std::vector<int32_t>& top, std::vector<uint8_t>& wide, int threads);
 
-static Layout make_layout(const HostCsr& a) {
-    Layout L;
-    const int32_t R = a.rows;
-    L.start.resize((size_t)R + 1);
-    int64_t off = 0;
-    for (int32_t i = 0; i < R; ++i) {
-        L.start[i] = off;
-        const int64_t len = a.ptr[i + 1] - a.ptr[i];
-        off += (len + kVec - 1) / kVec * kVec;
-    }
-    L.start[R] = off;
-    L.col.resize(off);
-    L.val.resize(off);
-    std::vector<std::pair<int32_t, double>> tmp;
-    for (int32_t i = 0; i < R; ++i) {
-        int64_t d = L.start[i];
-        const int64_t b = a.ptr[i], e = a.ptr[i + 1];
-        bool sorted = true;
-        for (int64_t k = b + 1; k < e; ++k) sorted = sorted && a.idx[k - 1] < a.idx[k];
-        if (sorted) {
-            for (int64_t k = b; k < e; ++k, ++d) {
-                L.col[d] = a.idx[k];
-                L.val[d] = a.val[k];
-            }
-        } else {   // entries in column order (the sliced windows rely on it)
-            tmp.clear();
-            for (int64_t k = b; k < e; ++k) tmp.emplace_back(a.idx[k], a.val[k]);
-            std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-            for (const auto& t : tmp) {
-                L.col[d] = t.first;
-                L.val[d] = t.second;
-                ++d;
-            }
-        }
-        for (; d < L.start[i + 1]; ++d) {   // padding: value 0 at the row's largest column
-            L.col[d] = L.col[d - 1];
-            L.val[d] = 0.0;
-        }
-    }
-    return L;
-}
-
+// ---------------------------------------------------------------- validation
 // ---------------------------------------------------------------- validation
 
 static int validate(const hpr_lp* lp) {
@@ -253,13 +185,14 @@ static int validate_opts(const hpr_opts* o) {
     if (std::isnan(o->lambda)) return fail(HPR_ERR_INVALID, "lambda is NaN");
     if ((o->scaling & HPR_SCALE_RUIZ) && o->ruiz_iters < 0) return fail(HPR_ERR_INVALID, "ruiz_iters < 0");
     if (!(o->warm_fallback_ratio > 0)) return fail(HPR_ERR_INVALID, "warm_fallback_ratio must be > 0");
+    if (o->warm_fallback < 0 || o->warm_fallback > 2) return fail(HPR_ERR_INVALID, "warm_fallback must be 0, 1 or 2");
     if (!(o->sigma_smoothing > 0 && o->sigma_smoothing <= 1) ||
         !(o->sigma_smoothing_warm > 0 && o->sigma_smoothing_warm <= 1))
         return fail(HPR_ERR_INVALID, "sigma_smoothing and sigma_smoothing_warm must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
-    if (o->lds_windows < -1 || o->lds_windows > 3)
-        return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1, 2 or 3");
+    if (o->lds_windows < -1 || o->lds_windows > 5)
+        return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1, 2, 3, 4 or 5");
     return HPR_OK;
 }
 
@@ -283,51 +216,129 @@ struct LpHost {
     std::vector<double> x_start, y_start;       // start point in the original space (empty = zero)
 };
 
+// Runs f(0) .. f(n - 1) on up to `threads` threads; the first exception is rethrown here.
+template <typename F>
+static void parallel_for(int n, int threads, F f) {
+    if (n <= 0) return;
+    threads = std::max(1, std::min(threads, n));
+    if (threads == 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::exception_ptr> errs((size_t)threads);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            try {
+                for (int i = next++; i < n; i = next++) f(i);
+            } catch (...) {
+                errs[t] = std::current_exception();
+            }
+        });
+    for (std::thread& th : pool) th.join();
+    for (std::exception_ptr& e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
+static int host_threads() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(8u, hw ? hw : 1u));
+}
+
+static void short_indices(const Layout& L, HostVec<uint16_t>& col16, std::vector<int32_t>& base,
+                          std::vector<int32_t>& top, std::vector<uint8_t>& wide, int threads) {
+    const int64_t R = (int64_t)L.start.size() - 1;
+    col16.resize(L.col.size());
+    base.assign(R, 0);
+    top.assign(R, 0);
+    wide.assign(R, 0);
+    constexpr int kChunks = 64;
+    parallel_for(kChunks, threads, [&](int p) {
+        for (int64_t i = R * p / kChunks; i < R * (p + 1) / kChunks; ++i) {
+            const int64_t b = L.start[i], e = L.start[i + 1];
+            if (b == e) continue;
+            int32_t lo = L.col[b], hi = L.col[b];
+            for (int64_t k = b; k < e; ++k) {
+                lo = std::min(lo, L.col[k]);
+                hi = std::max(hi, L.col[k]);
+            }
+            base[i] = lo;
+            top[i] = hi;
+            const bool w = (int64_t)hi - lo >= 65536;
+            wide[i] = w ? 1 : 0;
+            for (int64_t k = b; k < e; ++k) col16[k] = w ? (uint16_t)0 : (uint16_t)(L.col[k] - lo);
+        }
+    });
+}
+
+// The host preparation walks the caller's CSR in kParts row ranges of about equal entry
+// counts (a fixed partition, so sums combine in the same order whatever the thread count).
+constexpr int kParts = 16;
+
+static std::vector<int32_t> row_parts(const hpr_lp* lp) {
+    std::vector<int32_t> cut(kParts + 1, lp->m);
+    cut[0] = 0;
+    const int64_t nnz = lp->m > 0 ? lp->row_ptr[lp->m] : 0;
+    int32_t i = 0;
+    for (int p = 1; p < kParts; ++p) {
+        const int64_t goal = nnz * p / kParts;
+        while (i < lp->m && lp->row_ptr[i] < goal) ++i;
+        cut[p] = std::max(cut[p - 1], i);
+    }
+    return cut;
+}
+
 // Section III-A: optional Ruiz passes (rows/columns divided by the square root of their
 // largest magnitude), Pock-Chambolle with alpha = 1 (divided by the square root of the
 // absolute row/column sums; empty ones keep 1), then the bounds are divided by
 // beta_b = 1 + ||b~|| (b~ the finite sides of the scaled rows) and the cost by
-// beta_c = 1 + ||c~||. Scales `a` in place and fills the LP's scaled vectors.
-static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& h) {
+// beta_c = 1 + ||c~||. Fills the LP's diagonal scaling and scaled vectors; the scaled matrix
+// entries are a_ij dr_i dc_j, formed where the layouts are written (make_layouts).
+static void scale_host(const hpr_lp* lp, const hpr_opts& o, LpHost& h, const std::vector<int32_t>& cut,
+                       int threads) {
     const int32_t m = lp->m, n = lp->n;
     h.dr.assign((size_t)m, 1.0);
     h.dc.assign((size_t)n, 1.0);
-    std::vector<double> er((size_t)m), ec((size_t)n);
-    auto apply = [&]() {
-        for (int32_t i = 0; i < m; ++i)
-            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) a.val[k] *= er[i] * ec[a.idx[k]];
-        for (int32_t i = 0; i < m; ++i) h.dr[i] *= er[i];
-        for (int32_t j = 0; j < n; ++j) h.dc[j] *= ec[j];
-    };
-    if (o.scaling & HPR_SCALE_RUIZ) {
-        for (int32_t it = 0; it < o.ruiz_iters; ++it) {
-            std::fill(ec.begin(), ec.end(), 0.0);
-            for (int32_t i = 0; i < m; ++i) {
+    std::vector<double> ec((size_t)n);
+    std::vector<std::vector<double>> part(kParts);
+    const int64_t* rp = lp->row_ptr;
+    // one pass: per-row reduction into dr (row factor), per-column partials combined in part order;
+    // `sum` selects absolute sums (Pock-Chambolle) or maxima (Ruiz)
+    auto pass = [&](bool sum) {
+        parallel_for(kParts, threads, [&](int p) {
+            std::vector<double>& col = part[p];
+            col.assign((size_t)n, 0.0);
+            for (int32_t i = cut[p]; i < cut[p + 1]; ++i) {
+                const double di = h.dr[i];
                 double r = 0.0;
-                for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-                    const double v = std::fabs(a.val[k]);
-                    r = std::max(r, v);
-                    ec[a.idx[k]] = std::max(ec[a.idx[k]], v);
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                    const int32_t j = lp->col_idx[k];
+                    const double v = std::fabs(lp->val[k] * di * h.dc[j]);
+                    if (sum) {
+                        r += v;
+                        col[j] += v;
+                    } else {
+                        r = std::max(r, v);
+                        col[j] = std::max(col[j], v);
+                    }
                 }
-                er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
+                h.dr[i] = di * (r > 0 ? 1.0 / std::sqrt(r) : 1.0);
             }
-            for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
-            apply();
-        }
-    }
-    if (o.scaling & HPR_SCALE_PC) {
-        std::fill(ec.begin(), ec.end(), 0.0);
-        for (int32_t i = 0; i < m; ++i) {
-            double r = 0.0;
-            for (int64_t k = a.ptr[i]; k < a.ptr[i + 1]; ++k) {
-                r += std::fabs(a.val[k]);
-                ec[a.idx[k]] += std::fabs(a.val[k]);
+        });
+        parallel_for(kParts, threads, [&](int p) {   // columns in kParts ranges
+            const int32_t j0 = (int32_t)((int64_t)n * p / kParts), j1 = (int32_t)((int64_t)n * (p + 1) / kParts);
+            for (int32_t j = j0; j < j1; ++j) {
+                double c = 0.0;
+                for (int q = 0; q < kParts; ++q) c = sum ? c + part[q][j] : std::max(c, part[q][j]);
+                ec[j] = c;
+                h.dc[j] *= c > 0 ? 1.0 / std::sqrt(c) : 1.0;
             }
-            er[i] = r > 0 ? 1.0 / std::sqrt(r) : 1.0;
-        }
-        for (int32_t j = 0; j < n; ++j) ec[j] = ec[j] > 0 ? 1.0 / std::sqrt(ec[j]) : 1.0;
-        apply();
-    }
+        });
+    };
+    if (o.scaling & HPR_SCALE_RUIZ)
+        for (int32_t it = 0; it < o.ruiz_iters; ++it) pass(false);
+    if (o.scaling & HPR_SCALE_PC) pass(true);
     h.lo_s.resize(m);
     h.hi_s.resize(m);
     for (int32_t i = 0; i < m; ++i) {
@@ -371,6 +382,95 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, HostCsr& a, LpHost& 
     h.norm_b = std::sqrt(b2);
     h.norm_c = std::sqrt(c2);
     h.obj_offset = lp->obj_offset;
+}
+
+// Padded layouts of A~ = Dr A Dc (rows of the caller's CSR, each put in column order) and of
+// A~^T (rows = columns of A, each in increasing row order: a stable counting sort, partition by
+// partition), written straight from the caller's arrays: every row's storage is padded to a
+// multiple of 4 entries with value 0 at the row's largest column.
+static void make_layouts(const hpr_lp* lp, const LpHost& h, const std::vector<int32_t>& cut, int threads,
+                         Layout& la, Layout& lt) {
+    const int32_t m = lp->m, n = lp->n;
+    const int64_t* rp = lp->row_ptr;
+    auto pad = [](int64_t len) { return (len + kVec - 1) / kVec * kVec; };
+    // A~: offsets, then rows filled in parallel
+    la.start.resize((size_t)m + 1);
+    int64_t off = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        la.start[i] = off;
+        off += pad(rp[i + 1] - rp[i]);
+    }
+    la.start[m] = off;
+    la.col.resize(off);
+    la.val.resize(off);
+    // A~^T: per-partition column counts, padded row lengths, each partition's first slot per column
+    std::vector<std::vector<int64_t>> cnt(kParts);
+    parallel_for(kParts, threads, [&](int p) {
+        cnt[p].assign((size_t)n, 0);
+        for (int64_t k = (m ? rp[cut[p]] : 0); k < (m ? rp[cut[p + 1]] : 0); ++k) cnt[p][lp->col_idx[k]]++;
+    });
+    lt.start.resize((size_t)n + 1);
+    int64_t toff = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        lt.start[j] = toff;
+        int64_t len = 0;
+        for (int p = 0; p < kParts; ++p) {
+            const int64_t c = cnt[p][j];
+            cnt[p][j] = toff + len;     // first slot of partition p in row j of A~^T
+            len += c;
+        }
+        toff += pad(len);
+    }
+    lt.start[n] = toff;
+    lt.col.resize(toff);
+    lt.val.resize(toff);
+    parallel_for(kParts, threads, [&](int p) {
+        std::vector<std::pair<int32_t, double>> tmp;
+        std::vector<int64_t>& slot = cnt[p];
+        for (int32_t i = cut[p]; i < cut[p + 1]; ++i) {
+            const int64_t b = rp[i], e = rp[i + 1];
+            const double di = h.dr[i];
+            int64_t d = la.start[i];
+            bool sorted = true;
+            for (int64_t k = b + 1; k < e; ++k) sorted = sorted && lp->col_idx[k - 1] < lp->col_idx[k];
+            if (sorted) {
+                for (int64_t k = b; k < e; ++k, ++d) {
+                    const int32_t j = lp->col_idx[k];
+                    la.col[d] = j;
+                    la.val[d] = lp->val[k] * di * h.dc[j];
+                }
+            } else {   // entries in column order (the sliced windows rely on it)
+                tmp.clear();
+                for (int64_t k = b; k < e; ++k) tmp.emplace_back(lp->col_idx[k], lp->val[k]);
+                std::sort(tmp.begin(), tmp.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+                for (const auto& t : tmp) {
+                    la.col[d] = t.first;
+                    la.val[d] = t.second * di * h.dc[t.first];
+                    ++d;
+                }
+            }
+            for (int64_t q = la.start[i]; q < d; ++q) {   // scatter into A~^T, rows in increasing order
+                const int64_t s2 = slot[la.col[q]]++;
+                lt.col[s2] = i;
+                lt.val[s2] = la.val[q];
+            }
+            for (; d < la.start[i + 1]; ++d) {   // padding: value 0 at the row's largest column
+                la.col[d] = la.col[d - 1];
+                la.val[d] = 0.0;
+            }
+        }
+    });
+    // padding of A~^T rows: after the last partition's entries of each row
+    parallel_for(kParts, threads, [&](int p) {
+        const int32_t j0 = (int32_t)((int64_t)n * p / kParts), j1 = (int32_t)((int64_t)n * (p + 1) / kParts);
+        for (int32_t j = j0; j < j1; ++j) {
+            const int64_t used = cnt[kParts - 1][j];   // one past the last entry of row j
+            for (int64_t d = used; d < lt.start[j + 1]; ++d) {
+                lt.col[d] = lt.col[d - 1];
+                lt.val[d] = 0.0;
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------- pooled matrices and schedules
@@ -457,13 +557,16 @@ static void slice_block(BlockDesc& d, const int32_t* rows_of_block,
 // "full" window, wlen > 0. Otherwise, the two consecutive aligned tiles (2 tiles = win_max
 // columns, clipped to the vector's ncols entries) holding most of the block's entries become
 // a "split" window (wlen < 0) when they hold at least half of the entries and no fewer
-// entries than the window has columns.
+// entries than the window has columns. Blocks that get neither may get sliced windows
+// (`sliced`). With slice_cap >= 0, the rows of such blocks in bins above slice_cap are instead
+// regrouped into blocks of bin slice_cap (2^slice_cap lanes per row, so more rows share each
+// window copy) before their windows are sliced; rows stay in index order.
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
                           const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
                           const TileCounts& tc, int64_t ncols,
                           const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
-                          std::vector<RowRef>& rows, std::vector<BlockDesc>& sched, std::vector<int32_t>& seg,
-                          std::vector<int32_t>& cum) {
+                          int slice_cap, std::vector<RowRef>& rows, std::vector<BlockDesc>& sched,
+                          std::vector<int32_t>& seg, std::vector<int32_t>& cum) {
     std::vector<std::pair<int32_t, int64_t>> tiles;
     cum.clear();
     const int L = (int)lp_rows.size() - 1;
@@ -471,6 +574,77 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
     sched.clear();
     seg.assign((size_t)L + 1, 0);
     std::vector<int32_t> by_bin[kNumBins];
+    std::vector<int32_t> deferred;   // rows of blocks to regroup at bin slice_cap
+    // the block of rows list[0 .. count): its row list entries and its LDS windows; returns false
+    // (nothing emitted) when the block is to be regrouped
+    auto emit = [&](int b, int l, const int32_t* list, int32_t count, bool may_defer) -> bool {
+        BlockDesc d;
+        d.bin = b;
+        d.lp = l;
+        d.first = (int32_t)rows.size();
+        d.count = count;
+        int64_t wlo = INT64_MAX, whi = -1, entries = 0;
+        bool any_wide = false;
+        for (int32_t r = 0; r < count; ++r) {
+            const int32_t i = list[r];
+            const int32_t quads = (int32_t)((start[i + 1] - start[i]) / kVec);
+            if (quads == 0) continue;
+            any_wide = any_wide || wide[i];
+            wlo = std::min<int64_t>(wlo, base[i]);
+            whi = std::max<int64_t>(whi, top[i]);
+            entries += (int64_t)quads * kVec;
+        }
+        d.wlo = 0;
+        d.wlen = 0;
+        d.ns = 0;
+        d.cum_first = 0;
+        if (whi >= 0) wlo -= wlo % 4;   // 16-byte aligned start for the window copy
+        if (!any_wide && whi >= 0 && whi - wlo + 1 <= win_max && whi - wlo + 1 <= entries) {
+            d.wlo = (int32_t)wlo;
+            d.wlen = (int32_t)(whi - wlo + 1);
+        } else if (split && tc.tile > 0 && entries > 0) {
+            tiles.clear();
+            for (int32_t r = 0; r < count; ++r) {
+                const int32_t i = list[r];
+                for (int64_t t = tc.ptr[i]; t < tc.ptr[i + 1]; ++t) tiles.emplace_back(tc.id[t], tc.cnt[t]);
+            }
+            std::sort(tiles.begin(), tiles.end());
+            size_t w = 0;   // merge equal tiles
+            for (size_t t = 0; t < tiles.size(); ++t) {
+                if (w > 0 && tiles[w - 1].first == tiles[t].first) tiles[w - 1].second += tiles[t].second;
+                else tiles[w++] = tiles[t];
+            }
+            tiles.resize(w);
+            int64_t best = -1, best_in = 0;
+            for (size_t t = 0; t < tiles.size(); ++t) {
+                int64_t in = tiles[t].second;
+                if (t + 1 < tiles.size() && tiles[t + 1].first == tiles[t].first + 1) in += tiles[t + 1].second;
+                if (in > best_in) best_in = in, best = tiles[t].first;
+            }
+            if (best >= 0) {
+                const int64_t lo = best * (int64_t)tc.tile;
+                const int64_t len = std::min<int64_t>(2 * (int64_t)tc.tile, ncols - lo);
+                if (len > 0 && 2 * best_in >= entries && best_in >= len) {
+                    d.wlo = (int32_t)lo;
+                    d.wlen = -(int32_t)len;
+                }
+            }
+            if (d.wlen == 0 && sliced) {
+                if (may_defer) {
+                    deferred.insert(deferred.end(), list, list + count);
+                    return false;
+                }
+                slice_block(d, list, tiles, tc, ncols, entries, win_max, cum);
+            }
+        }
+        for (int32_t r = 0; r < count; ++r) {
+            const int32_t i = list[r];
+            const int32_t quads = (int32_t)((start[i + 1] - start[i]) / kVec);
+            rows.push_back(RowRef{i, quads | (wide[i] ? kWide : 0), base[i], (int32_t)(start[i] / kVec)});
+        }
+        sched.push_back(d);
+        return true;
+    };
     for (int l = 0; l < L; ++l) {
         seg[l] = (int32_t)sched.size();
         for (auto& v : by_bin) v.clear();
@@ -483,95 +657,27 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
         for (int b = 0; b < kNumBins; ++b) {
             const int per_block = kBlock >> b;
             const size_t bin_first = sched.size();
-            for (size_t k = 0; k < by_bin[b].size(); k += per_block) {
-                BlockDesc d;
-                d.bin = b;
-                d.lp = l;
-                d.first = (int32_t)rows.size();
-                d.count = (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k);
-                int64_t wlo = INT64_MAX, whi = -1, entries = 0;
-                bool any_wide = false;
-                for (int32_t r = 0; r < d.count; ++r) {
-                    const int32_t i = by_bin[b][k + r];
-                    const int32_t quads = (int32_t)((start[i + 1] - start[i]) / kVec);
-                    rows.push_back(RowRef{i, quads | (wide[i] ? kWide : 0), base[i], (int32_t)(start[i] / kVec)});
-                    if (quads == 0) continue;
-                    any_wide = any_wide || wide[i];
-                    wlo = std::min<int64_t>(wlo, base[i]);
-                    whi = std::max<int64_t>(whi, top[i]);
-                    entries += (int64_t)quads * kVec;
-                }
-                d.wlo = 0;
-                d.wlen = 0;
-                d.ns = 0;
-                d.cum_first = 0;
-                if (whi >= 0) wlo -= wlo % 4;   // 16-byte aligned start for the window copy
-                if (!any_wide && whi >= 0 && whi - wlo + 1 <= win_max && whi - wlo + 1 <= entries) {
-                    d.wlo = (int32_t)wlo;
-                    d.wlen = (int32_t)(whi - wlo + 1);
-                } else if (split && tc.tile > 0 && entries > 0) {
-                    tiles.clear();
-                    for (int32_t r = 0; r < d.count; ++r) {
-                        const int32_t i = by_bin[b][k + r];
-                        for (int64_t t = tc.ptr[i]; t < tc.ptr[i + 1]; ++t) tiles.emplace_back(tc.id[t], tc.cnt[t]);
-                    }
-                    std::sort(tiles.begin(), tiles.end());
-                    size_t w = 0;   // merge equal tiles
-                    for (size_t t = 0; t < tiles.size(); ++t) {
-                        if (w > 0 && tiles[w - 1].first == tiles[t].first) tiles[w - 1].second += tiles[t].second;
-                        else tiles[w++] = tiles[t];
-                    }
-                    tiles.resize(w);
-                    int64_t best = -1, best_in = 0;
-                    for (size_t t = 0; t < tiles.size(); ++t) {
-                        int64_t in = tiles[t].second;
-                        if (t + 1 < tiles.size() && tiles[t + 1].first == tiles[t].first + 1) in += tiles[t + 1].second;
-                        if (in > best_in) best_in = in, best = tiles[t].first;
-                    }
-                    if (best >= 0) {
-                        const int64_t lo = best * (int64_t)tc.tile;
-                        const int64_t len = std::min<int64_t>(2 * (int64_t)tc.tile, ncols - lo);
-                        if (len > 0 && 2 * best_in >= entries && best_in >= len) {
-                            d.wlo = (int32_t)lo;
-                            d.wlen = -(int32_t)len;
-                        }
-                    }
-                    if (d.wlen == 0 && sliced)
-                        slice_block(d, by_bin[b].data() + k, tiles, tc, ncols, entries, win_max, cum);
-                }
-                sched.push_back(d);
-            }
+            const bool may_defer = sliced && slice_cap >= 0 && b > slice_cap;
+            deferred.clear();
+            for (size_t k = 0; k < by_bin[b].size(); k += per_block)
+                emit(b, l, by_bin[b].data() + k,
+                     (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k), may_defer);
             deal_to_xcds(sched, bin_first);
+            if (!deferred.empty()) {   // regrouped: 2^slice_cap lanes per row
+                const std::vector<int32_t> list = deferred;
+                const int per = kBlock >> slice_cap;
+                const size_t first = sched.size();
+                for (size_t k = 0; k < list.size(); k += per)
+                    emit(slice_cap, l, list.data() + k, (int32_t)std::min<size_t>(per, list.size() - k), false);
+                deal_to_xcds(sched, first);
+            }
         }
     }
     seg[L] = (int32_t)sched.size();
 }
 
-// Runs f(0) .. f(n - 1) on up to `threads` threads; the first exception is rethrown here.
-template <typename F>
-static void parallel_for(int n, int threads, F f) {
-    if (n <= 0) return;
-    threads = std::max(1, std::min(threads, n));
-    std::atomic<int> next{0};
-    std::vector<std::exception_ptr> errs((size_t)threads);
-    std::vector<std::thread> pool;
-    for (int t = 0; t < threads; ++t)
-        pool.emplace_back([&, t] {
-            try {
-                for (int i = next++; i < n; i = next++) f(i);
-            } catch (...) {
-                errs[t] = std::current_exception();
-            }
-        });
-    for (std::thread& th : pool) th.join();
-    for (std::exception_ptr& e : errs)
-        if (e) std::rethrow_exception(e);
-}
-
-static int host_threads() {
-    const unsigned hw = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(8u, hw ? hw : 1u));
-}
+// lds_windows modes 4 and 5: sliced blocks regrouped with 16 and 8 lanes per row (bins 4, 3)
+static int slice_cap_of(int mode) { return mode == 4 ? 4 : (mode == 5 ? 3 : -1); }
 
 struct DevMatrix {
     DBuf start, col, col16, rows, sched, seg, val64, val32, slice_cum;
@@ -580,7 +686,8 @@ struct DevMatrix {
     std::vector<int32_t> base_h, top_h;
     std::vector<uint8_t> wide_h;
     int32_t win_max = 0;                     // LDS window limit in vector entries
-    int32_t win_mode = 2;                    // 0: no windows, 1: full, 2: full and split, 3: and sliced
+    int32_t win_mode = 2;                    // 0: no windows, 1: full, 2: full and split, 3: and sliced,
+                                             // 4, 5: sliced blocks regrouped (16, 8 lanes per row)
     int32_t has_sliced = 0;                  // the current schedule has sliced blocks
     TileCounts tiles;
     int64_t ncols = 0;                       // length of the gathered vector
@@ -589,19 +696,19 @@ struct DevMatrix {
     int32_t nrows = 0, nblocks = 0, nblocks_act = 0, unroll = 4, nontemporal = 0;
     bool use_act = false;
     int64_t padded = 0;
-    std::vector<uint16_t> c16;               // 16-bit offsets between host preparation and upload
+    HostVec<uint16_t> c16;                   // 16-bit offsets between host preparation and upload
     // host part of the upload (no HIP calls; A and A^T are prepared on two threads)
     void prepare(const Layout& L, const std::vector<int64_t>& lp_rows_in, int64_t ncols_in, bool fp32,
-                 int lds_windows) {
+                 int lds_windows, int threads) {
         nrows = (int32_t)L.start.size() - 1;
         ncols = ncols_in;
         win_mode = lds_windows < 0 ? 2 : lds_windows;
         padded = (int64_t)L.col.size();
-        start_h = L.start;
+        start_h.assign(L.start.begin(), L.start.end());
         lp_rows = lp_rows_in;
-        short_indices(L, c16, base_h, top_h, wide_h);
+        short_indices(L, c16, base_h, top_h, wide_h, threads);
         win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
-        count_tiles(L, win_max / 2);
+        count_tiles(L, win_max / 2, threads);
     }
     void upload_from(const Layout& L, bool fp32, hipStream_t st) {
         if (padded / kVec >= INT32_MAX) {
@@ -612,7 +719,7 @@ struct DevMatrix {
         upload(col, L.col, st);
         upload(col16, c16, st);
         sync_stream(st);
-        std::vector<uint16_t>().swap(c16);
+        HostVec<uint16_t>().swap(c16);
         upload(val64, L.val, st);
         if (fp32) {
             val32.alloc(L.val.size() * sizeof(float));
@@ -620,21 +727,37 @@ struct DevMatrix {
         }
         set_unroll(4, st);
     }
-    void count_tiles(const Layout& L, int32_t tile) {
+    void count_tiles(const Layout& L, int32_t tile, int threads) {
+        // rows are in column order: a row's tiles are runs of equal col / tile; counted first,
+        // then written, rows in ranges on several threads
         tiles.tile = tile;
         tiles.ptr.assign((size_t)nrows + 1, 0);
-        tiles.id.clear();
-        tiles.cnt.clear();
-        for (int32_t i = 0; i < nrows; ++i) {
-            tiles.ptr[i] = (int64_t)tiles.id.size();
-            const size_t first = tiles.id.size();
-            for (int64_t k = L.start[i]; k < L.start[i + 1]; ++k) {
-                const int32_t t = L.col[k] / tile;
-                if (tiles.id.size() > first && tiles.id.back() == t) ++tiles.cnt.back();
-                else tiles.id.push_back(t), tiles.cnt.push_back(1);
+        constexpr int kChunks = 64;
+        parallel_for(kChunks, threads, [&](int p) {
+            for (int64_t i = (int64_t)nrows * p / kChunks; i < (int64_t)nrows * (p + 1) / kChunks; ++i) {
+                int64_t runs = 0;
+                for (int64_t k = L.start[i]; k < L.start[i + 1]; ++k)
+                    runs += (k == L.start[i] || L.col[k] / tile != L.col[k - 1] / tile) ? 1 : 0;
+                tiles.ptr[i + 1] = runs;
             }
-        }
-        tiles.ptr[nrows] = (int64_t)tiles.id.size();
+        });
+        for (int32_t i = 0; i < nrows; ++i) tiles.ptr[i + 1] += tiles.ptr[i];
+        tiles.id.resize(tiles.ptr[nrows]);
+        tiles.cnt.resize(tiles.ptr[nrows]);
+        parallel_for(kChunks, threads, [&](int p) {
+            for (int64_t i = (int64_t)nrows * p / kChunks; i < (int64_t)nrows * (p + 1) / kChunks; ++i) {
+                int64_t q = tiles.ptr[i] - 1;
+                for (int64_t k = L.start[i]; k < L.start[i + 1]; ++k) {
+                    const int32_t t = L.col[k] / tile;
+                    if (k == L.start[i] || t != L.col[k - 1] / tile) {
+                        ++q;
+                        tiles.id[q] = t;
+                        tiles.cnt[q] = 0;
+                    }
+                    ++tiles.cnt[q];
+                }
+            }
+        });
     }
     // host schedules already built for a U (kept while the tuner switches between them)
     struct Built {
@@ -661,7 +784,7 @@ struct DevMatrix {
         parallel_for((int)todo.size(), threads, [&](int i) {
             Built& b = built[todo[i]];
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, b.U, b.mode >= 1 ? win_max : 0,
-                          b.mode >= 2, b.mode >= 3, b.rows, b.sched, b.seg, b.cum);
+                          b.mode >= 2, b.mode >= 3, slice_cap_of(b.mode), b.rows, b.sched, b.seg, b.cum);
         });
     }
     void set_unroll(int U, hipStream_t st) {
@@ -671,8 +794,8 @@ struct DevMatrix {
         if (!b) {
             built.push_back(Built{U, win_mode, {}, {}, {}, {}});
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, U, win_mode >= 1 ? win_max : 0,
-                          win_mode >= 2, win_mode >= 3, built.back().rows, built.back().sched, built.back().seg,
-                          built.back().cum);
+                          win_mode >= 2, win_mode >= 3, slice_cap_of(win_mode), built.back().rows, built.back().sched,
+                          built.back().seg, built.back().cum);
             b = &built.back();
         }
         unroll = U;
@@ -767,6 +890,7 @@ struct Engine {
     hpr_kernel_stats kstats{};
     bool solved_once = false;
     double setup_s = 0, solve_s = 0;
+    double t_prep = 0, t_upload = 0, t_tune = 0, t_power = 0;   // phases of hpr_create
     std::vector<double> done_at;             // per LP: seconds into the solve when it stopped
     std::vector<int32_t> warm_used, use_start_mask;   // per LP: solve started from the caller's point
 
@@ -830,7 +954,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->unroll = 0;
     o->lds_windows = -1;
     o->use_graph = 1;
-    o->warm_fallback = 1;
+    o->warm_fallback = 2;
     o->warm_fallback_ratio = 1000.0;
     o->sigma_smoothing = 1.0;
     o->sigma_smoothing_warm = 0.5;
@@ -964,7 +1088,7 @@ static void autotune(Engine* e) {
         std::vector<Cand> cand;
         for (int U : {1, 2, 4}) {
             if (tune_split) {
-                for (int mode : {1, 2, 3}) cand.push_back(Cand{U, mode, 1e30f});
+                for (int mode : {1, 2, 3, 4, 5}) cand.push_back(Cand{U, mode, 1e30f});
             } else {
                 cand.push_back(Cand{U, Mx.win_mode, 1e30f});
             }
@@ -973,6 +1097,31 @@ static void autotune(Engine* e) {
             std::vector<std::pair<int, int>> pairs;
             for (const Cand& c : cand) pairs.emplace_back(c.U, c.mode);
             Mx.prebuild(pairs, host_threads());
+            // a mode that adds no block of its kind gives the same schedule as the mode below it
+            std::vector<Cand> kept;
+            for (const Cand& c : cand) {
+                bool same = false;
+                if (tune_split && c.mode >= 2)
+                    for (const DevMatrix::Built& b : Mx.built)
+                        if (b.U == c.U && b.mode == c.mode) {
+                            // modes 3-5 differ from mode 2 only where blocks are sliced
+                            bool adds = false;
+                            for (const BlockDesc& d : b.sched) adds = adds || (c.mode == 2 ? d.wlen < 0 : d.ns > 0);
+                            same = !adds;
+                        }
+                if (!same && c.mode >= 4) {   // regrouping that changes nothing repeats a lower mode
+                    const DevMatrix::Built *me = nullptr, *lower = nullptr;
+                    for (const DevMatrix::Built& b : Mx.built) {
+                        if (b.U == c.U && b.mode == c.mode) me = &b;
+                        if (b.U == c.U && b.mode == c.mode - 1) lower = &b;
+                    }
+                    if (me && lower && me->sched.size() == lower->sched.size() &&
+                        std::memcmp(me->sched.data(), lower->sched.data(), sizeof(BlockDesc) * me->sched.size()) == 0)
+                        same = true;
+                }
+                if (!same) kept.push_back(c);
+            }
+            cand.swap(kept);
         }
         for (int round = 0; round < 3; ++round)
             for (Cand& c : cand) {
@@ -1004,8 +1153,12 @@ static void autotune(Engine* e) {
 // matrix: v <- A~(A~^T v), normalised per LP; estimate ||A~ A~^T v|| for unit v; an LP stops
 // at relative change <= power_tol or after power_max_iter products; lambda = 1.01 * estimate,
 // capped at 1 when the Pock-Chambolle scaling is on (it bounds ||A~|| by 1), and 1 when the
-// estimate is 0. Start vectors: SplitMix64 with LP-local indices.
+// estimate is 0. Start vectors: SplitMix64 with LP-local indices. The norms and the
+// normalisation stay on the device; every estimate is kept in a history that the host reads
+// every kPowerChunk products and replays the stopping rule on, in order (products after an
+// LP's stop change nothing it reports).
 static void power_method(Engine* e) {
+    constexpr int kPowerChunk = 8;
     const int L = e->L;
     hipStream_t st = e->st;
     std::vector<int64_t> seg(L + 1);
@@ -1023,7 +1176,8 @@ static void power_method(Engine* e) {
         if (e->lps[l].m == 0 || e->lps[l].nnz == 0) done[l] = 1;
     const bool any = std::find(done.begin(), done.end(), 0) != done.end();
     if (any) {
-        DBuf v, t, w, part, segd, bsegd, fac;
+        const int maxit = e->opts.power_max_iter;
+        DBuf v, t, w, part, segd, bsegd, fac, hist;
         v.alloc(sizeof(double) * std::max<int64_t>(e->M, 1));
         w.alloc(sizeof(double) * std::max<int64_t>(e->M, 1));
         t.alloc(sizeof(double) * std::max<int64_t>(e->N, 1));
@@ -1031,45 +1185,42 @@ static void power_method(Engine* e) {
         upload(segd, seg, st);
         upload(bsegd, bseg, st);
         fac.alloc(sizeof(double) * L);
-        std::vector<double> sums_h((size_t)L * kSumStride), f(L);
+        hist.alloc(sizeof(double) * L * (size_t)(kPowerChunk + 1));
+        std::vector<double> hist_h((size_t)L * kPowerChunk);
         const DevCsr<double> A = e->A.view<double>(), At = e->At.view<double>();
-        auto norms = [&](const double* p) {
+        // norms of p per LP into hist row `slot`, and p scaled to unit norm
+        auto normalise = [&](double* p, int slot) {
             launch_seg_sumsq(p, segd.as<int64_t>(), L, max_chunks, part.as<double>(), st);
             launch_finish_sums(part.as<double>(), 1, L * max_chunks, bsegd.as<int32_t>(), L, e->sums.as<double>(), 0,
                                st);
-            HIP_OK(hipMemcpyAsync(sums_h.data(), e->sums.p, sizeof(double) * L * kSumStride, hipMemcpyDeviceToHost,
-                                  st));
-            e->sync();
-        };
-        auto scale = [&](double* p) {
-            HIP_OK(hipMemcpyAsync(fac.p, f.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+            launch_power_norms(e->sums.as<double>(), L, hist.as<double>() + (size_t)slot * L, fac.as<double>(), st);
             launch_seg_scale(p, segd.as<int64_t>(), L, max_chunks, fac.as<double>(), st);
-            e->sync();
         };
         launch_seg_start_vector(v.as<double>(), segd.as<int64_t>(), L, max_chunks, e->opts.seed, st);
-        norms(v.as<double>());
-        for (int l = 0; l < L; ++l) {
-            const double nv = std::sqrt(sums_h[(size_t)l * kSumStride]);
-            f[l] = nv > 0 ? 1.0 / nv : 1.0;
-        }
-        scale(v.as<double>());
-        for (int it = 1; it <= e->opts.power_max_iter; ++it) {
-            launch_spmv<double>(At, v.as<double>(), t.as<double>(), st);
-            launch_spmv<double>(A, t.as<double>(), w.as<double>(), st);
-            norms(w.as<double>());
+        normalise(v.as<double>(), kPowerChunk);
+        for (int it0 = 1; it0 <= maxit; it0 += kPowerChunk) {
+            const int n = std::min(kPowerChunk, maxit - it0 + 1);
+            for (int k = 0; k < n; ++k) {
+                launch_spmv<double>(At, v.as<double>(), t.as<double>(), st);
+                launch_spmv<double>(A, t.as<double>(), w.as<double>(), st);
+                normalise(w.as<double>(), k);
+                std::swap(v.p, w.p);
+            }
+            HIP_OK(hipGetLastError());
+            HIP_OK(hipMemcpyAsync(hist_h.data(), hist.p, sizeof(double) * L * n, hipMemcpyDeviceToHost, st));
+            e->sync();
             bool all = true;
             for (int l = 0; l < L; ++l) {
-                const double s = std::sqrt(sums_h[(size_t)l * kSumStride]);
-                f[l] = s > 0 ? 1.0 / s : 1.0;
-                if (done[l]) continue;
-                est[l] = s;
-                if (s == 0.0) done[l] = 1;
-                else if (it > 1 && std::fabs(s - prev[l]) <= e->opts.power_tol * s) done[l] = 1;
-                else prev[l] = s;
+                for (int k = 0; k < n && !done[l]; ++k) {
+                    const int it = it0 + k;
+                    const double s = hist_h[(size_t)k * L + l];
+                    est[l] = s;
+                    if (s == 0.0) done[l] = 1;
+                    else if (it > 1 && std::fabs(s - prev[l]) <= e->opts.power_tol * s) done[l] = 1;
+                    else prev[l] = s;
+                }
                 all = all && done[l];
             }
-            scale(w.as<double>());
-            std::swap(v.p, w.p);
             if (all) break;
         }
     }
@@ -1086,49 +1237,97 @@ static void power_method(Engine* e) {
 }
 
 // Host preparation of one LP: scaling and the padded layouts of A~ and A~^T (independent per
-// LP, so a batch prepares several LPs at once; a single LP builds A~'s layout while the
-// transpose is formed).
+// LP, so a batch prepares several LPs at once with one thread each; a single LP uses several).
 struct PrepLp {
     LpHost h;
     Layout la, lt;
 };
 
-static void prep_lp(const hpr_lp* lp, const hpr_opts& o, PrepLp& p, bool two_threads) {
-    HostCsr a;
-    a.rows = lp->m;
-    a.cols = lp->n;
-    if (lp->m > 0) a.ptr.assign(lp->row_ptr, lp->row_ptr + lp->m + 1);
-    else a.ptr.assign(1, 0);
-    a.idx.assign(lp->col_idx, lp->col_idx + lp->nnz);
-    a.val.assign(lp->val, lp->val + lp->nnz);
-    scale_host(lp, o, a, p.h);
-    HostCsr at;
-    if (two_threads) {
-        std::exception_ptr err;
-        std::thread th([&] {
-            try {
-                p.la = make_layout(a);
-            } catch (...) {
-                err = std::current_exception();
-            }
-        });
-        try {
-            at = transpose(a);
-        } catch (...) {
-            th.join();
-            throw;
-        }
-        th.join();
-        if (err) std::rethrow_exception(err);
-    } else {
-        p.la = make_layout(a);
-        at = transpose(a);
-    }
-    a = HostCsr();            // free the scaled copy before the transpose's layout
-    p.lt = make_layout(at);
+static void prep_lp(const hpr_lp* lp, const hpr_opts& o, PrepLp& p, int threads) {
+    const std::vector<int32_t> cut = row_parts(lp);
+    scale_host(lp, o, p.h, cut, threads);
+    make_layouts(lp, p.h, cut, threads, p.la, p.lt);
 }
 
+// An LP whose arrays are device memory (hpr_lp.on_device), read into host copies on `st`.
+struct StagedLp {
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v, lo, hi, l, u, c;
+    hpr_lp lp{};
+};
+
+static int stage_device_lp(const hpr_lp* in, hipStream_t st, StagedLp& s) {
+    if (in->n < 1 || in->m < 0 || in->nnz < 0) return fail(HPR_ERR_INVALID, "bad m, n or nnz");
+    if (in->m == 0 && in->nnz != 0) return fail(HPR_ERR_INVALID, "nnz must be 0 when m = 0");
+    if (!in->col_lo || !in->col_hi || !in->c) return fail(HPR_ERR_INVALID, "col_lo, col_hi and c are required");
+    if (in->m > 0 && (!in->row_ptr || !in->row_lo || !in->row_hi))
+        return fail(HPR_ERR_INVALID, "row_ptr, row_lo and row_hi are required when m > 0");
+    if (in->nnz > 0 && (!in->col_idx || !in->val)) return fail(HPR_ERR_INVALID, "col_idx and val are required");
+    const size_t m = (size_t)in->m, n = (size_t)in->n, nnz = (size_t)in->nnz;
+    try {
+        s.rp.resize(m + 1);
+        s.ci.resize(nnz);
+        s.v.resize(nnz);
+        s.lo.resize(m);
+        s.hi.resize(m);
+        s.l.resize(n);
+        s.u.resize(n);
+        s.c.resize(n);
+        auto get = [&](void* dst, const void* src, size_t bytes) {
+            if (bytes) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        };
+        if (m > 0) {
+            get(s.rp.data(), in->row_ptr, sizeof(int64_t) * (m + 1));
+            get(s.lo.data(), in->row_lo, sizeof(double) * m);
+            get(s.hi.data(), in->row_hi, sizeof(double) * m);
+        } else {
+            s.rp.assign(1, 0);
+        }
+        get(s.ci.data(), in->col_idx, sizeof(int32_t) * nnz);
+        get(s.v.data(), in->val, sizeof(double) * nnz);
+        get(s.l.data(), in->col_lo, sizeof(double) * n);
+        get(s.u.data(), in->col_hi, sizeof(double) * n);
+        get(s.c.data(), in->c, sizeof(double) * n);
+        HIP_OK(hipStreamSynchronize(st));
+    } catch (const HipError& err) {
+        return err.code;
+    } catch (const std::bad_alloc&) {
+        return fail(HPR_ERR_NOMEM, "host allocation failed");
+    }
+    s.lp = hpr_lp{in->m, in->n, in->nnz, s.rp.data(), s.ci.data(), s.v.data(), s.lo.data(), s.hi.data(),
+                  s.l.data(), s.u.data(), s.c.data(), in->obj_offset, 0};
+    return HPR_OK;
+}
+
+static int engine_create_host(const hpr_lp* lps, int count, const hpr_opts* opts_in, Engine** out);
+
 static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, Engine** out) {
+    g_err.clear();
+    if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > kMaxBatch) return fail(HPR_ERR_INVALID, "count must be in [1, %d]", kMaxBatch);
+    if (!lps) return fail(HPR_ERR_INVALID, "lp is NULL");
+    bool any_dev = false;
+    for (int l = 0; l < count; ++l) any_dev = any_dev || lps[l].on_device != 0;
+    if (!any_dev) return engine_create_host(lps, count, opts_in, out);
+    std::vector<StagedLp> staged((size_t)count);
+    std::vector<hpr_lp> host((size_t)count);
+    hipStream_t st = opts_in ? (hipStream_t)opts_in->stream : nullptr;
+    for (int l = 0; l < count; ++l) {
+        if (lps[l].on_device != 0 && lps[l].on_device != 1) return fail(HPR_ERR_INVALID, "on_device must be 0 or 1");
+        if (!lps[l].on_device) {
+            host[l] = lps[l];
+            continue;
+        }
+        const int rc = stage_device_lp(&lps[l], st, staged[l]);
+        if (rc) return rc;
+        host[l] = staged[l].lp;
+    }
+    return engine_create_host(host.data(), count, opts_in, out);
+}
+
+static int engine_create_host(const hpr_lp* lps, int count, const hpr_opts* opts_in, Engine** out) {
     g_err.clear();
     if (!out) return fail(HPR_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -1173,8 +1372,8 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
         for (int c0 = 0; c0 < count; c0 += chunk) {
             const int c1 = std::min(count, c0 + chunk);
             std::vector<PrepLp> prep((size_t)(c1 - c0));
-            if (count == 1) prep_lp(&lps[0], o, prep[0], threads > 1);
-            else parallel_for(c1 - c0, threads, [&](int i) { prep_lp(&lps[c0 + i], o, prep[i], false); });
+            if (count == 1) prep_lp(&lps[0], o, prep[0], threads);
+            else parallel_for(c1 - c0, threads, [&](int i) { prep_lp(&lps[c0 + i], o, prep[i], 1); });
             for (int l = c0; l < c1; ++l) {
                 const hpr_lp* lp = &lps[l];
                 PrepLp& p = prep[l - c0];
@@ -1217,23 +1416,32 @@ static int engine_create(const hpr_lp* lps, int count, const hpr_opts* opts_in, 
             }
         }
         parallel_for(2, threads, [&](int i) {
-            if (i == 0) e->A.prepare(PA, rows_a, e->N, e->fp32, o.lds_windows);
-            else e->At.prepare(PAt, rows_at, e->M, e->fp32, o.lds_windows);
+            const int th = std::max(1, threads / 2);
+            if (i == 0) e->A.prepare(PA, rows_a, e->N, e->fp32, o.lds_windows, th);
+            else e->At.prepare(PAt, rows_at, e->M, e->fp32, o.lds_windows, th);
         });
+        const double t1 = now_s();
         e->A.upload_from(PA, e->fp32, e->st);
         e->At.upload_from(PAt, e->fp32, e->st);
         e->sync();
         upload_vectors(e.get());
         alloc_iterates(e.get());
+        const double t2 = now_s();
         if (e->fp32) autotune<float>(e.get());
         else autotune<double>(e.get());
         alloc_partials(e.get());
+        const double t3 = now_s();
         if (o.lambda > 0) {
             for (LpHost& h : e->lps) h.lambda = o.lambda;
         } else {
             power_method(e.get());
         }
         e->sync();
+        const double t4 = now_s();
+        e->t_prep = t1 - t0;
+        e->t_upload = t2 - t1;
+        e->t_tune = t3 - t2;
+        e->t_power = t4 - t3;
     } catch (const HipError& err) {
         return err.code;
     } catch (const std::bad_alloc&) {
@@ -1480,47 +1688,40 @@ void compact_schedules(Engine* e) {
     if (e->opts.use_graph) build_graphs<T>(e);
 }
 
-template <typename T>
-void solve_loop(Engine* e, double t0) {
-    const hpr_opts& o = e->opts;
-    if (o.use_graph && !e->graphs_built) build_graphs<T>(e);
-    // Warm starts fall back to the cold start (zero) for every LP whose first check from the
-    // warm point is not finite or worse than warm_fallback_ratio times the first check from zero.
-    e->warm_used.assign(e->L, 0);
-    bool any_start = false;
-    for (const LpHost& h : e->lps) any_start = any_start || !h.x_start.empty() || !h.y_start.empty();
-    if (any_start) {
-        for (int l = 0; l < e->L; ++l)
-            e->warm_used[l] = !e->lps[l].x_start.empty() || !e->lps[l].y_start.empty();
-        e->use_start_mask.clear();
-        if (o.warm_fallback) {
-            const std::vector<double> cold = probe_first_check<T>(e, false);
-            const std::vector<double> warm = probe_first_check<T>(e, true);
-            for (int l = 0; l < e->L; ++l)
-                if (e->warm_used[l] && !(std::isfinite(warm[l]) && warm[l] <= o.warm_fallback_ratio * cold[l]))
-                    e->warm_used[l] = 0;
-        }
-    }
-    e->use_start_mask = e->warm_used;
-    upload_start<T>(e, true);
-    init_control(e, true);
-    e->kstats = hpr_kernel_stats{};
-    if (o.profile && !e->ev[0])
-        for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
+// Counters of the block loop of a solve.
+struct LoopState {
     int64_t it = 0, blocks = 0;
-    int32_t launched = e->L;   // LPs whose blocks the current schedules launch
-    int32_t seen_running = e->L;
-    e->done_at.assign(e->L, -1.0);
-    while (true) {
+    int32_t launched = 0;       // LPs whose blocks the current schedules launch
+    int32_t seen_running = 0;
+};
+
+// Back to the full schedules after a run that compacted them (the graphs captured for the
+// compacted schedules are dropped; the next run captures new ones).
+void full_schedules(Engine* e) {
+    if (e->A.use_act || e->At.use_act) {
+        e->A.full();
+        e->At.full();
+        e->drop_graphs();
+    }
+}
+
+// Blocks of iterations from the state in `ls` until every LP has stopped, max_iter, or
+// `max_blocks` blocks in this call; returns the number of LPs still running.
+template <typename T>
+int32_t run_blocks(Engine* e, double t0, LoopState& ls, int64_t max_blocks) {
+    const hpr_opts& o = e->opts;
+    int32_t running = 0;
+    for (int64_t nbl = 0; nbl < max_blocks; ++nbl) {
+        const int64_t it = ls.it;
         const int nb = (int)((it == 0) ? 1 : std::min<int64_t>(o.check_every, o.max_iter - it));
-        const bool sample = o.profile && nb >= 2 && (blocks % 4 == 1);
+        const bool sample = o.profile && nb >= 2 && (ls.blocks % 4 == 1);
         hipGraphExec_t g = (nb == 1 && it == 0) ? e->g_first : (nb == o.check_every ? e->g_block : nullptr);
         if (g && !sample) HIP_OK(hipGraphLaunch(g, e->st));
         else enqueue_block<T>(e, nb, sample);
         HIP_OK(hipGetLastError());
-        it += nb;
-        blocks += 1;
-        int32_t running = read_stat(e, 0);
+        ls.it += nb;
+        ls.blocks += 1;
+        running = read_stat(e, 0);
         if (sample) {
             float a = 0.f, b = 0.f;
             HIP_OK(hipEventElapsedTime(&a, e->ev[0], e->ev[1]));
@@ -1539,25 +1740,103 @@ void solve_loop(Engine* e, double t0) {
             launch_control(control_args(e, 4, 0), e->st);
             running = read_stat(e, 0);
         }
-        if (e->L > 1 && running < seen_running) {   // per-LP time to its stop, at check granularity
+        if (e->L > 1 && running < ls.seen_running) {   // per-LP time to its stop, at check granularity
             HIP_OK(hipMemcpyAsync(e->ctrl_h.data(), e->ctrl.p, sizeof(Ctrl) * e->L, hipMemcpyDeviceToHost, e->st));
             e->sync();
             const double t = now_s() - t0;
             for (int l = 0; l < e->L; ++l)
                 if (!e->ctrl_h[l].active && e->done_at[l] < 0) e->done_at[l] = t;
-            seen_running = running;
+            ls.seen_running = running;
         }
-        if (running == 0 || it >= o.max_iter) break;
-        if (e->L > 1 && 2 * running <= launched) {
+        if (running == 0 || ls.it >= o.max_iter) break;
+        if (e->L > 1 && 2 * running <= ls.launched) {
             compact_schedules<T>(e);
-            launched = running;
+            ls.launched = running;
         }
     }
-    if (e->A.use_act || e->At.use_act) {   // the report and the solution cover every LP
-        e->A.full();
-        e->At.full();
-        e->drop_graphs();                  // captured for the compacted schedules
+    return running;
+}
+
+// From the start points selected by use_start_mask (or zero): iterates, controls and loop
+// counters of a fresh solve.
+template <typename T>
+LoopState start_run(Engine* e) {
+    full_schedules(e);
+    if (e->opts.use_graph && !e->graphs_built) build_graphs<T>(e);
+    upload_start<T>(e, true);
+    init_control(e, true);
+    e->done_at.assign(e->L, -1.0);
+    LoopState ls;
+    ls.launched = e->L;
+    ls.seen_running = e->L;
+    return ls;
+}
+
+template <typename T>
+void solve_loop(Engine* e, double t0) {
+    const hpr_opts& o = e->opts;
+    if (o.use_graph && !e->graphs_built) build_graphs<T>(e);
+    if (o.warm_fallback < 0 || o.warm_fallback > 2) {
+        fail(HPR_ERR_INVALID, "warm_fallback must be 0, 1 or 2");
+        throw HipError{HPR_ERR_INVALID};
     }
+    if (o.profile && !e->ev[0])
+        for (hipEvent_t& ev : e->ev) HIP_OK(hipEventCreate(&ev));
+    e->warm_used.assign(e->L, 0);
+    bool any_start = false;
+    for (const LpHost& h : e->lps) any_start = any_start || !h.x_start.empty() || !h.y_start.empty();
+    for (int l = 0; l < e->L; ++l) e->warm_used[l] = !e->lps[l].x_start.empty() || !e->lps[l].y_start.empty();
+    e->use_start_mask.clear();
+    bool resumed = false;
+    LoopState ls;
+    if (any_start && o.warm_fallback == 1) {
+        // Guard: an LP starts from zero when its first check (one iteration) from the caller's
+        // point is not finite or above warm_fallback_ratio times the first check from zero.
+        const std::vector<double> cold = probe_first_check<T>(e, false);
+        const std::vector<double> warm = probe_first_check<T>(e, true);
+        for (int l = 0; l < e->L; ++l)
+            if (e->warm_used[l] && !(std::isfinite(warm[l]) && warm[l] <= o.warm_fallback_ratio * cold[l]))
+                e->warm_used[l] = 0;
+    } else if (any_start && o.warm_fallback == 2) {
+        // Race to the second check (1 + check_every iterations): both starts run that far and
+        // an LP keeps the caller's point when it stopped there as solved, or when its rel_kkt is
+        // finite and no higher than the zero start's (which did not stop as solved). When every
+        // LP with a point keeps it, the warm run simply continues; otherwise all LPs start again
+        // from the chosen points.
+        std::vector<int32_t> has = e->warm_used;
+        e->use_start_mask.assign(e->L, 0);
+        LoopState lc = start_run<T>(e);
+        run_blocks<T>(e, t0, lc, 2);
+        HIP_OK(hipMemcpyAsync(e->state_h.data(), e->state.p, sizeof(LpState) * e->L, hipMemcpyDeviceToHost, e->st));
+        e->sync();
+        const std::vector<LpState> cold = e->state_h;
+        e->use_start_mask = has;
+        LoopState lw = start_run<T>(e);
+        run_blocks<T>(e, t0, lw, 2);
+        HIP_OK(hipMemcpyAsync(e->state_h.data(), e->state.p, sizeof(LpState) * e->L, hipMemcpyDeviceToHost, e->st));
+        e->sync();
+        bool all_warm = true;
+        for (int l = 0; l < e->L; ++l) {
+            if (!has[l]) continue;
+            const LpState& w = e->state_h[l];
+            const LpState& c = cold[l];
+            const bool keep = w.term == HPR_SOLVED ||
+                              (c.term != HPR_SOLVED && std::isfinite(w.rel_kkt) && w.rel_kkt <= c.rel_kkt);
+            e->warm_used[l] = keep ? 1 : 0;
+            all_warm = all_warm && keep;
+        }
+        if (all_warm) {
+            resumed = true;
+            ls = lw;
+        }
+    }
+    e->kstats = hpr_kernel_stats{};
+    if (!resumed) {
+        e->use_start_mask = e->warm_used;
+        ls = start_run<T>(e);
+    }
+    run_blocks<T>(e, t0, ls, INT64_MAX);
+    full_schedules(e);                     // the report and the solution cover every LP
     if (e->fp32) {
         // report the residuals of the returned points in FP64
         enqueue_check<double, double, float>(e, e->sums64.as<double>());
@@ -1635,12 +1914,75 @@ static int engine_get_solution(Engine* e, int i, double* x, double* y, double* z
     return HPR_OK;
 }
 
+// Round and Algorithm 1 on the device over x (host, original space) or, when x is NULL, over
+// the bar point of the last solve of LP i, unscaled on the device.
+static int engine_fix_binaries(Engine* e, int i, const double* x, int32_t G, int32_t T, const int32_t* cols,
+                               const double* fixval, double tau, int8_t* fixed, int8_t* rounded) {
+    if (i < 0 || i >= e->L) return fail(HPR_ERR_INVALID, "LP index %d out of range", i);
+    if (G < 1 || T < 1 || (int64_t)G * T > (int64_t)1 << 28) return fail(HPR_ERR_INVALID, "bad G or T");
+    if (!cols || !fixed || !rounded) return fail(HPR_ERR_INVALID, "cols, fixed and rounded are required");
+    if (!(tau >= 0.0 && tau < 0.5)) return fail(HPR_ERR_INVALID, "tau must be in [0, 0.5)");
+    const LpHost& h = e->lps[i];
+    const int64_t ne = (int64_t)G * T * 3;
+    for (int64_t k = 0; k < ne; ++k) {
+        if (cols[k] >= h.n) return fail(HPR_ERR_INVALID, "column %d out of range at entry %lld", cols[k], (long long)k);
+        if (cols[k] < 0 && (!fixval || !std::isfinite(fixval[k])))
+            return fail(HPR_ERR_INVALID, "entry %lld names no column and has no finite fixed value", (long long)k);
+    }
+    if (!x && !e->solved_once) return fail(HPR_ERR_STATE, "no solve has run on this handle");
+    if (x)
+        for (int32_t j = 0; j < h.n; ++j)
+            if (!std::isfinite(x[j])) return fail(HPR_ERR_INVALID, "non-finite x at %d", j);
+    try {
+        DBuf dcols, dfix, dx, dout;
+        // host copies live until the stream is synchronised below
+        const std::vector<int32_t> hcols(cols, cols + ne);
+        const std::vector<double> hfix = fixval ? std::vector<double>(fixval, fixval + ne) : std::vector<double>();
+        const std::vector<double> hx = x ? std::vector<double>(x, x + h.n) : std::vector<double>();
+        upload(dcols, hcols, e->st);
+        if (fixval) upload(dfix, hfix, e->st);
+        const double* xs = nullptr;
+        if (x) {
+            upload(dx, hx, e->st);
+            xs = dx.as<double>();
+        } else {
+            if (e->fp32)
+                launch_unscale<float>(e->A.view<float>(), e->At.view<float>(), e->iter<float>(), e->dr_d.as<double>(),
+                                      e->dc_d.as<double>(), e->ctrl.as<Ctrl>(), e->ux.as<double>(),
+                                      e->uy.as<double>(), e->uz.as<double>(), e->st);
+            else
+                launch_unscale<double>(e->A.view<double>(), e->At.view<double>(), e->iter<double>(),
+                                       e->dr_d.as<double>(), e->dc_d.as<double>(), e->ctrl.as<Ctrl>(),
+                                       e->ux.as<double>(), e->uy.as<double>(), e->uz.as<double>(), e->st);
+            xs = e->ux.as<double>() + h.col_off;
+        }
+        dout.alloc((size_t)ne + (size_t)G * T);
+        int8_t* d_round = dout.as<int8_t>();
+        int8_t* d_fixed = d_round + ne;
+        launch_fix_strategy(xs, dcols.as<int32_t>(), fixval ? dfix.as<double>() : nullptr, G, T, tau, d_fixed,
+                            d_round, e->st);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(rounded, d_round, (size_t)ne, hipMemcpyDeviceToHost, e->st));
+        HIP_OK(hipMemcpyAsync(fixed, d_fixed, (size_t)G * T, hipMemcpyDeviceToHost, e->st));
+        e->sync();
+    } catch (const HipError& err) {
+        return err.code;
+    } catch (const std::bad_alloc&) {
+        return fail(HPR_ERR_NOMEM, "host allocation failed");
+    }
+    return HPR_OK;
+}
+
 static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     *out = e->kstats;
     out->unroll_a = e->A.unroll;
     out->unroll_at = e->At.unroll;
     out->nontemporal_a = e->A.nontemporal;
     out->nontemporal_at = e->At.nontemporal;
+    out->setup_prep_s = e->t_prep;
+    out->setup_upload_s = e->t_upload;
+    out->setup_tune_s = e->t_tune;
+    out->setup_power_s = e->t_power;
     e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->sliced_blocks_a, out->blocks_a);
     e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->sliced_blocks_at, out->blocks_at);
     if (out->samples > 0) {
@@ -1698,6 +2040,13 @@ extern "C" int hpr_get_solution(hpr_handle* h, double* x, double* y, double* z) 
     g_err.clear();
     if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
     return engine_get_solution(h->e, 0, x, y, z);
+}
+
+extern "C" int hpr_fix_binaries(hpr_handle* h, const double* x, int32_t G, int32_t T, const int32_t* cols,
+                                const double* fixval, double tau, int8_t* fixed, int8_t* rounded) {
+    g_err.clear();
+    if (!h) return fail(HPR_ERR_INVALID, "handle is NULL");
+    return engine_fix_binaries(h->e, 0, x, G, T, cols, fixval, tau, fixed, rounded);
 }
 
 extern "C" int hpr_get_kernel_stats(hpr_handle* h, hpr_kernel_stats* out) {

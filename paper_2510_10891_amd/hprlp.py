@@ -33,7 +33,8 @@ class hpr_lp(C.Structure):
     _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
                 ("row_lo", C.c_void_p), ("row_hi", C.c_void_p), ("col_lo", C.c_void_p),
-                ("col_hi", C.c_void_p), ("c", C.c_void_p), ("obj_offset", C.c_double)]
+                ("col_hi", C.c_void_p), ("c", C.c_void_p), ("obj_offset", C.c_double),
+                ("on_device", C.c_int32)]
 
 
 class hpr_opts(C.Structure):
@@ -51,7 +52,9 @@ class hpr_kernel_stats(C.Structure):
                 ("unroll_a", C.c_int32), ("unroll_at", C.c_int32), ("nontemporal_a", C.c_int32),
                 ("nontemporal_at", C.c_int32), ("full_blocks_a", C.c_int32), ("split_blocks_a", C.c_int32),
                 ("full_blocks_at", C.c_int32), ("split_blocks_at", C.c_int32), ("blocks_a", C.c_int32),
-                ("blocks_at", C.c_int32), ("sliced_blocks_a", C.c_int32), ("sliced_blocks_at", C.c_int32)]
+                ("blocks_at", C.c_int32), ("sliced_blocks_a", C.c_int32), ("sliced_blocks_at", C.c_int32),
+                ("setup_prep_s", C.c_double), ("setup_upload_s", C.c_double), ("setup_tune_s", C.c_double),
+                ("setup_power_s", C.c_double)]
 
 
 class hpr_info(C.Structure):
@@ -64,7 +67,7 @@ class hpr_info(C.Structure):
 
 _lib = None
 EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", "hpr_solve",
-           "hpr_get_solution", "hpr_get_kernel_stats", "hpr_destroy", "hpr_batch_create", "hpr_batch_size",
+           "hpr_get_solution", "hpr_get_kernel_stats", "hpr_fix_binaries", "hpr_destroy", "hpr_batch_create", "hpr_batch_size",
            "hpr_batch_set_bounds", "hpr_batch_set_start", "hpr_batch_solve", "hpr_batch_get_solution",
            "hpr_batch_get_kernel_stats", "hpr_batch_destroy", "hpr_probe_stream", "hpr_last_error")
 
@@ -116,7 +119,7 @@ class Options:
     unroll: int = 0
     lds_windows: int = -1
     use_graph: int = 1
-    warm_fallback: int = 1
+    warm_fallback: int = 2
     warm_fallback_ratio: float = 1000.0
     stream: int = 0
 
@@ -133,7 +136,9 @@ def _kstats(s: hpr_kernel_stats) -> dict:
                 unroll_at=s.unroll_at, nt_a=s.nontemporal_a, nt_at=s.nontemporal_at,
                 full_blocks_a=s.full_blocks_a, split_blocks_a=s.split_blocks_a, full_blocks_at=s.full_blocks_at,
                 split_blocks_at=s.split_blocks_at, blocks_a=s.blocks_a, blocks_at=s.blocks_at,
-                sliced_blocks_a=s.sliced_blocks_a, sliced_blocks_at=s.sliced_blocks_at)
+                sliced_blocks_a=s.sliced_blocks_a, sliced_blocks_at=s.sliced_blocks_at,
+                setup_phases_s=dict(prep=round(s.setup_prep_s, 4), upload=round(s.setup_upload_s, 4),
+                                    tune=round(s.setup_tune_s, 4), power=round(s.setup_power_s, 4)))
 
 
 def hpr_default_opts() -> hpr_opts:
@@ -183,7 +188,40 @@ class _LPArrays:
         nnz = len(self.ci)   # the library checks row_ptr[m] == nnz
         ptr = lambda a: a.ctypes.data if a.size else None
         self.s = hpr_lp(lp.m, lp.n, nnz, ptr(self.rp), ptr(self.ci), ptr(self.v), ptr(self.lo),
-                        ptr(self.hi), ptr(self.l), ptr(self.u), ptr(self.c), float(lp.obj_offset))
+                        ptr(self.hi), ptr(self.l), ptr(self.u), ptr(self.c), float(lp.obj_offset), 0)
+
+
+class DeviceLP:
+    """An LP whose arrays are torch tensors on the GPU (hpr_lp.on_device = 1): int64 row_ptr,
+    int32 col_idx, float64 val and bounds and cost, as in hprlp.h. The tensors are kept alive
+    with the struct; the library copies what it needs during hpr_create."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, row_lo, row_hi, col_lo, col_hi, c, obj_offset=0.0):
+        import torch
+        want = [(row_ptr, torch.int64, m + 1, "row_ptr"), (col_idx, torch.int32, None, "col_idx"),
+                (val, torch.float64, None, "val"), (row_lo, torch.float64, m, "row_lo"),
+                (row_hi, torch.float64, m, "row_hi"), (col_lo, torch.float64, n, "col_lo"),
+                (col_hi, torch.float64, n, "col_hi"), (c, torch.float64, n, "c")]
+        for t, dt, length, name in want:
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == 1):
+                raise ValueError(f"{name} must be a contiguous 1-D {dt} CUDA tensor")
+            if length is not None and t.numel() != length and not (name == "row_ptr" and m == 0):
+                raise ValueError(f"{name} has {t.numel()} entries, expected {length}")
+        if col_idx.numel() != val.numel():
+            raise ValueError("col_idx and val differ in length")
+        self.m, self.n = int(m), int(n)
+        self.keep = [row_ptr, col_idx, val, row_lo, row_hi, col_lo, col_hi, c]
+        ptr = lambda t: t.data_ptr() if t.numel() else None
+        self.s = hpr_lp(self.m, self.n, int(col_idx.numel()), ptr(row_ptr), ptr(col_idx), ptr(val), ptr(row_lo),
+                        ptr(row_hi), ptr(col_lo), ptr(col_hi), ptr(c), float(obj_offset), 1)
+
+
+def hpr_create_device(dlp: DeviceLP, opts: Options | None = None) -> "Handle":
+    """hpr_create from device arrays (DeviceLP)."""
+    o = (opts or Options()).to_c()
+    out = C.c_void_p()
+    _check(lib().hpr_create(C.byref(dlp.s), C.byref(o), C.byref(out)))
+    return Handle(out, dlp.m, dlp.n)
 
 
 class Handle:
@@ -250,6 +288,30 @@ def hpr_get_solution(h: Handle):
     _check(lib().hpr_get_solution(h.ptr, x.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p),
                                   z.ctypes.data_as(C.c_void_p)))
     return x, y[:h.m], z
+
+
+def hpr_fix_binaries(h: Handle, cols, tau: float, x=None, fixval=None):
+    """Round and Algorithm 1 on the device (hpr_fix_binaries): cols [G][T][3] LP columns of
+    (u, v, w), negative where presolve removed the column (its value then from fixval, same
+    shape); x: original-space point, or None for the last solve's bar point on the device.
+    Returns (fixed [G][T] bool, rounded [G][T][3] int8)."""
+    cols = np.ascontiguousarray(cols, np.int32)
+    if cols.ndim != 3 or cols.shape[2] != 3:
+        raise ValueError(f"cols has shape {cols.shape}, expected (G, T, 3)")
+    G, T = cols.shape[:2]
+    fv = None
+    if fixval is not None:
+        fv = np.ascontiguousarray(fixval, np.float64)
+        if fv.shape != cols.shape:
+            raise ValueError(f"fixval has shape {fv.shape}, expected {cols.shape}")
+    xa = _vec(x, h.n, "x")
+    fixed = np.zeros((G, T), np.int8)
+    rounded = np.zeros((G, T, 3), np.int8)
+    _check(lib().hpr_fix_binaries(h.ptr, None if xa is None else xa.ctypes.data_as(C.c_void_p), C.c_int32(G),
+                                  C.c_int32(T), cols.ctypes.data_as(C.c_void_p),
+                                  None if fv is None else fv.ctypes.data_as(C.c_void_p), C.c_double(tau),
+                                  fixed.ctypes.data_as(C.c_void_p), rounded.ctypes.data_as(C.c_void_p)))
+    return fixed.astype(bool), rounded
 
 
 def hpr_get_kernel_stats(h: Handle) -> dict:

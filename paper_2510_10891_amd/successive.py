@@ -1,11 +1,14 @@
 """Successive fixing (Algorithm 2) around the GPU LP solver, without the MILP presolve and
 the final MILP solve (both need a MILP solver).
 
-Each round solves the current LP relaxation, runs the Fixing-Strategy (Algorithm 1) on the
-relaxed binaries and applies Fix(M, S, s) by setting equal column bounds. One solver handle
-serves every round: the matrix, its scaling and lambda stay on the GPU, only the bounds
-change, and each round starts from the previous round's solution (projected onto the new
-bounds), so the re-solves are cheap. Rounds whose LP cannot be solved stop the loop.
+Each round solves the current LP relaxation, runs Round and the Fixing-Strategy (Algorithm 1)
+on the device over the relaxed binaries of the bar point the solve left in HBM
+(hpr_fix_binaries), and applies Fix(M, S, s) by setting equal column bounds. With `presolve`
+(Algorithm 2's LP-Presolve step, the default) the next round's LP is the fixed LP with its
+fixed columns substituted out and emptied rows dropped, on a handle of its own; without it one
+handle serves every round and only the bounds change. A round starts from the previous round's
+solution (restricted to the columns and rows it keeps) when `warm`. A round whose LP cannot be
+solved (or that presolve finds infeasible) stops the loop.
 """
 from __future__ import annotations
 
@@ -27,6 +30,11 @@ class Round:
     rel_kkt: float
     fixed_u: float          # fraction of all u fixed after this round
     newly_fixed: int
+    setup_s: float = 0.0    # creation of the round's handle (presolved LP), 0 when it was reused
+    n: int = 0              # columns, rows and stored entries of the LP the round solved
+    m: int = 0
+    nnz: int = 0
+    fixed: np.ndarray | None = None   # [G][T] units-hours fixed after this round
 
 
 @dataclass
@@ -37,41 +45,82 @@ class Result:
     x: np.ndarray | None = None
 
 
+def binary_columns(G: int, T: int) -> np.ndarray:
+    """[G][T][3] columns of (u, v, w) of the compact SCUC model."""
+    t = np.arange(T)[None, :]
+    g = np.arange(G)[:, None]
+    return np.stack([scuc.col_index(G, t, var, g) for var in (scuc.U, scuc.V, scuc.W)], -1).astype(np.int32)
+
+
 def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
-        opts: hprlp.Options | None = None, warm: bool = True, log=None) -> Result:
-    """Up to `rounds` rounds of solve, Algorithm 1 and Fix on one handle; `log` (optional)
+        opts: hprlp.Options | None = None, warm: bool = True, presolve: bool = True, log=None) -> Result:
+    """Up to `rounds` rounds of solve, Algorithm 1 (device) and Fix; `log` (optional)
     receives one line per round."""
     G, T = data.cfg.n_gen, data.cfg.T
     opts = opts or hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32)
-    h = hprlp.hpr_create(lp, opts)
+    cols = binary_columns(G, T)
     res = Result()
     lo, hi = lp.col_lo.copy(), lp.col_hi.copy()
     fixed = np.zeros((G, T), bool)
-    x = y = None
+    x_full = y_full = None
+    h = None
     try:
         for i in range(1, rounds + 1):
-            if warm and x is not None:
-                hprlp.hpr_set_start(h, x, y)
+            setup = 0.0
+            if presolve:
+                pre = fixing.presolve_fixed(lp.replace(col_lo=lo, col_hi=hi))
+                if not pre.feasible:
+                    res.rounds.append(Round(i, "primal_infeasible", 0, 0.0, np.nan, np.nan, float(fixed.mean()), 0,
+                                            fixed=fixed.copy()))
+                    break
+                cur, kc, kr = pre.lp, pre.cols, pre.rows
+                if h is not None:
+                    hprlp.hpr_destroy(h)
+                t0 = time.perf_counter()
+                h = hprlp.hpr_create(cur, opts)
+                setup = time.perf_counter() - t0
+            else:
+                cur, kc, kr = lp.replace(col_lo=lo, col_hi=hi), np.arange(lp.n), np.arange(lp.m)
+                if h is None:
+                    t0 = time.perf_counter()
+                    h = hprlp.hpr_create(cur, opts)
+                    setup = time.perf_counter() - t0
+                else:
+                    hprlp.hpr_set_bounds(h, lo, hi)
+            if warm and x_full is not None:
+                hprlp.hpr_set_start(h, x_full[kc], y_full[kr])
             t0 = time.perf_counter()
             info = hprlp.hpr_solve(h)
             dt = time.perf_counter() - t0
             x, y, _ = hprlp.hpr_get_solution(h)
+            x_full = np.where(lo == hi, lo, 0.0)
+            x_full[kc] = x
+            y_full = np.zeros(lp.m)
+            y_full[kr] = y
+            shape = dict(setup_s=setup, n=cur.n, m=cur.m, nnz=cur.nnz)
             if info.term != "solved":
                 res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
-                                        float(fixed.mean()), 0))
+                                        float(fixed.mean()), 0, fixed=fixed.copy(), **shape))
                 break
-            u, v, w = fixing.gather_binaries(x, G, T)
-            new, ur, vr, wr = fixing.fixing_strategy(u, v, w, tau)
+            # Round and Algorithm 1 over the bar point in HBM: columns of the solved LP, and the
+            # values of the binaries presolve removed
+            pos = np.full(lp.n, -1, np.int64)
+            pos[kc] = np.arange(len(kc))
+            new, rounded = hprlp.hpr_fix_binaries(h, pos[cols].astype(np.int32), tau, fixval=lo[cols])
             add = new & ~fixed
-            lo, hi = fixing.fix_bounds(lp.replace(col_lo=lo, col_hi=hi), G, T, add, ur, vr, wr)
+            gg, tt = np.nonzero(add)
+            for k in range(3):
+                c = cols[gg, tt, k]
+                lo[c] = rounded[gg, tt, k]
+                hi[c] = rounded[gg, tt, k]
             fixed |= new
-            hprlp.hpr_set_bounds(h, lo, hi)
             res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
-                                    float(fixed.mean()), int(add.sum())))
+                                    float(fixed.mean()), int(add.sum()), fixed=fixed.copy(), **shape))
             if log is not None:
-                log(f"round {i}: {info.term}, {info.iters} iterations, {dt:.2f} s, "
-                    f"{fixed.mean():.3f} of u fixed")
+                log(f"round {i}: {info.term}, {info.iters} iterations, {dt:.2f} s solve, {setup:.2f} s setup, "
+                    f"n {cur.n}, {fixed.mean():.3f} of u fixed")
     finally:
-        hprlp.hpr_destroy(h)
-    res.col_lo, res.col_hi, res.x = lo, hi, x
+        if h is not None:
+            hprlp.hpr_destroy(h)
+    res.col_lo, res.col_hi, res.x = lo, hi, x_full
     return res

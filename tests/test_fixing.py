@@ -1,11 +1,14 @@
 """Algorithm 1 (Fixing-Strategy), the Round operator and the LP presolve of the
-successive-fixing loop (Section IV), on hand-worked cases and invariants."""
+successive-fixing loop (Section IV), on hand-worked cases and invariants: the oracle's
+reference (oracle/fixing.py) against the paper's text, and the product's host versions (used
+to synthesise the reduced-LP batches) against the oracle."""
 import json
 import os
 
 import numpy as np
 import pytest
 
+from oracle import fixing as ofix
 from paper_2510_10891_amd import fixing, scuc
 from tests.helpers import highs, rel
 
@@ -16,6 +19,72 @@ def test_round_operator_thresholds():
     tau = 0.1
     s = np.array([0.0, 0.1, 0.1000001, 0.5, 0.8999999, 0.9, 1.0, -1e-12])
     assert fixing.round_tau(s, tau).tolist() == [0, 0, -1, -1, -1, 1, 1, -1]
+
+
+def test_oracle_round_operator_thresholds():
+    tau = 0.1
+    s = [0.0, 0.1, 0.1000001, 0.5, 0.8999999, 0.9, 1.0, -1e-12]
+    assert [ofix.round_value(v, tau) for v in s] == [0, 0, -1, -1, -1, 1, 1, -1]
+
+
+def cols_of(G, T):
+    """[G][T][3] columns of (u, v, w) when unit g's hour t holds them at 3 (g T + t) + k."""
+    return [[[3 * (g * T + t) + k for k in range(3)] for t in range(T)] for g in range(G)]
+
+
+@pytest.mark.parametrize("case", GOLDEN["cases"], ids=[c["name"] for c in GOLDEN["cases"]])
+def test_oracle_algorithm1_hand_worked(case):
+    T = len(case["u"])
+    x = np.zeros(3 * T)
+    for t in range(T):
+        x[3 * t:3 * t + 3] = case["u"][t], case["v"][t], case["w"][t]
+    fixed, rounded = ofix.algorithm1(x, cols_of(1, T), case["tau"])
+    hours = (np.nonzero(fixed[0])[0] + 1).tolist()
+    assert hours == case["fixed"]
+    assert [rounded[0, h - 1].tolist() for h in hours] == case["values"]
+
+
+def test_product_algorithm1_matches_oracle_on_random_relaxations():
+    rng = np.random.default_rng(3)
+    G, T = 40, 24
+    for tau in (0.05, 0.1, 0.3):
+        u = np.clip(rng.choice([0, 1], (G, T)) + rng.normal(0, 0.1, (G, T)), 0, 1)
+        v = np.clip(np.abs(rng.normal(0.0, 0.15, (G, T))), 0, 1)
+        w = np.clip(np.abs(rng.normal(0.0, 0.15, (G, T))), 0, 1)
+        x = np.stack([u, v, w], -1).reshape(-1)
+        ofixed, orounded = ofix.algorithm1(x, cols_of(G, T), tau)
+        fixed, ur, vr, wr = fixing.fixing_strategy(u, v, w, tau)
+        assert np.array_equal(fixed, ofixed == 1)
+        assert np.array_equal(np.stack([ur, vr, wr], -1), orounded)
+
+
+def test_oracle_presolve_matches_the_products_and_keeps_the_optimum():
+    data, lp = scuc.make_instance("small", 6)
+    G, T = data.cfg.n_gen, data.cfg.T
+    u, v, w = fixing.synthetic_relaxation(G, T, 0.5, np.random.default_rng(1))
+    fixed, ur, vr, wr = fixing.fixing_strategy(u, v, w, 0.1)
+    lo, hi = fixing.fix_bounds(lp, G, T, fixed, ur, vr, wr)
+    full = lp.replace(col_lo=lo, col_hi=hi)
+    red, kc, kr, feasible = ofix.presolve_fixed(full)
+    pre = fixing.presolve_fixed(full)
+    assert feasible and pre.feasible
+    assert np.array_equal(kc, pre.cols) and np.array_equal(kr, pre.rows)
+    assert np.array_equal(red.row_ptr, pre.lp.row_ptr) and np.array_equal(red.col_idx, pre.lp.col_idx)
+    assert np.array_equal(red.val, pre.lp.val)
+    for a, b in ((red.row_lo, pre.lp.row_lo), (red.row_hi, pre.lp.row_hi), (red.c, pre.lp.c)):
+        fin = np.isfinite(b)
+        assert np.array_equal(np.isfinite(a), fin) and np.allclose(a[fin], b[fin], rtol=1e-12, atol=1e-12)
+    assert rel(red.obj_offset, pre.lp.obj_offset) < 1e-12
+    a_obj, _, _ = highs(full)
+    b_obj, _, _ = highs(red)
+    assert rel(a_obj, b_obj) < 1e-9
+
+
+def test_oracle_presolve_flags_a_violated_empty_row():
+    from tests.helpers import dense_lp
+    lp = dense_lp([[1.0, 0.0], [1.0, 1.0]], [2.0, 0.0], [np.inf, 5.0], [0, 0], [1, 1], [1.0, 1.0])
+    fixed = lp.replace(col_lo=np.array([1.0, 0.0]), col_hi=np.array([1.0, 1.0]))
+    assert not ofix.presolve_fixed(fixed)[3]
 
 
 @pytest.mark.parametrize("case", GOLDEN["cases"], ids=[c["name"] for c in GOLDEN["cases"]])

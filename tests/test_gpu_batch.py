@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2510_10891_amd import hprlp, scuc
-from tests.test_gpu_parity import FP64_RTOL, assert_close, assert_parity, ragged_lp
+from tests.test_gpu_parity import FP32_RTOL, FP64_RTOL, assert_close, assert_parity, ragged_lp
 
 pytestmark = pytest.mark.gpu
 
@@ -191,3 +191,35 @@ def test_batch_with_sliced_windows_matches_oracle_per_lp():
     for lp, info, (x, y, z) in zip(lps, infos, sols):
         o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=130))
         assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
+@pytest.mark.parametrize("mode", [3, 4, 5])
+@pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
+def test_sliced_windows_of_a_with_rows_out_of_column_order(mode, precision):
+    """Rows of A spread over three windows, given out of column order (the library stores them
+    in column order, which the sliced windows rely on), forced through sliced windows of A with
+    64 (mode 3), 16 (mode 4) or 8 (mode 5) lanes per row: iterates against the oracle."""
+    lp = spread_lp(7)
+    rng = np.random.default_rng(8)
+    idx, val = lp.col_idx.copy(), lp.val.copy()
+    for i in range(lp.m):
+        a, b = lp.row_ptr[i], lp.row_ptr[i + 1]
+        perm = a + rng.permutation(b - a)
+        idx[a:b], val[a:b] = idx[perm], val[perm]
+    lp = lp.replace(col_idx=idx, val=val)
+    K = 130
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K))
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=K, lds_windows=mode, unroll=2, precision=precision))
+    try:
+        info = hprlp.hpr_solve(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+        ks = hprlp.hpr_get_kernel_stats(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    assert ks["sliced_blocks_a"] > 0, ks
+    if precision == hprlp.HPR_FP64:
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+    else:
+        assert info.iters == o.iters
+        assert_close(x, o.x, FP32_RTOL * 10 * K, "x")
+        assert_close(y, o.y, FP32_RTOL * 10 * K, "y")

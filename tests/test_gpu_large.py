@@ -31,6 +31,35 @@ def test_large_fp64_and_fp32_iterates_match_oracle(large):
     assert_close(y, o65.y, 2e-4, "y")
 
 
+@pytest.fixture(scope="module")
+def large_o65(large):
+    return oracle.solve(large, oracle.Options(tol=0.0, max_iter=65, lambda_in=1.0))
+
+
+@pytest.mark.parametrize("mode,precision", [(4, hprlp.HPR_FP64), (5, hprlp.HPR_FP64), (3, hprlp.HPR_FP32),
+                                            (4, hprlp.HPR_FP32), (5, hprlp.HPR_FP32)])
+def test_large_regrouped_sliced_windows_match_oracle(large, large_o65, mode, precision):
+    """Sliced windows with the long rows regrouped to 16 (mode 4) or 8 (mode 5) lanes per row,
+    and every sliced mode in FP32 storage (4,096-column windows): 65 iterations against the
+    oracle (FP64 storage at the FP64 tolerance, FP32 storage at the FP32 tolerance)."""
+    lp, o65 = large, large_o65
+    h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=65, lambda_=1.0, lds_windows=mode, unroll=2,
+                                           precision=precision))
+    try:
+        info = hprlp.hpr_solve(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+        ks = hprlp.hpr_get_kernel_stats(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    assert ks["sliced_blocks_at"] > 0, ks
+    if precision == hprlp.HPR_FP64:
+        assert_parity(o65, info, x, y, z, FP64_RTOL)
+    else:
+        assert info.iters == o65.iters
+        assert_close(x, o65.x, 2e-4, "x")
+        assert_close(y, o65.y, 2e-4, "y")
+
+
 def test_large_sliced_windows_match_oracle(large):
     """The primal step of this instance reads y through sliced LDS windows (a unit's output
     column meets the 21,000 security rows of its hour): 65 FP64 iterations with lds_windows = 3

@@ -1,10 +1,15 @@
 """The warm-start network's GPU kernels (MFMA BF16 products, FP32 accumulate, Adam)
-against the FP64 reference in oracle/mlp.py.
+against the FP64 reference in oracle/mlp.py, entry by entry.
 
-The reference gets the BF16-rounded weights and inputs the GPU uses; what remains is the
-BF16 rounding of hidden activations and gradients and the summation order, so results are
-compared with relative tolerances derived from BF16's 8-bit mantissa (2^-8 ~ 4e-3 per
-rounding, a few roundings per path): 2e-2 on norms of whole arrays."""
+The reference gets the BF16-rounded weights and inputs the GPU uses and rounds the hidden
+activations and the backward pass's gradients to BF16 at the same points (the network's
+stated storage precision), so what separates the two is the summation order of the FP32
+products. That order can push a value across a BF16 rounding boundary, which moves it by one
+BF16 step (2^-8 of its size) and carries on through later layers; every entry must lie within
+2^-6 (a few such steps) of the sum of the magnitudes of its terms (oracle.mlp.magnitudes). A
+wrong tile, a dropped edge row or a transposed operand moves entries by their own size,
+which is of the order of that sum (measured on a CPU model of the kernels: a zeroed 16 x 16
+tile of dW sits at 0.7 to 1.0 of it, order effects at 2e-3 at most)."""
 import numpy as np
 import pytest
 
@@ -13,16 +18,14 @@ from paper_2510_10891_amd import mlp
 
 pytestmark = pytest.mark.gpu
 
+TOL = 2.0 ** -6
+
 
 def bf16(a):
-    """Round float32 values to the nearest BF16 (ties to even), returned as float64."""
+    """Round values to the nearest BF16 (ties to even) through float32, returned as float64."""
     u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
     u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def relerr(a, b):
-    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(1e-30, np.linalg.norm(np.ravel(b)))
 
 
 def problem(sizes, rows, seed):
@@ -40,31 +43,39 @@ def reference(params, sizes, X):
     return Ws, [np.asarray(b, np.float64) for b in bs], bf16(X)
 
 
-SHAPES = [([12, 256, 256, 4], 1000), ([9, 256, 256, 1], 333), ([16, 32, 5], 17), ([3, 7], 64)]
+# widths and row counts off the 16-wide tiles on purpose (M, N and K of every product)
+SHAPES = [([12, 256, 256, 4], 1000), ([9, 256, 256, 1], 333), ([16, 32, 5], 17), ([3, 7], 64),
+          ([20, 48, 33, 7], 45)]
 
 
 @pytest.mark.parametrize("sizes,rows", SHAPES)
-def test_forward_matches_reference(sizes, rows):
-    params, X, _ = problem(sizes, rows, 0)
+def test_forward_matches_reference_entrywise(sizes, rows):
+    params, X, T = problem(sizes, rows, 0)
     net = mlp.MLP(sizes, params)
     Y = net.forward(X)
     Ws, bs, Xb = reference(params, sizes, X)
-    out, _, _ = ref.forward(Xb, Ws, bs)
-    assert relerr(Y, out) < 2e-2
+    out, _, _ = ref.forward(Xb, Ws, bs, rnd=bf16)
+    mo, _, _ = ref.magnitudes(Xb, Ws, bs, T.astype(np.float64), rnd=bf16)
+    err = np.abs(Y - out)
+    assert np.all(err <= TOL * mo), (err / mo).max()
 
 
 @pytest.mark.parametrize("sizes,rows", SHAPES)
-def test_gradients_match_reference(sizes, rows):
+def test_gradients_match_reference_entrywise(sizes, rows):
     params, X, T = problem(sizes, rows, 1)
     net = mlp.MLP(sizes, params)
     loss, g = net.gradients(X, T)
     Ws, bs, Xb = reference(params, sizes, X)
-    rloss, dWs, dbs = ref.backward(Xb, Ws, bs, T.astype(np.float64))
-    assert abs(loss - rloss) <= 2e-2 * rloss
+    T64 = T.astype(np.float64)
+    rloss, dWs, dbs = ref.backward(Xb, Ws, bs, T64, rnd=bf16)
+    _, mW, mb = ref.magnitudes(Xb, Ws, bs, T64, rnd=bf16)
+    assert abs(loss - rloss) <= 1e-3 * rloss
     gW, gb = mlp.unpack(g, sizes)
     for i in range(len(Ws)):
-        assert relerr(gW[i], dWs[i]) < 3e-2, f"dW{i}"
-        assert relerr(gb[i], dbs[i]) < 3e-2, f"db{i}"
+        eW = np.abs(gW[i] - dWs[i])
+        assert np.all(eW <= TOL * mW[i] + 1e-12), (f"dW{i}", (eW / (mW[i] + 1e-300)).max())
+        eb = np.abs(gb[i] - dbs[i])
+        assert np.all(eb <= TOL * mb[i] + 1e-12), (f"db{i}", (eb / (mb[i] + 1e-300)).max())
 
 
 def test_adam_step_matches_reference():

@@ -451,14 +451,49 @@ def test_unbounded_lps_are_certified_at_the_oracles_check(case):
     assert o.term == "dual_infeasible", name
     info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-8, max_iter=200000))
     assert info.term == "dual_infeasible" and info.iters == o.iters, (name, info.iters, o.iters)
+    # FP32 storage: the same test at a 1e-3 margin (the ray is a difference of FP32 iterates)
     info32, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-8, max_iter=200000, precision=hprlp.HPR_FP32))
     assert info32.term == "dual_infeasible", name
 
 
 @pytest.mark.parametrize("case", range(7))
 def test_bounded_lps_with_unbounded_columns_match_the_oracle(case):
+    """LPs with unbounded columns but a finite optimum are solved, never reported without one,
+    in FP64 at the oracle's iteration and in FP32 storage at the wider ray margin."""
     name, lp = _unbounded_lps()[1][case]
     o = oracle.solve(lp, oracle.Options(tol=1e-9, max_iter=400000))
     info, x, y, z = hprlp.solve(lp, hprlp.Options(tol=1e-9, max_iter=400000))
     assert o.term == "solved" and info.term == "solved" and info.iters == o.iters, (name, info.iters, o.iters)
     assert abs(info.pobj - o.pobj) <= 1e-8 * (1 + abs(o.pobj))
+    info32, x32, y32, z32 = hprlp.solve(lp, hprlp.Options(tol=1e-5, max_iter=400000, precision=hprlp.HPR_FP32))
+    assert info32.term == "solved", (name, info32.term)
+    assert abs(info32.pobj - o.pobj) <= 1e-3 * (1 + abs(o.pobj))
+
+
+def test_create_from_device_arrays_matches_host_arrays():
+    """hpr_lp.on_device = 1 with torch-allocated arrays: the same scaling, schedule and solve as
+    from host arrays (iterates bit for bit); wrong dtypes are refused by the binding."""
+    torch = pytest.importorskip("torch")
+    _, lp = scuc.make_instance("small", 2)
+    dev = torch.device("cuda:0")
+
+    def t(a, dt):
+        return torch.from_numpy(np.ascontiguousarray(a, dt)).to(dev)
+
+    arrays = (t(lp.row_ptr, np.int64), t(lp.col_idx, np.int32), t(lp.val, np.float64), t(lp.row_lo, np.float64),
+              t(lp.row_hi, np.float64), t(lp.col_lo, np.float64), t(lp.col_hi, np.float64), t(lp.c, np.float64))
+    dlp = hprlp.DeviceLP(lp.m, lp.n, *arrays, lp.obj_offset)
+    torch.cuda.synchronize()
+    opts = hprlp.Options(tol=1e-6, max_iter=100000, unroll=2, lds_windows=2,
+                         stream=torch.cuda.current_stream().cuda_stream)
+    h = hprlp.hpr_create_device(dlp, opts)
+    try:
+        info = hprlp.hpr_solve(h)
+        x, y, z = hprlp.hpr_get_solution(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    info2, x2, y2, z2 = hprlp.solve(lp, opts)
+    assert info.term == "solved" and info.iters == info2.iters
+    assert np.array_equal(x, x2) and np.array_equal(y, y2) and np.array_equal(z, z2)
+    with pytest.raises(ValueError):
+        hprlp.DeviceLP(lp.m, lp.n, arrays[0].to(torch.int32), *arrays[1:], lp.obj_offset)
