@@ -225,7 +225,7 @@ def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
     return out
 
 
-def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000):
+def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, detail=None):
     """The reduced LPs of successive-fixing rounds (uneven sizes) solved as one batch with FP32
     storage, against the same LPs solved one after another with the same options. `parent`:
     "mixed" = parents of 30 to 1,000 buses; "medium" = 2,000-bus parents (seeds 100 + i), each
@@ -297,6 +297,11 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000):
                               rel_kkt=infos[i].rel_kkt, rel_p=infos[i].rel_p, rel_d=infos[i].rel_d,
                               rel_gap=infos[i].rel_gap, restarts=infos[i].restarts, sigma=infos[i].sigma)
                          for i in range(count) if infos[i].term != "solved"])
+    if detail:   # per-LP record: size, iterations and time to stop, batched and one by one
+        with open(detail, "w") as fh:
+            json.dump([dict(index=i, parent=lps[i].meta.get("parent"), n=lps[i].n, m=lps[i].m, nnz=int(lps[i].nnz),
+                            iters=infos[i].iters, stop_s=infos[i].solve_s, term=infos[i].term,
+                            seq_s=(seq[i].solve_s if i < len(seq) else None)) for i in range(count)], fh)
     log(f"batch: {out}")
     return out
 
@@ -521,6 +526,7 @@ def main():
     ap.add_argument("--batch-no-seq", action="store_true",
                     help="skip the one-by-one solves of the batch's LPs")
     ap.add_argument("--batch-max-iter", type=int, default=100000)
+    ap.add_argument("--batch-detail", default=None, help="write per-LP batch results to this JSON file")
     ap.add_argument("--successive", type=int, default=4,
                     help="rounds of the successive-fixing leg on the bench instance (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2,
@@ -602,8 +608,8 @@ def main():
     roof = roofline(lp, f32["ks"], workload, read_gbs, copy_gbs)
 
 
-    batch = (batch_leg(args.batch, stream, args.batch_parent, not args.batch_no_seq, args.batch_max_iter)
-             if args.batch > 0 else None)
+    batch = (batch_leg(args.batch, stream, args.batch_parent, not args.batch_no_seq, args.batch_max_iter,
+                       args.batch_detail) if args.batch > 0 else None)
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
     sf = None
     if args.successive > 0 and args.formulation == "compact":
@@ -633,6 +639,14 @@ def main():
         log(f"cpu baseline: {cpu}")
 
     rel_obj = abs(f32["info"].pobj - f64["info"].pobj) / max(1.0, abs(f64["info"].pobj))
+    exact = None
+    gold = os.path.join(ROOT, "tests", "golden", f"highs_{args.config}_seed{args.seed}.json")
+    if os.path.exists(gold) and args.formulation == "compact":
+        g = json.load(open(gold))
+        if (g["m"], g["n"], g["nnz"]) == (lp.m, lp.n, lp.nnz):
+            exact = dict(objective=g["objective"], source="HiGHS interior point (tests/golden)",
+                         fp32_rel_err=abs(f32["info"].pobj - g["objective"]) / abs(g["objective"]),
+                         fp64_rel_err=abs(f64["info"].pobj - g["objective"]) / abs(g["objective"]))
     out = {
         "metric": "time-to-1e-4 rel KKT (s)",
         "value": round(f32["sec"], 5),
@@ -660,6 +674,7 @@ def main():
                  "rel_kkt_fp64_eval": f64["info"].rel_kkt,
                  "dual_us": round(f64["ks"]["dual_ms"] * 1e3, 2),
                  "primal_us": round(f64["ks"]["primal_ms"] * 1e3, 2)},
+        "objective_vs_exact": exact,
         "fp32_vs_fp64": {"speedup": round(f64["sec"] / f32["sec"], 3), "obj_rel_diff": rel_obj,
                          "x_rel_diff": float(np.linalg.norm(f32["x"] - f64["x"]) /
                                              max(1e-30, np.linalg.norm(f64["x"])))},

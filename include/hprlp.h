@@ -142,8 +142,10 @@ typedef struct {
                                    up to 8 consecutive 16 KB windows one at a time, entries
                                    outside them read from global memory); 4, 5 = as 3, with the
                                    rows of sliced blocks regrouped to 16 (4) or 8 (5) lanes per
-                                   row, so that each window copy serves more rows; -1 (default) =
-                                   the mode 1 to 5 picked per matrix by timing at hpr_create
+                                   row, so that each window copy serves more rows; 6, 7 = as 3,
+                                   with every row given at most 16 (6) or 8 (7) lanes; -1
+                                   (default) = the mode 1 to 7 picked per matrix by timing at
+                                   hpr_create
                                    (2 when unroll is given). Results agree to rounding across
                                    modes; modes 0, 1 and 2 sum in the same order. */
     int32_t use_graph;          /* 1 (default): replay each block of check_every iterations,

@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libhprlp.so")
 # the matrix-product instantiations first: they take the longest to compile
 SOURCES = ["kernels_check_cols64.hip", "kernels_check_cols32.hip", "kernels_check_colsmixed.hip",
            "kernels_primal32.hip", "kernels_primal64.hip", "kernels_dual32.hip", "kernels_dual64.hip",
-           "kernels_spmv.hip", "kernels_check_rows.hip", "kernels.hip", "solver.hip", "mlp.hip", "probe.hip"]
+           "kernels_spmv.hip", "kernels_check_rows.hip", "kernels.hip", "setup.hip", "solver.hip", "mlp.hip",
+           "probe.hip"]
 HEADERS = ["internal.h", "csr.h"]
 
 FLAGS = [

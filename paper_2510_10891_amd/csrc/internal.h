@@ -183,6 +183,57 @@ void launch_unscale(const DevCsr<T>& A, const DevCsr<T>& At, const DevIter<T>& v
 // cols, fixval, rounded [G][T][3] (col < 0: value fixval), fixed [G][T].
 void launch_fix_strategy(const double* x, const int32_t* cols, const double* fixval, int G, int T, double tau,
                          int8_t* fixed, int8_t* rounded, hipStream_t st);
+// ---- device setup of one LP (setup.hip)
+
+// A device buffer that grows on demand and frees itself; release() hands the memory over.
+struct DevScratch {
+    void* p = nullptr;
+    size_t cap = 0;
+    DevScratch() = default;
+    DevScratch(const DevScratch&) = delete;
+    DevScratch& operator=(const DevScratch&) = delete;
+    ~DevScratch();
+    hipError_t reserve(size_t bytes);
+    void* release() {
+        void* q = p;
+        p = nullptr;
+        cap = 0;
+        return q;
+    }
+};
+
+// One padded layout built on the device: row starts [rows + 1], 32-bit columns, 16-bit offsets,
+// FP64 (and FP32) values [padded], per row the smallest and largest column and the wide flag,
+// and the runs of equal column / tile (tptr [rows + 1], tid, tcnt [nruns]).
+struct DevLayout {
+    DevScratch start, col, col16, val64, val32, base, top, wide, tptr, tid, tcnt;
+    int64_t padded = 0, nruns = 0;
+};
+
+struct DevSetupIn {
+    const int64_t* rp;       // caller's CSR on the device (rows in column order)
+    const int32_t* ci;
+    const double* v;
+    int32_t m, n;
+    int64_t nnz;
+    double* dr;              // [m], [n] device: diagonal scaling
+    double* dc;
+    double* dr_host;         // [m], [n] host: the same factors (formed here)
+    double* dc_host;
+    int32_t ruiz_iters;      // Ruiz passes (0: none)
+    int32_t pc;              // Pock-Chambolle pass
+    int32_t fp32;            // also write FP32 values
+    int32_t tile;            // columns per tile of the window choice
+};
+
+struct DevSetupOut {
+    DevLayout a, at;
+    DevScratch row_of, idx, perm, keys, tptr, f, lens;   // work buffers
+};
+
+// Scaling factors and both padded layouts of one LP on `st` (returns the first HIP error).
+hipError_t device_setup(const DevSetupIn& in, DevSetupOut& out, hipStream_t st);
+
 // FP64 -> T copy
 template <typename T>
 void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st);

@@ -26,6 +26,8 @@
 #include <thread>
 #include <vector>
 
+#include <sys/mman.h>
+
 #include "../../include/hprlp.h"
 #include "internal.h"
 
@@ -92,6 +94,8 @@ static void sync_stream(hipStream_t st) { HIP_OK(hipStreamSynchronize(st)); }
 
 // Allocator whose resize leaves new elements uninitialised: the large host layouts are written
 // in full by several threads, so zero-filling them first on one thread would only cost time.
+// Blocks of 2 MiB and more are 2 MiB-aligned and marked for transparent huge pages, so their
+// first touch costs one page fault per 2 MiB instead of one per 4 KiB.
 template <typename T>
 struct NoInit : std::allocator<T> {
     template <typename U>
@@ -101,6 +105,19 @@ struct NoInit : std::allocator<T> {
     NoInit() = default;
     template <typename U>
     NoInit(const NoInit<U>&) noexcept {}
+    T* allocate(size_t count) {
+        const size_t bytes = count * sizeof(T);
+        constexpr size_t kHuge = size_t(2) << 20;
+        if (bytes < kHuge) return std::allocator<T>::allocate(count);
+        void* p = std::aligned_alloc(kHuge, (bytes + kHuge - 1) / kHuge * kHuge);
+        if (!p) throw std::bad_alloc();
+        (void)madvise(p, bytes, MADV_HUGEPAGE);
+        return static_cast<T*>(p);
+    }
+    void deallocate(T* p, size_t count) {
+        if (count * sizeof(T) < (size_t(2) << 20)) std::allocator<T>::deallocate(p, count);
+        else std::free(p);
+    }
     template <typename U>
     void construct(U* p) noexcept {
         ::new ((void*)p) U;
@@ -137,7 +154,7 @@ static void short_indices(const Layout& L, HostVec<uint16_t>& col16, std::vector
 // ---------------------------------------------------------------- validation
 // ---------------------------------------------------------------- validation
 
-static int validate(const hpr_lp* lp) {
+static int validate(const hpr_lp* lp, bool* sorted_rows = nullptr) {
     if (!lp) return fail(HPR_ERR_INVALID, "lp is NULL");
     if (lp->n < 1) return fail(HPR_ERR_INVALID, "n must be >= 1 (got %d)", lp->n);
     if (lp->m < 0 || lp->nnz < 0) return fail(HPR_ERR_INVALID, "negative m or nnz");
@@ -154,6 +171,7 @@ static int validate(const hpr_lp* lp) {
             if (lp->row_ptr[i + 1] < lp->row_ptr[i]) return fail(HPR_ERR_INVALID, "row_ptr decreases at row %d", i);
     }
     std::vector<int32_t> mark((size_t)lp->n, -1);
+    bool sorted = true;
     for (int32_t i = 0; i < lp->m; ++i)
         for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
             const int32_t j = lp->col_idx[k];
@@ -161,7 +179,9 @@ static int validate(const hpr_lp* lp) {
             if (mark[j] == i) return fail(HPR_ERR_INVALID, "column %d repeated in row %d", j, i);
             mark[j] = i;
             if (!std::isfinite(lp->val[k])) return fail(HPR_ERR_INVALID, "non-finite value in row %d", i);
+            if (k > lp->row_ptr[i] && lp->col_idx[k - 1] > j) sorted = false;
         }
+    if (sorted_rows) *sorted_rows = sorted;
     auto bad_pair = [](double lo, double hi) {
         return std::isnan(lo) || std::isnan(hi) || lo > hi || lo == INFINITY || hi == -INFINITY;
     };
@@ -191,8 +211,8 @@ static int validate_opts(const hpr_opts* o) {
         return fail(HPR_ERR_INVALID, "sigma_smoothing and sigma_smoothing_warm must be in (0, 1]");
     if (o->unroll != 0 && o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8)
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
-    if (o->lds_windows < -1 || o->lds_windows > 5)
-        return fail(HPR_ERR_INVALID, "lds_windows must be -1, 0, 1, 2, 3, 4 or 5");
+    if (o->lds_windows < -1 || o->lds_windows > 7)
+        return fail(HPR_ERR_INVALID, "lds_windows must be in [-1, 7]");
     return HPR_OK;
 }
 
@@ -243,7 +263,7 @@ static void parallel_for(int n, int threads, F f) {
 
 static int host_threads() {
     const unsigned hw = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(8u, hw ? hw : 1u));
+    return (int)std::max(1u, std::min(16u, hw ? hw : 1u));
 }
 
 static void short_indices(const Layout& L, HostVec<uint16_t>& col16, std::vector<int32_t>& base,
@@ -289,56 +309,93 @@ static std::vector<int32_t> row_parts(const hpr_lp* lp) {
     return cut;
 }
 
+// The entries of A in column order: for column j, positions tptr[j] .. tptr[j+1] of trow (the
+// entry's row) and tent (its position in the caller's arrays), rows increasing within a column
+// (a stable counting sort, partition by partition).
+struct ColOrder {
+    std::vector<int64_t> tptr;
+    HostVec<int32_t> trow;
+    HostVec<int64_t> tent;
+};
+
+static void column_order(const hpr_lp* lp, const std::vector<int32_t>& cut, int threads, ColOrder& co) {
+    const int32_t m = lp->m, n = lp->n;
+    const int64_t* rp = lp->row_ptr;
+    std::vector<std::vector<int64_t>> cnt(kParts);
+    parallel_for(kParts, threads, [&](int p) {
+        cnt[p].assign((size_t)n, 0);
+        for (int64_t k = (m ? rp[cut[p]] : 0); k < (m ? rp[cut[p + 1]] : 0); ++k) cnt[p][lp->col_idx[k]]++;
+    });
+    co.tptr.assign((size_t)n + 1, 0);
+    int64_t off = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        co.tptr[j] = off;
+        for (int p = 0; p < kParts; ++p) {
+            const int64_t c = cnt[p][j];
+            cnt[p][j] = off;            // first slot of partition p in column j
+            off += c;
+        }
+    }
+    co.tptr[n] = off;
+    co.trow.resize(off);
+    co.tent.resize(off);
+    parallel_for(kParts, threads, [&](int p) {
+        std::vector<int64_t>& slot = cnt[p];
+        for (int32_t i = cut[p]; i < cut[p + 1]; ++i)
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int64_t q = slot[lp->col_idx[k]]++;
+                co.trow[q] = i;
+                co.tent[q] = k;
+            }
+    });
+}
+
 // Section III-A: optional Ruiz passes (rows/columns divided by the square root of their
-// largest magnitude), Pock-Chambolle with alpha = 1 (divided by the square root of the
-// absolute row/column sums; empty ones keep 1), then the bounds are divided by
-// beta_b = 1 + ||b~|| (b~ the finite sides of the scaled rows) and the cost by
-// beta_c = 1 + ||c~||. Fills the LP's diagonal scaling and scaled vectors; the scaled matrix
-// entries are a_ij dr_i dc_j, formed where the layouts are written (make_layouts).
-static void scale_host(const hpr_lp* lp, const hpr_opts& o, LpHost& h, const std::vector<int32_t>& cut,
-                       int threads) {
+// largest magnitude), then Pock-Chambolle with alpha = 1 (divided by the square root of the
+// absolute row/column sums; empty ones keep 1). A pass reduces every row over its entries in
+// the caller's order and every column over its entries in row order, both from the factors
+// at the pass's start, with the terms |a_ij dr_i dc_j| formed as (a dr) dc: the device setup
+// does the same, so both give the same factors bit for bit.
+static void scale_factors(const hpr_lp* lp, const hpr_opts& o, LpHost& h, const ColOrder& co, int threads) {
     const int32_t m = lp->m, n = lp->n;
     h.dr.assign((size_t)m, 1.0);
     h.dc.assign((size_t)n, 1.0);
-    std::vector<double> ec((size_t)n);
-    std::vector<std::vector<double>> part(kParts);
+    std::vector<double> drn((size_t)m);
     const int64_t* rp = lp->row_ptr;
-    // one pass: per-row reduction into dr (row factor), per-column partials combined in part order;
-    // `sum` selects absolute sums (Pock-Chambolle) or maxima (Ruiz)
+    constexpr int kChunks = 64;
     auto pass = [&](bool sum) {
-        parallel_for(kParts, threads, [&](int p) {
-            std::vector<double>& col = part[p];
-            col.assign((size_t)n, 0.0);
-            for (int32_t i = cut[p]; i < cut[p + 1]; ++i) {
-                const double di = h.dr[i];
+        parallel_for(kChunks, threads, [&](int p) {
+            for (int64_t i = (int64_t)m * p / kChunks; i < (int64_t)m * (p + 1) / kChunks; ++i) {
                 double r = 0.0;
                 for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-                    const int32_t j = lp->col_idx[k];
-                    const double v = std::fabs(lp->val[k] * di * h.dc[j]);
-                    if (sum) {
-                        r += v;
-                        col[j] += v;
-                    } else {
-                        r = std::max(r, v);
-                        col[j] = std::max(col[j], v);
-                    }
+                    const double a = std::fabs(lp->val[k] * h.dr[i] * h.dc[lp->col_idx[k]]);
+                    r = sum ? r + a : std::max(r, a);
                 }
-                h.dr[i] = di * (r > 0 ? 1.0 / std::sqrt(r) : 1.0);
+                drn[i] = h.dr[i] * (r > 0 ? 1.0 / std::sqrt(r) : 1.0);
             }
         });
-        parallel_for(kParts, threads, [&](int p) {   // columns in kParts ranges
-            const int32_t j0 = (int32_t)((int64_t)n * p / kParts), j1 = (int32_t)((int64_t)n * (p + 1) / kParts);
-            for (int32_t j = j0; j < j1; ++j) {
+        parallel_for(kChunks, threads, [&](int p) {
+            for (int64_t j = (int64_t)n * p / kChunks; j < (int64_t)n * (p + 1) / kChunks; ++j) {
                 double c = 0.0;
-                for (int q = 0; q < kParts; ++q) c = sum ? c + part[q][j] : std::max(c, part[q][j]);
-                ec[j] = c;
+                for (int64_t q = co.tptr[j]; q < co.tptr[j + 1]; ++q) {
+                    const double a = std::fabs(lp->val[co.tent[q]] * h.dr[co.trow[q]] * h.dc[j]);
+                    c = sum ? c + a : std::max(c, a);
+                }
                 h.dc[j] *= c > 0 ? 1.0 / std::sqrt(c) : 1.0;
             }
         });
+        h.dr.swap(drn);
     };
     if (o.scaling & HPR_SCALE_RUIZ)
         for (int32_t it = 0; it < o.ruiz_iters; ++it) pass(false);
     if (o.scaling & HPR_SCALE_PC) pass(true);
+}
+
+// From the diagonal scaling: the scaled bounds and cost, then division of the bounds by
+// beta_b = 1 + ||b~|| (b~ the finite sides of the scaled rows) and of the cost by
+// beta_c = 1 + ||c~||, and the norms of the original rhs and cost.
+static void scale_vectors(const hpr_lp* lp, const hpr_opts& o, LpHost& h) {
+    const int32_t m = lp->m, n = lp->n;
     h.lo_s.resize(m);
     h.hi_s.resize(m);
     for (int32_t i = 0; i < m; ++i) {
@@ -385,15 +442,14 @@ static void scale_host(const hpr_lp* lp, const hpr_opts& o, LpHost& h, const std
 }
 
 // Padded layouts of A~ = Dr A Dc (rows of the caller's CSR, each put in column order) and of
-// A~^T (rows = columns of A, each in increasing row order: a stable counting sort, partition by
-// partition), written straight from the caller's arrays: every row's storage is padded to a
-// multiple of 4 entries with value 0 at the row's largest column.
-static void make_layouts(const hpr_lp* lp, const LpHost& h, const std::vector<int32_t>& cut, int threads,
-                         Layout& la, Layout& lt) {
+// A~^T (rows = columns of A, from the column order), written straight from the caller's arrays:
+// every row's storage is padded to a multiple of 4 entries with value 0 at the row's largest
+// column; entries a_ij dr_i dc_j.
+static void make_layouts(const hpr_lp* lp, const LpHost& h, const ColOrder& co, const std::vector<int32_t>& cut,
+                         int threads, Layout& la, Layout& lt) {
     const int32_t m = lp->m, n = lp->n;
     const int64_t* rp = lp->row_ptr;
     auto pad = [](int64_t len) { return (len + kVec - 1) / kVec * kVec; };
-    // A~: offsets, then rows filled in parallel
     la.start.resize((size_t)m + 1);
     int64_t off = 0;
     for (int32_t i = 0; i < m; ++i) {
@@ -403,30 +459,8 @@ static void make_layouts(const hpr_lp* lp, const LpHost& h, const std::vector<in
     la.start[m] = off;
     la.col.resize(off);
     la.val.resize(off);
-    // A~^T: per-partition column counts, padded row lengths, each partition's first slot per column
-    std::vector<std::vector<int64_t>> cnt(kParts);
-    parallel_for(kParts, threads, [&](int p) {
-        cnt[p].assign((size_t)n, 0);
-        for (int64_t k = (m ? rp[cut[p]] : 0); k < (m ? rp[cut[p + 1]] : 0); ++k) cnt[p][lp->col_idx[k]]++;
-    });
-    lt.start.resize((size_t)n + 1);
-    int64_t toff = 0;
-    for (int32_t j = 0; j < n; ++j) {
-        lt.start[j] = toff;
-        int64_t len = 0;
-        for (int p = 0; p < kParts; ++p) {
-            const int64_t c = cnt[p][j];
-            cnt[p][j] = toff + len;     // first slot of partition p in row j of A~^T
-            len += c;
-        }
-        toff += pad(len);
-    }
-    lt.start[n] = toff;
-    lt.col.resize(toff);
-    lt.val.resize(toff);
     parallel_for(kParts, threads, [&](int p) {
         std::vector<std::pair<int32_t, double>> tmp;
-        std::vector<int64_t>& slot = cnt[p];
         for (int32_t i = cut[p]; i < cut[p + 1]; ++i) {
             const int64_t b = rp[i], e = rp[i + 1];
             const double di = h.dr[i];
@@ -449,23 +483,31 @@ static void make_layouts(const hpr_lp* lp, const LpHost& h, const std::vector<in
                     ++d;
                 }
             }
-            for (int64_t q = la.start[i]; q < d; ++q) {   // scatter into A~^T, rows in increasing order
-                const int64_t s2 = slot[la.col[q]]++;
-                lt.col[s2] = i;
-                lt.val[s2] = la.val[q];
-            }
             for (; d < la.start[i + 1]; ++d) {   // padding: value 0 at the row's largest column
                 la.col[d] = la.col[d - 1];
                 la.val[d] = 0.0;
             }
         }
     });
-    // padding of A~^T rows: after the last partition's entries of each row
-    parallel_for(kParts, threads, [&](int p) {
-        const int32_t j0 = (int32_t)((int64_t)n * p / kParts), j1 = (int32_t)((int64_t)n * (p + 1) / kParts);
-        for (int32_t j = j0; j < j1; ++j) {
-            const int64_t used = cnt[kParts - 1][j];   // one past the last entry of row j
-            for (int64_t d = used; d < lt.start[j + 1]; ++d) {
+    lt.start.resize((size_t)n + 1);
+    int64_t toff = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        lt.start[j] = toff;
+        toff += pad(co.tptr[j + 1] - co.tptr[j]);
+    }
+    lt.start[n] = toff;
+    lt.col.resize(toff);
+    lt.val.resize(toff);
+    constexpr int kChunks = 64;
+    parallel_for(kChunks, threads, [&](int p) {
+        for (int64_t j = (int64_t)n * p / kChunks; j < (int64_t)n * (p + 1) / kChunks; ++j) {
+            int64_t d = lt.start[j];
+            for (int64_t q = co.tptr[j]; q < co.tptr[j + 1]; ++q, ++d) {
+                const int32_t i = co.trow[q];
+                lt.col[d] = i;
+                lt.val[d] = lp->val[co.tent[q]] * h.dr[i] * h.dc[j];
+            }
+            for (; d < lt.start[j + 1]; ++d) {
                 lt.col[d] = lt.col[d - 1];
                 lt.val[d] = 0.0;
             }
@@ -560,12 +602,14 @@ static void slice_block(BlockDesc& d, const int32_t* rows_of_block,
 // entries than the window has columns. Blocks that get neither may get sliced windows
 // (`sliced`). With slice_cap >= 0, the rows of such blocks in bins above slice_cap are instead
 // regrouped into blocks of bin slice_cap (2^slice_cap lanes per row, so more rows share each
-// window copy) before their windows are sliced; rows stay in index order.
+// window copy) before their windows are sliced; rows stay in index order. With lane_cap >= 0
+// every row of a bin above lane_cap goes to bin lane_cap (at most 2^lane_cap lanes per row)
+// before blocks are formed, so full and split windows are shared by more rows too.
 static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
                           const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
                           const TileCounts& tc, int64_t ncols,
                           const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
-                          int slice_cap, std::vector<RowRef>& rows, std::vector<BlockDesc>& sched,
+                          int slice_cap, int lane_cap, std::vector<RowRef>& rows, std::vector<BlockDesc>& sched,
                           std::vector<int32_t>& seg, std::vector<int32_t>& cum) {
     std::vector<std::pair<int32_t, int64_t>> tiles;
     cum.clear();
@@ -652,6 +696,7 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
             const int64_t quads = (start[i + 1] - start[i]) / kVec;
             int b = 0;
             while (b < kNumBins - 1 && (int64_t)U * (int64_t(1) << b) < quads) ++b;
+            if (lane_cap >= 0 && b > lane_cap) b = lane_cap;   // longer rows take more passes
             by_bin[b].push_back((int32_t)i);
         }
         for (int b = 0; b < kNumBins; ++b) {
@@ -676,8 +721,10 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
     seg[L] = (int32_t)sched.size();
 }
 
-// lds_windows modes 4 and 5: sliced blocks regrouped with 16 and 8 lanes per row (bins 4, 3)
+// lds_windows modes 4 and 5: sliced blocks regrouped with 16 and 8 lanes per row (bins 4, 3);
+// modes 6 and 7: every row capped at 16 and 8 lanes
 static int slice_cap_of(int mode) { return mode == 4 ? 4 : (mode == 5 ? 3 : -1); }
+static int lane_cap_of(int mode) { return mode == 6 ? 4 : (mode == 7 ? 3 : -1); }
 
 struct DevMatrix {
     DBuf start, col, col16, rows, sched, seg, val64, val32, slice_cum;
@@ -687,7 +734,8 @@ struct DevMatrix {
     std::vector<uint8_t> wide_h;
     int32_t win_max = 0;                     // LDS window limit in vector entries
     int32_t win_mode = 2;                    // 0: no windows, 1: full, 2: full and split, 3: and sliced,
-                                             // 4, 5: sliced blocks regrouped (16, 8 lanes per row)
+                                             // 4, 5: sliced blocks regrouped (16, 8 lanes per row),
+                                             // 6, 7: every row at most 16, 8 lanes
     int32_t has_sliced = 0;                  // the current schedule has sliced blocks
     TileCounts tiles;
     int64_t ncols = 0;                       // length of the gathered vector
@@ -725,6 +773,51 @@ struct DevMatrix {
             val32.alloc(L.val.size() * sizeof(float));
             launch_cast<float>(val64.as<double>(), val32.as<float>(), (int64_t)L.val.size(), st);
         }
+        set_unroll(4, st);
+    }
+    // Takes over a layout built on the device (device_setup): the device buffers become this
+    // matrix's, and the per-row metadata the schedules need is copied to the host.
+    void adopt(DevLayout& L, const std::vector<int64_t>& lp_rows_in, int32_t rows, int64_t ncols_in, bool fp32,
+               int lds_windows, hipStream_t st) {
+        nrows = rows;
+        ncols = ncols_in;
+        win_mode = lds_windows < 0 ? 2 : lds_windows;
+        padded = L.padded;
+        lp_rows = lp_rows_in;
+        win_max = kWinBytes / (fp32 ? (int)sizeof(float) : (int)sizeof(double));
+        if (padded / kVec >= INT32_MAX) {
+            fail(HPR_ERR_INVALID, "matrix too large: more than 2^33 stored entries");
+            throw HipError{HPR_ERR_INVALID};
+        }
+        start_h.resize((size_t)rows + 1);
+        base_h.resize(rows);
+        top_h.resize(rows);
+        wide_h.resize(rows);
+        tiles.tile = win_max / 2;
+        tiles.ptr.resize((size_t)rows + 1);
+        tiles.id.resize(L.nruns);
+        tiles.cnt.resize(L.nruns);
+        auto get = [&](void* dst, const DevScratch& src, size_t bytes) {
+            if (bytes) HIP_OK(hipMemcpyAsync(dst, src.p, bytes, hipMemcpyDeviceToHost, st));
+        };
+        get(start_h.data(), L.start, sizeof(int64_t) * ((size_t)rows + 1));
+        get(base_h.data(), L.base, sizeof(int32_t) * rows);
+        get(top_h.data(), L.top, sizeof(int32_t) * rows);
+        get(wide_h.data(), L.wide, rows);
+        get(tiles.ptr.data(), L.tptr, sizeof(int64_t) * ((size_t)rows + 1));
+        get(tiles.id.data(), L.tid, sizeof(int32_t) * L.nruns);
+        get(tiles.cnt.data(), L.tcnt, sizeof(int32_t) * L.nruns);
+        HIP_OK(hipStreamSynchronize(st));
+        auto take = [](DBuf& d, DevScratch& src) {
+            d.release();
+            d.bytes = src.cap;
+            d.p = src.release();
+        };
+        take(start, L.start);
+        take(col, L.col);
+        take(col16, L.col16);
+        take(val64, L.val64);
+        if (fp32) take(val32, L.val32);
         set_unroll(4, st);
     }
     void count_tiles(const Layout& L, int32_t tile, int threads) {
@@ -784,7 +877,8 @@ struct DevMatrix {
         parallel_for((int)todo.size(), threads, [&](int i) {
             Built& b = built[todo[i]];
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, b.U, b.mode >= 1 ? win_max : 0,
-                          b.mode >= 2, b.mode >= 3, slice_cap_of(b.mode), b.rows, b.sched, b.seg, b.cum);
+                          b.mode >= 2, b.mode >= 3, slice_cap_of(b.mode), lane_cap_of(b.mode), b.rows, b.sched,
+                          b.seg, b.cum);
         });
     }
     void set_unroll(int U, hipStream_t st) {
@@ -794,8 +888,8 @@ struct DevMatrix {
         if (!b) {
             built.push_back(Built{U, win_mode, {}, {}, {}, {}});
             make_schedule(start_h, base_h, top_h, wide_h, tiles, ncols, lp_rows, U, win_mode >= 1 ? win_max : 0,
-                          win_mode >= 2, win_mode >= 3, slice_cap_of(win_mode), built.back().rows, built.back().sched,
-                          built.back().seg, built.back().cum);
+                          win_mode >= 2, win_mode >= 3, slice_cap_of(win_mode), lane_cap_of(win_mode),
+                          built.back().rows, built.back().sched, built.back().seg, built.back().cum);
             b = &built.back();
         }
         unroll = U;
@@ -1068,9 +1162,9 @@ static void autotune(Engine* e) {
                 if (which == 0) launch_dual_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
                 else launch_primal_step<T>(view, p, v, e->ctrl.as<Ctrl>(), 0, false, st);
             };
-            for (int r = 0; r < 2; ++r) launch();
+            launch();
             HIP_OK(hipEventRecord(e0, st));
-            for (int r = 0; r < 8; ++r) launch();
+            for (int r = 0; r < 5; ++r) launch();
             HIP_OK(hipEventRecord(e1, st));
             HIP_OK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -1088,7 +1182,7 @@ static void autotune(Engine* e) {
         std::vector<Cand> cand;
         for (int U : {1, 2, 4}) {
             if (tune_split) {
-                for (int mode : {1, 2, 3, 4, 5}) cand.push_back(Cand{U, mode, 1e30f});
+                for (int mode : {1, 2, 3, 4, 5, 6, 7}) cand.push_back(Cand{U, mode, 1e30f});
             } else {
                 cand.push_back(Cand{U, Mx.win_mode, 1e30f});
             }
@@ -1101,7 +1195,7 @@ static void autotune(Engine* e) {
             std::vector<Cand> kept;
             for (const Cand& c : cand) {
                 bool same = false;
-                if (tune_split && c.mode >= 2)
+                if (tune_split && c.mode >= 2 && c.mode <= 5)
                     for (const DevMatrix::Built& b : Mx.built)
                         if (b.U == c.U && b.mode == c.mode) {
                             // modes 3-5 differ from mode 2 only where blocks are sliced
@@ -1109,7 +1203,7 @@ static void autotune(Engine* e) {
                             for (const BlockDesc& d : b.sched) adds = adds || (c.mode == 2 ? d.wlen < 0 : d.ns > 0);
                             same = !adds;
                         }
-                if (!same && c.mode >= 4) {   // regrouping that changes nothing repeats a lower mode
+                if (!same && c.mode >= 4) {   // a regrouping or cap that changes nothing repeats a lower mode
                     const DevMatrix::Built *me = nullptr, *lower = nullptr;
                     for (const DevMatrix::Built& b : Mx.built) {
                         if (b.U == c.U && b.mode == c.mode) me = &b;
@@ -1123,7 +1217,7 @@ static void autotune(Engine* e) {
             }
             cand.swap(kept);
         }
-        for (int round = 0; round < 3; ++round)
+        for (int round = 0; round < 2; ++round)
             for (Cand& c : cand) {
                 Mx.win_mode = c.mode;
                 Mx.set_unroll(c.U, st);
@@ -1135,7 +1229,7 @@ static void autotune(Engine* e) {
         Mx.win_mode = best->mode;
         Mx.set_unroll(best->U, st);
         float ms_plain = 1e30f, ms_nt = 1e30f;
-        for (int round = 0; round < 3; ++round) {
+        for (int round = 0; round < 2; ++round) {
             Mx.nontemporal = 0;
             ms_plain = std::min(ms_plain, time_it());
             Mx.nontemporal = 1;
@@ -1245,8 +1339,11 @@ struct PrepLp {
 
 static void prep_lp(const hpr_lp* lp, const hpr_opts& o, PrepLp& p, int threads) {
     const std::vector<int32_t> cut = row_parts(lp);
-    scale_host(lp, o, p.h, cut, threads);
-    make_layouts(lp, p.h, cut, threads, p.la, p.lt);
+    ColOrder co;
+    column_order(lp, cut, threads, co);
+    scale_factors(lp, o, p.h, co, threads);
+    scale_vectors(lp, o, p.h);
+    make_layouts(lp, p.h, co, cut, threads, p.la, p.lt);
 }
 
 // An LP whose arrays are device memory (hpr_lp.on_device), read into host copies on `st`.
@@ -1338,8 +1435,9 @@ static int engine_create_host(const hpr_lp* lps, int count, const hpr_opts* opts
     else hpr_default_opts(&o);
     int rc = validate_opts(&o);
     if (rc) return rc;
+    bool sorted = true;
     for (int l = 0; l < count; ++l) {
-        rc = validate(&lps[l]);
+        rc = validate(&lps[l], &sorted);
         if (rc) {
             if (count > 1) {
                 std::string msg = g_err;
@@ -1369,7 +1467,55 @@ static int engine_create_host(const hpr_lp* lps, int count, const hpr_opts* opts
         std::vector<int64_t> rows_a(1, 0), rows_at(1, 0);
         const int threads = host_threads();
         const int chunk = count == 1 ? 1 : threads;
-        for (int c0 = 0; c0 < count; c0 += chunk) {
+        // One LP whose rows are in column order is set up on the device: the caller's CSR is
+        // uploaded once and scaled, transposed and laid out there (device_setup); batches and
+        // rows out of order take the host path, which computes the same values.
+        const bool on_gpu = count == 1 && sorted && lps[0].m > 0 && lps[0].nnz > 0 && lps[0].nnz < INT32_MAX;
+        if (on_gpu) {
+            const hpr_lp* lp = &lps[0];
+            LpHost& h = e->lps[0];
+            h.m = lp->m;
+            h.n = lp->n;
+            h.nnz = lp->nnz;
+            DBuf drp, dci, dv, ddr, ddc;
+            drp.alloc(sizeof(int64_t) * ((size_t)lp->m + 1));
+            dci.alloc(sizeof(int32_t) * (size_t)lp->nnz);
+            dv.alloc(sizeof(double) * (size_t)lp->nnz);
+            ddr.alloc(sizeof(double) * (size_t)lp->m);
+            ddc.alloc(sizeof(double) * (size_t)lp->n);
+            HIP_OK(hipMemcpyAsync(drp.p, lp->row_ptr, drp.bytes, hipMemcpyHostToDevice, e->st));
+            HIP_OK(hipMemcpyAsync(dci.p, lp->col_idx, dci.bytes, hipMemcpyHostToDevice, e->st));
+            HIP_OK(hipMemcpyAsync(dv.p, lp->val, dv.bytes, hipMemcpyHostToDevice, e->st));
+            DevSetupIn in;
+            in.rp = drp.as<int64_t>();
+            in.ci = dci.as<int32_t>();
+            in.v = dv.as<double>();
+            in.m = lp->m;
+            in.n = lp->n;
+            in.nnz = lp->nnz;
+            in.dr = ddr.as<double>();
+            in.dc = ddc.as<double>();
+            h.dr.resize(lp->m);
+            h.dc.resize(lp->n);
+            in.dr_host = h.dr.data();
+            in.dc_host = h.dc.data();
+            in.ruiz_iters = (o.scaling & HPR_SCALE_RUIZ) ? o.ruiz_iters : 0;
+            in.pc = (o.scaling & HPR_SCALE_PC) ? 1 : 0;
+            in.fp32 = e->fp32 ? 1 : 0;
+            in.tile = kWinBytes / (e->fp32 ? (int)sizeof(float) : (int)sizeof(double)) / 2;
+            {
+                DevSetupOut out;
+                HIP_OK(device_setup(in, out, e->st));
+                scale_vectors(lp, o, h);
+                e->M = lp->m;
+                e->N = lp->n;
+                rows_a.push_back(e->M);
+                rows_at.push_back(e->N);
+                e->A.adopt(out.a, rows_a, lp->m, e->N, e->fp32, o.lds_windows, e->st);
+                e->At.adopt(out.at, rows_at, lp->n, e->M, e->fp32, o.lds_windows, e->st);
+            }
+        }
+        for (int c0 = 0; c0 < (on_gpu ? 0 : count); c0 += chunk) {
             const int c1 = std::min(count, c0 + chunk);
             std::vector<PrepLp> prep((size_t)(c1 - c0));
             if (count == 1) prep_lp(&lps[0], o, prep[0], threads);
@@ -1415,14 +1561,17 @@ static int engine_create_host(const hpr_lp* lps, int count, const hpr_opts* opts
                 }
             }
         }
-        parallel_for(2, threads, [&](int i) {
-            const int th = std::max(1, threads / 2);
-            if (i == 0) e->A.prepare(PA, rows_a, e->N, e->fp32, o.lds_windows, th);
-            else e->At.prepare(PAt, rows_at, e->M, e->fp32, o.lds_windows, th);
-        });
+        if (!on_gpu)
+            parallel_for(2, threads, [&](int i) {
+                const int th = std::max(1, threads / 2);
+                if (i == 0) e->A.prepare(PA, rows_a, e->N, e->fp32, o.lds_windows, th);
+                else e->At.prepare(PAt, rows_at, e->M, e->fp32, o.lds_windows, th);
+            });
         const double t1 = now_s();
-        e->A.upload_from(PA, e->fp32, e->st);
-        e->At.upload_from(PAt, e->fp32, e->st);
+        if (!on_gpu) {
+            e->A.upload_from(PA, e->fp32, e->st);
+            e->At.upload_from(PAt, e->fp32, e->st);
+        }
         e->sync();
         upload_vectors(e.get());
         alloc_iterates(e.get());

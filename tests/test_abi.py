@@ -81,7 +81,7 @@ def test_create_rejects_no_columns():
 @pytest.mark.parametrize("opt", [dict(max_iter=0), dict(check_every=0), dict(sigma0=0.0), dict(sigma0=-1.0),
                                  dict(tol=-1.0), dict(precision=7), dict(power_max_iter=0),
                                  dict(lambda_=float("nan")), dict(warm_fallback_ratio=0.0), dict(warm_fallback=3),
-                                 dict(unroll=3), dict(lds_windows=6), dict(lds_windows=-2),
+                                 dict(unroll=3), dict(lds_windows=8), dict(lds_windows=-2),
                                  dict(sigma_smoothing=0.0), dict(sigma_smoothing=1.5),
                                  dict(sigma_smoothing_warm=0.0)])
 def test_create_rejects_bad_options(opt):

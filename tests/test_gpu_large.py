@@ -37,11 +37,13 @@ def large_o65(large):
 
 
 @pytest.mark.parametrize("mode,precision", [(4, hprlp.HPR_FP64), (5, hprlp.HPR_FP64), (3, hprlp.HPR_FP32),
-                                            (4, hprlp.HPR_FP32), (5, hprlp.HPR_FP32)])
+                                            (4, hprlp.HPR_FP32), (5, hprlp.HPR_FP32), (6, hprlp.HPR_FP64),
+                                            (7, hprlp.HPR_FP32)])
 def test_large_regrouped_sliced_windows_match_oracle(large, large_o65, mode, precision):
     """Sliced windows with the long rows regrouped to 16 (mode 4) or 8 (mode 5) lanes per row,
-    and every sliced mode in FP32 storage (4,096-column windows): 65 iterations against the
-    oracle (FP64 storage at the FP64 tolerance, FP32 storage at the FP32 tolerance)."""
+    every row capped at 16 or 8 lanes (modes 6, 7), and the sliced modes in FP32 storage
+    (4,096-column windows): 65 iterations against the oracle (FP64 storage at the FP64
+    tolerance, FP32 storage at the FP32 tolerance)."""
     lp, o65 = large, large_o65
     h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=65, lambda_=1.0, lds_windows=mode, unroll=2,
                                            precision=precision))

@@ -288,6 +288,18 @@ def test_lds_window_modes_agree_bitwise(formulation):
             assert_close(y, runs[0][2], FP64_RTOL, "y")
 
 
+@pytest.mark.parametrize("mode", [6, 7])
+def test_lane_capped_window_modes_match_oracle(mode):
+    """Every row of the 2,000-bus matrices given at most 16 (mode 6) or 8 (mode 7) lanes, so
+    that full and split windows are shared by more rows: 65 FP64 iterations against the oracle."""
+    _, lp = scuc.make_instance("medium", 0)
+    K = 65
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, lambda_in=1.0))
+    info, x, y, z, ks = _run_mode(lp, K, mode, hprlp.HPR_FP64)
+    assert ks["full_blocks_a"] > 0
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 3])
 def test_rows_given_out_of_column_order(mode):
     """CSR rows whose entries are not in column order (allowed by the interface) are stored in
