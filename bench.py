@@ -225,7 +225,39 @@ def cpu_baseline(lp, gpu_fp64_iters, limit_s, gpu_objs):
     return out
 
 
-def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, detail=None):
+TAU_GRID = (0.0, 1e-6, 1e-4, 1e-3, 0.01, 0.03, 0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.45)
+
+
+def reduced_batch(count, big, stream):
+    """The batch's reduced LPs: member i has parent seed 100 + i and Algorithm 1's fixing of its
+    parent's solved relaxation at the tau (of TAU_GRID) whose share of fixed unit-hours is
+    nearest 0.2 + 0.7 i / (count - 1). Mixed parents (30 to 1,000 buses): the fixings stored
+    under tests/golden (relaxations solved by the oracle); 2,000-bus parents: relaxations solved
+    here by the GPU solver (FP32, 1e-4), Algorithm 1 on the device."""
+    from paper_2510_10891_amd import fixing, hprlp, scuc, successive
+
+    if not big:
+        path = os.path.join(ROOT, "tests", "golden", "fixing_masks_mixed.json")
+        fx = fixing.load_fixings(path) if count <= 64 and os.path.exists(path) else None
+        return [p.lp for p in fixing.make_reduced_batch(count=count, seed0=100, fixings=fx[:count] if fx else None)]
+    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=200000, stream=stream)
+    lps = []
+    for i in range(count):
+        target = 0.2 + 0.7 * i / max(count - 1, 1)
+        data, lp = scuc.make_instance(scuc.MEDIUM, 100 + i)
+        fx = successive.solved_fixing(data, lp, target, TAU_GRID, opts)
+        if fx is None:
+            raise RuntimeError(f"parent relaxation of member {i} was not solved")
+        fixed, ur, vr, wr, tau, info = fx
+        pre = fixing.apply_fixing(scuc.MEDIUM, 100 + i, target, data, lp, fixed, ur, vr, wr,
+                                  f"solved relaxation (GPU, {info.iters} iterations), tau {tau}")
+        lps.append(pre.lp)
+        log(f"reduced LP {i + 1}/{count}: tau {tau}, {pre.lp.meta['fixed_u']:.3f} of u fixed (target {target:.3f}), "
+            f"n {pre.lp.n}, nnz {pre.lp.nnz}")
+    return lps
+
+
+def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, detail=None, stall_iters=8192):
     """The reduced LPs of successive-fixing rounds (uneven sizes) solved as one batch with FP32
     storage, against the same LPs solved one after another with the same options. `parent`:
     "mixed" = parents of 30 to 1,000 buses; "medium" = 2,000-bus parents (seeds 100 + i), each
@@ -234,20 +266,17 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
     import numpy as np
     import torch
 
-    from paper_2510_10891_amd import fixing, hprlp, scuc
+    from paper_2510_10891_amd import fixing, hprlp, mixed, scuc
 
     big = parent == "medium"
     t = time.perf_counter()
-    pre = fixing.make_reduced_batch(count=count, seed0=100, parent=scuc.MEDIUM if big else None,
-                                    workers=min(8, os.cpu_count() or 1) if big else 1, log=log if big else None)
-    lps = [p.lp for p in pre]
-    del pre
+    lps = reduced_batch(count, big, stream)
     log(f"batch: {count} reduced LPs, n {min(lp.n for lp in lps)}..{max(lp.n for lp in lps)}, "
         f"nnz total {sum(lp.nnz for lp in lps)} ({time.perf_counter() - t:.1f} s)")
     # the 2,000-bus batch is one long library call: a time limit bounds it (members still running
     # then end as time_limit and are counted as unsolved)
     opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=max_iter, stream=stream,
-                         time_limit_s=150.0 if big else 0.0)
+                         time_limit_s=150.0 if big else 0.0, stall_iters=stall_iters)
     t = time.perf_counter()
     b = hprlp.hpr_batch_create(lps, opts)
     log(f"batch engine created in {time.perf_counter() - t:.1f} s")
@@ -256,13 +285,15 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = hprlp.hpr_batch_solve(b)
+    # members whose FP32 run stalled above the tolerance go on in FP64 from their points
+    infos, cont = mixed.continue_stalled(lps, opts, infos, lambda i: hprlp.hpr_batch_get_solution(b, i), t0)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     log(f"batch solve {t_batch:.2f} s")
     worst = max(i.rel_kkt for i in infos)       # FP64 evaluation by the library
     setup = infos[0].setup_s
     hprlp.hpr_batch_destroy(b)
-    seq, t_seq = [], 0.0
+    seq, t_seq, seq_cont = [], 0.0, 0
     for k in range(0, count if sequential else 0, 16 if big else count):   # big members: 16 handles at a time
         handles = [hprlp.hpr_create(lp, opts) for lp in lps[k:k + (16 if big else count)]]
         if not big:
@@ -270,7 +301,11 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
                 hprlp.hpr_solve(h)               # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        seq += [hprlp.hpr_solve(h) for h in handles]
+        part = [hprlp.hpr_solve(h) for h in handles]
+        part, c = mixed.continue_stalled(lps[k:k + len(handles)], opts, part,
+                                         lambda i: hprlp.hpr_get_solution(handles[i]))
+        seq += part
+        seq_cont += len(c)
         torch.cuda.synchronize()
         t_seq += time.perf_counter() - t0
         for h in handles:
@@ -278,7 +313,10 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
         log(f"sequential: {len(seq)}/{count} solved one by one ({t_seq:.1f} s)")
     iters = np.array([i.iters for i in infos])
     name = "2,000-bus parents" if big else "parents of 30-1,000 buses"
-    out = dict(workload=f"{count} reduced SCUC LPs ({name}; Algorithm 1 fixings, 20-90% of u fixed, presolved)",
+    shares = [float(lp.meta.get("fixed_u", 0.0)) for lp in lps]
+    out = dict(workload=f"{count} reduced SCUC LPs ({name}; Algorithm 1 fixings of the solved relaxations, "
+                        f"{min(shares):.0%}-{max(shares):.0%} of u fixed, presolved)",
+               fixings=lps[0].meta.get("fixing_source", "").split(",")[0] if lps else None,
                lps=count, nnz_total=int(sum(lp.nnz for lp in lps)),
                n_min=int(min(lp.n for lp in lps)), n_max=int(max(lp.n for lp in lps)),
                batch_s=round(t_batch, 4), lps_per_s=round(count / t_batch, 2),
@@ -286,6 +324,7 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
                speedup_vs_sequential=round(t_seq / t_batch, 3) if sequential else None,
                solved=int(sum(i.term == "solved" for i in infos)),
                seq_solved=int(sum(i.term == "solved" for i in seq)),
+               stall_iters=stall_iters, continued_in_fp64=sorted(cont), seq_continued_in_fp64=seq_cont,
                worst_rel_kkt_fp64_eval=worst, setup_s=round(setup, 2),
                iters_min=int(iters.min()), iters_median=int(np.median(iters)), iters_max=int(iters.max()),
                lp_time_to_stop_s=[round(float(q), 4) for q in np.percentile([i.solve_s for i in infos],
@@ -527,6 +566,8 @@ def main():
                     help="skip the one-by-one solves of the batch's LPs")
     ap.add_argument("--batch-max-iter", type=int, default=100000)
     ap.add_argument("--batch-detail", default=None, help="write per-LP batch results to this JSON file")
+    ap.add_argument("--stall-iters", type=int, default=8192,
+                    help="FP32 stall-test span of the batch leg (stalled members continue in FP64; 0: off)")
     ap.add_argument("--successive", type=int, default=4,
                     help="rounds of the successive-fixing leg on the bench instance (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2,
@@ -609,7 +650,7 @@ def main():
 
 
     batch = (batch_leg(args.batch, stream, args.batch_parent, not args.batch_no_seq, args.batch_max_iter,
-                       args.batch_detail) if args.batch > 0 else None)
+                       args.batch_detail, args.stall_iters) if args.batch > 0 else None)
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
     sf = None
     if args.successive > 0 and args.formulation == "compact":

@@ -56,7 +56,7 @@ enum {
                                    magnitudes (h <= 0 for every sign-feasible y of a feasible
                                    LP), and the sign violations of dz on infinite column bounds
                                    sum to at most 1e-6 sum |ybar_i|; FP64-evaluated. */
-    HPR_DUAL_INFEASIBLE = 6     /* at a check, the step's primal move d = xbar - x (scaled
+    HPR_DUAL_INFEASIBLE = 6,    /* at a check, the step's primal move d = xbar - x (scaled
                                    problem) is a ray: c~^T d < 0, and the distances of A~ d to
                                    the rows' recession cone ((A~d)_i = 0 for two finite sides,
                                    >= 0 with only lo_i finite, <= 0 with only hi_i finite) and of
@@ -66,6 +66,15 @@ enum {
                                    Tested after the two above; FP64-evaluated. With FP32 storage
                                    the margin is 1e-3 instead of 1e-6: the iterates grow along
                                    the ray and d carries their FP32 rounding. */
+    HPR_STALLED = 7             /* FP32 storage only (hpr_opts.stall_iters): the check rel_kkt
+                                   did not fall to half its value at the last such halving while
+                                   the iteration count since then grew to the count at that
+                                   halving and to at least stall_iters. FP32 rounding of the
+                                   scaled matrix and of the iterates puts a floor under the
+                                   residuals (of the order of 2^-24 ||A~^T|y~| || / ||c~|| for
+                                   the dual one), so such an LP is to be continued with FP64
+                                   storage from the returned point (hpr_set_start on an
+                                   HPR_FP64 handle of the same LP). */
 };
 
 /* storage precision of A and of the iterates (hpr_opts.precision) */
@@ -166,6 +175,11 @@ typedef struct {
     double warm_fallback_ratio; /* mode 1's ratio, default 1000 (a guard against broken
                                    predictions: an early check does not predict the iteration
                                    count) */
+    int64_t stall_iters;        /* FP32 storage: smallest iteration span of the stall test that
+                                   ends a solve as HPR_STALLED (default 0 = no test: the solve
+                                   runs to its limits; a plateau of the method itself can pass
+                                   the test too, so it is for callers that continue such LPs
+                                   with FP64 storage) */
     void *stream;               /* hipStream_t or NULL */
 } hpr_opts;
 

@@ -474,12 +474,14 @@ struct PrimalOp {
     int check;
     T sigma, a0, a1;
     T xk, x0k, ck, lk, uk;
+    double sigd;
     double q[1];
     double* partials;
     __device__ __forceinline__ bool init(const BlockDesc& d) {
         const Ctrl& c = ctrl[d.lp];
         if (!c.active) return false;
         const int64_t k = c.k_base + j;
+        sigd = c.sigma;
         sigma = T(c.sigma);
         a0 = T(1.0 / double(k + 2));
         a1 = T(double(k + 1) / double(k + 2));
@@ -499,9 +501,21 @@ struct PrimalOp {
         v.xh[col] = xh;
         v.x[col] = a0 * x0k + a1 * xh;
         if (check) {
-            v.xb[col] = xb;
-            v.zb[col] = (xb - w) / sigma;
-            v.dx[col] = xk - xb;
+            if constexpr (std::is_same<T, float>::value) {
+                // The check's bar point, z and step come from w formed in FP64: in FP32 the step
+                // sigma (A^T y - c) is rounded against x (to 2^-24 |x|), and z = (xbar - w) / sigma
+                // would carry that rounding divided by sigma, a floor on the dual residual and gap
+                // that grows as sigma shrinks.
+                const double wd = double(xk) + sigd * (double(aty) - double(ck));
+                const double xbd = clampv(wd, double(lk), double(uk));
+                v.xb[col] = T(xbd);
+                v.zb[col] = T((xbd - wd) / sigd);
+                v.dx[col] = T(double(xk) - xbd);
+            } else {
+                v.xb[col] = xb;
+                v.zb[col] = (xb - w) / sigma;
+                v.dx[col] = xk - xb;
+            }
         }
     }
 };
@@ -527,12 +541,14 @@ struct DualOp {
     int check;
     T s, a0, a1;
     T yk, y0k, lok, hik;
+    double sd;
     double q[1];
     double* partials;
     __device__ __forceinline__ bool init(const BlockDesc& d) {
         const Ctrl& c = ctrl[d.lp];
         if (!c.active) return false;
         const int64_t k = c.k_base + j;
+        sd = c.s;
         s = T(c.s);
         a0 = T(1.0 / double(k + 2));
         a1 = T(double(k + 1) / double(k + 2));
@@ -552,8 +568,17 @@ struct DualOp {
         const T yh = T(2) * yb - yk;
         v.y[row] = a0 * y0k + a1 * yh;
         if (check) {
-            v.yb[row] = yb;
-            v.dy[row] = yk - yb;
+            if constexpr (std::is_same<T, float>::value) {   // as in the primal step: ybar and
+                const double vd = double(yk) - sd * double(ax);   // y - ybar from FP64 arithmetic
+                const double upd = vd + sd * double(lok);
+                const double dnd = vd + sd * double(hik);
+                const double ybd = upd > 0.0 ? upd : (dnd < 0.0 ? dnd : 0.0);
+                v.yb[row] = T(ybd);
+                v.dy[row] = T(double(yk) - ybd);
+            } else {
+                v.yb[row] = yb;
+                v.dy[row] = yk - yb;
+            }
         }
     }
 };

@@ -96,6 +96,8 @@ struct LpState {
     double norm_b, norm_c, obj_offset;
     double rel_p, rel_d, rel_gap, rel_kkt, pobj, dobj, merit;
     double p32[6];               // FP32-storage check values kept while FP64 confirms them
+    double mark_kkt;             // FP32 storage: rel_kkt at the last halving of the best one
+    int64_t mark_it;             // and the iteration count there
     int64_t it, k, restarts;
     int32_t term;                // 0 running, else HPR_SOLVED ...
     int32_t candidate;           // FP32 check passed, awaiting FP64 confirmation
@@ -159,6 +161,7 @@ struct ControlArgs {
     int sigma_update;
     double sigma_smoothing;       // weight of sigma* in the log-space update (cold start)
     double sigma_smoothing_warm;  // the same from the caller's start point
+    int64_t stall_iters;          // FP32 storage: minimum iterations of the stall test (0: off)
 };
 void launch_control(const ControlArgs& a, hipStream_t st);
 // y = A x (plain product, used by the power method).

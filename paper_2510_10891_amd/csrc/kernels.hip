@@ -124,6 +124,20 @@ __device__ void decide(LpState& S, Ctrl& c, const ControlArgs& a, double r, doub
     c.k_base = S.k;
 }
 
+// FP32 storage only: an LP has stalled when its check rel_kkt has not fallen to half the value
+// it had at the last such halving while the iteration count since then reached the count at
+// that halving (and at least stall_iters): FP32 rounding of A~ and of the iterates sets a floor
+// on the residuals that FP64 storage does not have.
+__device__ bool stalled(LpState& S, double rel_kkt, int64_t stall_iters) {
+    if (rel_kkt <= 0.5 * S.mark_kkt) {
+        S.mark_kkt = rel_kkt;
+        S.mark_it = S.it;
+        return false;
+    }
+    const int64_t since = S.it - S.mark_it;
+    return since >= stall_iters && since >= S.mark_it;
+}
+
 __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
     __shared__ int n_run, n_cand;
     if (threadIdx.x == 0) {
@@ -158,6 +172,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
                         S.p32[1] = v.move_x;
                         S.p32[2] = v.move_y;
                     }
+                } else if (a.fp32 && a.stall_iters > 0 && S.it < a.max_iter && stalled(S, v.rel_kkt, a.stall_iters)) {
+                    S.term = 7;   // HPR_STALLED
+                    c.active = 0;
                 } else {
                     decide(S, c, a, v.merit, v.move_x, v.move_y);
                 }
@@ -170,6 +187,9 @@ __global__ __launch_bounds__(kMaxBatch) void control_kernel(ControlArgs a) {
                 if (!v.bad && (v.rel_kkt <= a.tol || v.infeasible || v.unbounded)) {
                     store_values(S, v);
                     S.term = v.rel_kkt <= a.tol ? 1 : (v.infeasible ? 5 : 6);
+                    c.active = 0;
+                } else if (!v.bad && a.stall_iters > 0 && S.it < a.max_iter && stalled(S, v.rel_kkt, a.stall_iters)) {
+                    S.term = 7;   // HPR_STALLED
                     c.active = 0;
                 } else {
                     decide(S, c, a, S.p32[0], S.p32[1], S.p32[2]);

@@ -213,6 +213,7 @@ static int validate_opts(const hpr_opts* o) {
         return fail(HPR_ERR_INVALID, "unroll must be 0, 1, 2, 4 or 8");
     if (o->lds_windows < -1 || o->lds_windows > 7)
         return fail(HPR_ERR_INVALID, "lds_windows must be in [-1, 7]");
+    if (o->stall_iters < 0) return fail(HPR_ERR_INVALID, "stall_iters must be >= 0");
     return HPR_OK;
 }
 
@@ -1052,6 +1053,7 @@ extern "C" void hpr_default_opts(hpr_opts* o) {
     o->warm_fallback_ratio = 1000.0;
     o->sigma_smoothing = 1.0;
     o->sigma_smoothing_warm = 0.5;
+    o->stall_iters = 0;
     o->stream = nullptr;
 }
 
@@ -1703,6 +1705,7 @@ ControlArgs control_args(Engine* e, int phase, int nb) {
     a.sigma_update = e->opts.sigma_update;
     a.sigma_smoothing = e->opts.sigma_smoothing;
     a.sigma_smoothing_warm = e->opts.sigma_smoothing_warm;
+    a.stall_iters = e->opts.stall_iters;
     return a;
 }
 
@@ -1792,6 +1795,8 @@ void init_control(Engine* e, bool use_start) {
         S.norm_b = h.norm_b;
         S.norm_c = h.norm_c;
         S.obj_offset = h.obj_offset;
+        S.mark_kkt = INFINITY;
+        S.mark_it = 0;
         const bool has_start = !h.x_start.empty() || !h.y_start.empty();
         S.warm = (use_start && has_start && (e->use_start_mask.empty() || e->use_start_mask[l])) ? 1 : 0;
     }

@@ -8,6 +8,9 @@ none of the LP iteration's arithmetic.
 """
 from __future__ import annotations
 
+import base64
+import json
+import zlib
 from dataclasses import dataclass
 
 import numpy as np
@@ -199,15 +202,8 @@ def postsolve_free_singletons(s: Substituted, x_red, y_red, z_red):
 
 # ----------------------------------------------------------------------------- the reduced batch
 
-# Parent instances of the batch cycle through five sizes (buses, lines, units, hours,
-# monitored lines, outages per line).
-BATCH_PARENTS = [
-    scuc.SCUCConfig(30, 41, 10, 24, None, 0, 0.0, "batch-30bus"),
-    scuc.SCUCConfig(100, 150, 25, 24, 40, 3, 1e-3, "batch-100bus"),
-    scuc.SCUCConfig(300, 450, 75, 36, 60, 4, 1e-3, "batch-300bus"),
-    scuc.SCUCConfig(600, 900, 150, 48, 100, 5, 1e-3, "batch-600bus"),
-    scuc.SCUCConfig(1000, 1500, 250, 48, 150, 6, 1e-3, "batch-1000bus"),
-]
+# Parent instances of the mixed batch (defined with the generator).
+BATCH_PARENTS = scuc.BATCH_PARENTS
 
 
 def synthetic_relaxation(G: int, T: int, target: float, rng: np.random.Generator):
@@ -225,35 +221,78 @@ def synthetic_relaxation(G: int, T: int, target: float, rng: np.random.Generator
     return u, v, w
 
 
-def reduced_lp(parent: scuc.SCUCConfig, seed: int, target: float, tau: float = 0.1):
-    """One reduced LP of a successive-fixing round: Algorithm 1 (tau = 0.1) applied to the
-    parent's relaxed binaries, the fixings written as equal column bounds, then presolved."""
+def _plane(text: str, G: int, T: int) -> np.ndarray:
+    bits = np.unpackbits(np.frombuffer(zlib.decompress(base64.b64decode(text)), np.uint8))
+    return bits[:G * T].reshape(G, T).astype(bool)
+
+
+def decode_fixing(rec: dict):
+    """(fixed, ur, vr, wr) over [G][T] of a stored fixing: a record with G, T and four bit
+    planes (zlib-compressed, base64-encoded, row-major [G][T]): the fixed unit-hours and the
+    rounded u, v, w of the fixed ones."""
+    G, T = int(rec["G"]), int(rec["T"])
+    fixed = _plane(rec["fixed"], G, T)
+    ur, vr, wr = (_plane(rec[k], G, T).astype(np.int8) for k in ("u", "v", "w"))
+    return fixed, ur, vr, wr
+
+
+def load_fixings(path: str) -> list:
+    """The member records of a stored batch of fixings (a JSON file with a "members" list)."""
+    with open(path) as f:
+        return json.load(f)["members"]
+
+
+def reduced_lp(parent: scuc.SCUCConfig, seed: int, target: float, tau: float = 0.1, fixing: dict | None = None):
+    """One reduced LP of a successive-fixing round: the parent's binaries fixed by Algorithm 1,
+    the fixings written as equal column bounds, then presolved. With `fixing` (a stored record
+    for this parent and seed: Algorithm 1 on the solved relaxation, see decode_fixing) that
+    fixing is applied; otherwise Algorithm 1 (tau) runs on a synthetic relaxation aimed at
+    `target`."""
     data, lp = scuc.make_instance(parent, seed)
     G, T = parent.n_gen, parent.T
-    rng = np.random.default_rng(seed + 7919)
-    u, v, w = synthetic_relaxation(G, T, target, rng)
-    fixed, ur, vr, wr = fixing_strategy(u, v, w, tau)
+    if fixing is not None:
+        if fixing["parent"] != parent.name or int(fixing["seed"]) != seed:
+            raise ValueError(f"stored fixing is for {fixing['parent']} seed {fixing['seed']}, "
+                             f"not {parent.name} seed {seed}")
+        fixed, ur, vr, wr = decode_fixing(fixing)
+        source = f"solved relaxation, tau {fixing['tau']}"
+    else:
+        rng = np.random.default_rng(seed + 7919)
+        u, v, w = synthetic_relaxation(G, T, target, rng)
+        fixed, ur, vr, wr = fixing_strategy(u, v, w, tau)
+        source = "synthetic relaxation"
+    return apply_fixing(parent, seed, target, data, lp, fixed, ur, vr, wr, source)
+
+
+def apply_fixing(parent: scuc.SCUCConfig, seed: int, target: float, data, lp: LP, fixed, ur, vr, wr,
+                 source: str):
+    """Fix(M, S, s) for the given fixing of the parent LP, then presolve; the result's LP
+    carries the parent, seed, fixing and the kept columns and rows in its meta."""
+    G, T = parent.n_gen, parent.T
     lo, hi = fix_bounds(lp, G, T, fixed, ur, vr, wr)
     pre = presolve_fixed(lp.replace(col_lo=lo, col_hi=hi))
     pre.lp.meta.update(parent=parent.name, seed=seed, fixed_u=float(fixed.sum()) / (G * T), target=target,
                        data=data, fixed=fixed, u_fixed=np.where(fixed, ur, 0).astype(np.int8),
-                       cols=pre.cols, rows=pre.rows)
+                       cols=pre.cols, rows=pre.rows, fixing_source=source)
     return pre
 
 
 def _batch_member(args):
-    parent, seed, target = args
-    return reduced_lp(parent, seed, target)
+    parent, seed, target, fixing = args
+    return reduced_lp(parent, seed, target, fixing=fixing)
 
 
 def make_reduced_batch(count: int = 64, seed0: int = 100, classes: int | None = None,
-                       parent: scuc.SCUCConfig | None = None, workers: int = 1, log=None):
+                       parent: scuc.SCUCConfig | None = None, workers: int = 1, log=None,
+                       fixings: list | None = None):
     """`count` reduced LPs: LP i has parent seed seed0 + i and about 0.2 + 0.7 i / (count - 1)
     of its u variables fixed. Its parent is `parent` when given (e.g. the 2,000-bus preset),
-    else size class i mod (number of classes) of the mixed parent list."""
+    else size class i mod (number of classes) of the mixed parent list. `fixings` (optional):
+    stored fixings, record i for LP i (see reduced_lp)."""
     k = classes or len(BATCH_PARENTS)
     jobs = [(parent if parent is not None else BATCH_PARENTS[i % k], seed0 + i,
-             0.2 + 0.7 * i / max(count - 1, 1)) for i in range(count)]
+             0.2 + 0.7 * i / max(count - 1, 1), fixings[i] if fixings is not None else None)
+            for i in range(count)]
     if workers <= 1:
         out = []
         for j in jobs:

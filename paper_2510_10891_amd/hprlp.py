@@ -15,12 +15,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhprlp.s
 
 HPR_OK, HPR_ERR_INVALID, HPR_ERR_NOMEM, HPR_ERR_HIP, HPR_ERR_STATE = 0, -1, -2, -3, -4
 HPR_SOLVED, HPR_ITER_LIMIT, HPR_TIME_LIMIT, HPR_NUMERIC_FAIL, HPR_PRIMAL_INFEASIBLE = 1, 2, 3, 4, 5
-HPR_DUAL_INFEASIBLE = 6
+HPR_DUAL_INFEASIBLE, HPR_STALLED = 6, 7
 HPR_FP64, HPR_FP32 = 0, 1
 HPR_SCALE_PC, HPR_SCALE_RUIZ, HPR_SCALE_BC = 1, 2, 4
 TERM_NAMES = {HPR_SOLVED: "solved", HPR_ITER_LIMIT: "iter_limit", HPR_TIME_LIMIT: "time_limit",
               HPR_NUMERIC_FAIL: "numeric_fail", HPR_PRIMAL_INFEASIBLE: "primal_infeasible",
-              HPR_DUAL_INFEASIBLE: "dual_infeasible"}
+              HPR_DUAL_INFEASIBLE: "dual_infeasible", HPR_STALLED: "stalled"}
 
 
 class HprError(RuntimeError):
@@ -44,7 +44,8 @@ class hpr_opts(C.Structure):
                 ("seed", C.c_uint64), ("restart", C.c_int32), ("sigma_update", C.c_int32),
                 ("sigma_smoothing", C.c_double), ("sigma_smoothing_warm", C.c_double), ("power_max_iter", C.c_int32), ("power_tol", C.c_double), ("profile", C.c_int32),
                 ("unroll", C.c_int32), ("lds_windows", C.c_int32), ("use_graph", C.c_int32),
-                ("warm_fallback", C.c_int32), ("warm_fallback_ratio", C.c_double), ("stream", C.c_void_p)]
+                ("warm_fallback", C.c_int32), ("warm_fallback_ratio", C.c_double), ("stall_iters", C.c_int64),
+                ("stream", C.c_void_p)]
 
 
 class hpr_kernel_stats(C.Structure):
@@ -121,6 +122,7 @@ class Options:
     use_graph: int = 1
     warm_fallback: int = 2
     warm_fallback_ratio: float = 1000.0
+    stall_iters: int = 0
     stream: int = 0
 
     def to_c(self) -> hpr_opts:

@@ -85,6 +85,16 @@ class SCUCConfig:
 SMALL = SCUCConfig(30, 41, 10, 24, None, 0, 0.0, "scuc-30bus-10gen-T24")
 MEDIUM = SCUCConfig(2000, 3000, 500, 48, 300, 10, 1e-3, "scuc-2000bus-500gen-T48")
 LARGE = SCUCConfig(13500, 20000, 4000, 36, 1000, 20, 1e-3, "scuc-13500bus-4000gen-T36")
+
+# Parent instances of the batch cycle through five sizes (buses, lines, units, hours,
+# monitored lines, outages per line).
+BATCH_PARENTS = [
+    SCUCConfig(30, 41, 10, 24, None, 0, 0.0, "batch-30bus"),
+    SCUCConfig(100, 150, 25, 24, 40, 3, 1e-3, "batch-100bus"),
+    SCUCConfig(300, 450, 75, 36, 60, 4, 1e-3, "batch-300bus"),
+    SCUCConfig(600, 900, 150, 48, 100, 5, 1e-3, "batch-600bus"),
+    SCUCConfig(1000, 1500, 250, 48, 150, 6, 1e-3, "batch-1000bus"),
+]
 PRESETS = {"small": SMALL, "medium": MEDIUM, "large": LARGE}
 
 

@@ -7,8 +7,9 @@ on the device over the relaxed binaries of the bar point the solve left in HBM
 (Algorithm 2's LP-Presolve step, the default) the next round's LP is the fixed LP with its
 fixed columns substituted out and emptied rows dropped, on a handle of its own; without it one
 handle serves every round and only the bounds change. A round starts from the previous round's
-solution (restricted to the columns and rows it keeps) when `warm`. A round whose LP cannot be
-solved (or that presolve finds infeasible) stops the loop.
+solution (restricted to the columns and rows it keeps) when `warm`. A round whose FP32 solve
+stalls above the tolerance is finished with FP64 storage from that point (mixed.py). A round
+whose LP cannot be solved (or that presolve finds infeasible) stops the loop.
 """
 from __future__ import annotations
 
@@ -17,7 +18,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import fixing, hprlp, scuc
+from . import fixing, hprlp, mixed, scuc
 
 
 @dataclass
@@ -35,6 +36,7 @@ class Round:
     m: int = 0
     nnz: int = 0
     fixed: np.ndarray | None = None   # [G][T] units-hours fixed after this round
+    continued: bool = False # the FP32 solve stalled and the round's LP was finished in FP64
 
 
 @dataclass
@@ -91,22 +93,36 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
                 hprlp.hpr_set_start(h, x_full[kc], y_full[kr])
             t0 = time.perf_counter()
             info = hprlp.hpr_solve(h)
+            hs = h                      # the handle whose bar point the round ends with
+            if info.term == "stalled":  # FP32 floor above tol: go on in FP64 from this point
+                x, y, _ = hprlp.hpr_get_solution(h)
+                h64 = hprlp.hpr_create(cur, mixed.fp64_options(opts, info.iters))
+                hprlp.hpr_set_start(h64, x, y)
+                offset = time.perf_counter() - t0
+                info = mixed.merge(info, hprlp.hpr_solve(h64), offset)
+                hs = h64
             dt = time.perf_counter() - t0
-            x, y, _ = hprlp.hpr_get_solution(h)
+            x, y, _ = hprlp.hpr_get_solution(hs)
             x_full = np.where(lo == hi, lo, 0.0)
             x_full[kc] = x
             y_full = np.zeros(lp.m)
             y_full[kr] = y
             shape = dict(setup_s=setup, n=cur.n, m=cur.m, nnz=cur.nnz)
             if info.term != "solved":
+                if hs is not h:
+                    hprlp.hpr_destroy(hs)
                 res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
-                                        float(fixed.mean()), 0, fixed=fixed.copy(), **shape))
+                                        float(fixed.mean()), 0, fixed=fixed.copy(), continued=hs is not h,
+                                        **shape))
                 break
             # Round and Algorithm 1 over the bar point in HBM: columns of the solved LP, and the
             # values of the binaries presolve removed
             pos = np.full(lp.n, -1, np.int64)
             pos[kc] = np.arange(len(kc))
-            new, rounded = hprlp.hpr_fix_binaries(h, pos[cols].astype(np.int32), tau, fixval=lo[cols])
+            new, rounded = hprlp.hpr_fix_binaries(hs, pos[cols].astype(np.int32), tau, fixval=lo[cols])
+            continued = hs is not h
+            if continued:
+                hprlp.hpr_destroy(hs)
             add = new & ~fixed
             gg, tt = np.nonzero(add)
             for k in range(3):
@@ -115,7 +131,8 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
                 hi[c] = rounded[gg, tt, k]
             fixed |= new
             res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
-                                    float(fixed.mean()), int(add.sum()), fixed=fixed.copy(), **shape))
+                                    float(fixed.mean()), int(add.sum()), fixed=fixed.copy(), continued=continued,
+                                    **shape))
             if log is not None:
                 log(f"round {i}: {info.term}, {info.iters} iterations, {dt:.2f} s solve, {setup:.2f} s setup, "
                     f"n {cur.n}, {fixed.mean():.3f} of u fixed")
@@ -124,3 +141,31 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
             hprlp.hpr_destroy(h)
     res.col_lo, res.col_hi, res.x = lo, hi, x_full
     return res
+
+
+def solved_fixing(data: scuc.SCUCData, lp: scuc.LP, target: float, taus, opts: hprlp.Options | None = None):
+    """Algorithm 1 on the solved relaxation of `lp`, at the tau of `taus` whose share of fixed
+    unit-hours is nearest `target` (the smaller tau on a tie): the first round of the loop,
+    with tau picked to reach a given share. Returns (fixed, ur, vr, wr, tau, info) with
+    fixed [G][T] bool and the rounded u, v, w as int8, or None when the solve did not succeed."""
+    G, T = data.cfg.n_gen, data.cfg.T
+    opts = opts or hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32)
+    cols = binary_columns(G, T)
+    h = hprlp.hpr_create(lp, opts)
+    try:
+        info = hprlp.hpr_solve(h)
+        if info.term != "solved":
+            return None
+        best = None
+        for tau in taus:
+            fixed, rounded = hprlp.hpr_fix_binaries(h, cols, tau)
+            share = float(fixed.mean())
+            if best is None or abs(share - target) < abs(best[1] - target):
+                best = (tau, share, fixed, rounded)
+    finally:
+        hprlp.hpr_destroy(h)
+    tau, _, fixed, rounded = best
+    r = rounded.astype(np.int8)
+    on = fixed.astype(bool)
+    return on, np.where(on, r[:, :, 0], 0), np.where(on, r[:, :, 1], 0), np.where(on, r[:, :, 2], 0), tau, info
+

@@ -83,7 +83,7 @@ def test_create_rejects_no_columns():
                                  dict(lambda_=float("nan")), dict(warm_fallback_ratio=0.0), dict(warm_fallback=3),
                                  dict(unroll=3), dict(lds_windows=8), dict(lds_windows=-2),
                                  dict(sigma_smoothing=0.0), dict(sigma_smoothing=1.5),
-                                 dict(sigma_smoothing_warm=0.0)])
+                                 dict(sigma_smoothing_warm=0.0), dict(stall_iters=-1)])
 def test_create_rejects_bad_options(opt):
     with pytest.raises(hprlp.HprError) as e:
         hprlp.hpr_create(_good(), hprlp.Options(**opt))

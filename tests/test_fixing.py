@@ -152,3 +152,42 @@ def test_reduced_batch_members_are_feasible_and_uneven():
     for p in pres[:2]:
         obj, _, _ = highs(p.lp)                           # every member has an optimum
         assert np.isfinite(obj)
+
+
+def test_stored_fixings_are_algorithm1_outputs():
+    """The stored fixings of the mixed batch (Algorithm 1 on oracle-solved relaxations): member
+    i is parent class i mod 5 with seed 100 + i; per unit the fixed hours are one run starting
+    at the second hour; on fixed hours the rounded binaries satisfy v + w <= 1 and, where the
+    previous hour is fixed too, u_t - u_{t-1} = v_t - w_t; the share matches the record."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "fixing_masks_mixed.json")
+    recs = fixing.load_fixings(path)
+    assert len(recs) == 64
+    shares = []
+    for i, r in enumerate(recs):
+        parent = fixing.BATCH_PARENTS[i % len(fixing.BATCH_PARENTS)]
+        assert (r["parent"], r["seed"], r["G"], r["T"]) == (parent.name, 100 + i, parent.n_gen, parent.T)
+        assert r["oracle_term"] == "solved" and r["oracle_rel_kkt"] <= 1e-4
+        fixed, ur, vr, wr = fixing.decode_fixing(r)
+        assert abs(fixed.mean() - r["fixed_u"]) < 1e-12
+        assert not fixed[:, 0].any()
+        run = np.cumprod(fixed[:, 1:], axis=1).astype(bool)      # the run from the second hour
+        assert np.array_equal(run, fixed[:, 1:])
+        assert np.all(vr[fixed] + wr[fixed] <= 1)
+        both = fixed[:, 2:] & fixed[:, 1:-1]
+        lhs = ur[:, 2:].astype(int) - ur[:, 1:-1]
+        assert np.array_equal(lhs[both], (vr[:, 2:].astype(int) - wr[:, 2:])[both])
+        assert not (ur[~fixed].any() or vr[~fixed].any() or wr[~fixed].any())
+        shares.append(r["fixed_u"])
+    assert min(shares) < 0.3 and max(shares) > 0.8
+
+
+def test_stored_fixings_give_feasible_reduced_lps():
+    path = os.path.join(os.path.dirname(__file__), "golden", "fixing_masks_mixed.json")
+    recs = fixing.load_fixings(path)
+    pres = fixing.make_reduced_batch(count=3, seed0=100, fixings=recs[:3])
+    for p, r in zip(pres, recs):
+        assert p.feasible and p.lp.meta["fixing_source"].startswith("solved relaxation")
+        obj, _, _ = highs(p.lp)
+        assert np.isfinite(obj)
+    with pytest.raises(ValueError):                        # a record for another parent or seed
+        fixing.reduced_lp(fixing.BATCH_PARENTS[1], 100, 0.5, fixing=recs[0])

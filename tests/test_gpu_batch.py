@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2510_10891_amd import hprlp, scuc
+from paper_2510_10891_amd import fixing, hprlp, scuc
 from tests.test_gpu_parity import FP32_RTOL, FP64_RTOL, assert_close, assert_parity, ragged_lp
 
 pytestmark = pytest.mark.gpu
@@ -223,3 +223,24 @@ def test_sliced_windows_of_a_with_rows_out_of_column_order(mode, precision):
         assert info.iters == o.iters
         assert_close(x, o.x, FP32_RTOL * 10 * K, "x")
         assert_close(y, o.y, FP32_RTOL * 10 * K, "y")
+
+
+def test_stored_fixings_batch_reaches_tolerance():
+    """The first ten members of the mixed batch with the stored fixings (Algorithm 1 on solved
+    relaxations), as one FP32 batch with the stall test and the FP64 continuation: every
+    member ends solved, judged by the oracle's FP64 KKT evaluator."""
+    import os
+    from paper_2510_10891_amd import mixed
+    recs = fixing.load_fixings(os.path.join(os.path.dirname(__file__), "golden", "fixing_masks_mixed.json"))
+    lps = [p.lp for p in fixing.make_reduced_batch(count=10, seed0=100, fixings=recs[:10])]
+    opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000, stall_iters=8192)
+    b = hprlp.hpr_batch_create(lps, opts)
+    try:
+        infos = hprlp.hpr_batch_solve(b)
+        infos, cont = mixed.continue_stalled(lps, opts, infos, lambda i: hprlp.hpr_batch_get_solution(b, i))
+        sols = [cont[i] if i in cont else hprlp.hpr_batch_get_solution(b, i) for i in range(len(lps))]
+    finally:
+        hprlp.hpr_batch_destroy(b)
+    for lp, info, (x, y, z) in zip(lps, infos, sols):
+        assert info.term == "solved", (lp.meta["parent"], info)
+        assert oracle.kkt(lp, x, y, z)["rel_kkt"] <= 1e-4 * (1 + 1e-6)
