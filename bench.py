@@ -42,7 +42,7 @@ def recorded_traffic(kernel, workload):
     return float(m_val.group(1))
 
 
-KERNEL_SOURCES = ("csr.h", "kernels_dual32.hip", "kernels_primal32.hip", "solver.hip")
+KERNEL_SOURCES = ("csr.h", "kernels_dual32.hip", "kernels_primal32.hip", "solver.hip", "setup.hip")
 
 
 def sources_sha256():

@@ -8,6 +8,7 @@
 // used by the products is refreshed after every step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -44,9 +45,15 @@ __host__ __device__ inline float from_bf16(uint16_t h) {
 
 // C(i, j) = sum_k A(i, k) B(k, j) for an M x N output, BF16 operands addressed with
 // element strides (A(i,k) = A[i*sa0 + k*sa1], B(k,j) = B[k*sb0 + j*sb1]) so transposed
-// operands need no copy. One wavefront computes one 16 x 16 tile with
-// v_mfma_f32_16x16x16_bf16 over K in steps of 16; out-of-range rows/columns/depths are
-// read as zero. Epilogue: + bias (FP32, may be null), optional ReLU, FP32 and/or BF16 store.
+// operands need no copy; one of each operand's strides is 1. A workgroup of four wavefronts
+// computes a 64 x 64 block of C: per step of 32 depths it stages the A (64 x 32) and B (32 x 64)
+// tiles in LDS with loads that run along the operand's contiguous dimension (coalesced), both
+// stored depth-contiguous, and each wavefront runs v_mfma_f32_16x16x16_bf16 on its 32 x 32
+// quarter (2 x 2 tiles, depths in ascending steps of 16: the summation order of a one-tile-per-
+// wavefront loop). Out-of-range rows/columns/depths are staged as zero. With `ws` the depth range
+// is split over gridDim.z slices that write FP32 partial blocks to ws[z][M][N]; finish_split_kernel
+// adds them in slice order. Epilogue: + bias (FP32, may be null), optional ReLU, FP32 and/or BF16
+// store.
 struct GemmArgs {
     const uint16_t* A;
     const uint16_t* B;
@@ -56,49 +63,126 @@ struct GemmArgs {
     int relu;
     float* C32;        // [M][N] or null
     uint16_t* C16;     // [M][N] or null
+    float* ws;         // split-depth partials [splits][M][N], or null (no split)
+    int kslice;        // depths per slice (multiple of kBK) when ws is set
 };
 
-__global__ __launch_bounds__(kThreads) void gemm_bf16_kernel(GemmArgs g) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int tiles_n = (g.N + kTile - 1) / kTile;
-    const int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wave;
-    const int64_t tiles = (int64_t)((g.M + kTile - 1) / kTile) * tiles_n;
-    if (tile >= tiles) return;
-    const int i0 = (int)(tile / tiles_n) * kTile;
-    const int j0 = (int)(tile % tiles_n) * kTile;
-    const int r = lane & 15;          // A row / B column of this lane
-    const int kq = (lane >> 4) * 4;   // first of the 4 depths this lane supplies
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kTile) {
-        bf16x4 a, b;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = k0 + kq + t;
-            const int ia = i0 + r, jb = j0 + r;
-            a[t] = (ia < g.M && k < g.K) ? (short)g.A[(int64_t)ia * g.sa0 + (int64_t)k * g.sa1] : (short)0;
-            b[t] = (jb < g.N && k < g.K) ? (short)g.B[(int64_t)k * g.sb0 + (int64_t)jb * g.sb1] : (short)0;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    const int j = j0 + r;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int i = i0 + (lane >> 4) * 4 + t;
-        if (i < g.M && j < g.N) {
-            float v = acc[t] + (g.bias ? g.bias[j] : 0.f);
-            if (g.relu) v = v > 0.f ? v : 0.f;
-            if (g.C32) g.C32[(int64_t)i * g.N + j] = v;
-            if (g.C16) g.C16[(int64_t)i * g.N + j] = to_bf16(v);
-        }
-    }
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kLdsRow = kBK + 8;     // shorts per staged row (padding against bank conflicts)
+
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, int i, int j, float v) {
+    v += g.bias ? g.bias[j] : 0.f;
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    if (g.C32) g.C32[(int64_t)i * g.N + j] = v;
+    if (g.C16) g.C16[(int64_t)i * g.N + j] = to_bf16(v);
 }
 
-void gemm(const GemmArgs& g, hipStream_t st) {
+__global__ __launch_bounds__(kThreads) void gemm_bf16_kernel(GemmArgs g) {
+    __shared__ short As[kBM * kLdsRow];   // [row][depth]
+    __shared__ short Bs[kBN * kLdsRow];   // [column][depth]
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int i0 = blockIdx.y * kBM, j0 = blockIdx.x * kBN;
+    const int kb = g.ws ? blockIdx.z * g.kslice : 0;
+    const int ke = g.ws ? min(g.K, kb + g.kslice) : g.K;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += kBK) {
+        // stage A: 64 x 32 = 8 per thread, consecutive threads along the contiguous dimension
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int q = e * kThreads + t;
+            int row, k;
+            if (g.sa1 == 1) { row = q / kBK; k = q % kBK; }
+            else            { k = q / kBM;  row = q % kBM; }
+            const int ia = i0 + row, ka = k0 + k;
+            As[row * kLdsRow + k] = (ia < g.M && ka < ke) ? (short)g.A[(int64_t)ia * g.sa0 + (int64_t)ka * g.sa1] : (short)0;
+        }
+        // stage B: 32 x 64
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int q = e * kThreads + t;
+            int col, k;
+            if (g.sb1 == 1) { k = q / kBN; col = q % kBN; }
+            else            { col = q / kBK; k = q % kBK; }
+            const int jb = j0 + col, kk = k0 + k;
+            Bs[col * kLdsRow + k] = (jb < g.N && kk < ke) ? (short)g.B[(int64_t)kk * g.sb0 + (int64_t)jb * g.sb1] : (short)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 16) {
+            bf16x4 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const short* pa = As + (wm + a * 16 + r) * kLdsRow + kk + kq;
+                const short* pb = Bs + (wn + a * 16 + r) * kLdsRow + kk + kq;
+                av[a] = bf16x4{pa[0], pa[1], pa[2], pa[3]};
+                bv[a] = bf16x4{pb[0], pb[1], pb[2], pb[3]};
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + wn + b * 16 + r;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + wm + a * 16 + (lane >> 4) * 4 + u;
+                if (i < g.M && j < g.N) {
+                    if (g.ws) g.ws[((int64_t)blockIdx.z * g.M + i) * g.N + j] = acc[a][b][u];
+                    else gemm_epilogue(g, i, j, acc[a][b][u]);
+                }
+            }
+        }
+}
+
+// C = sum over the slices of ws, added in slice order, then the epilogue.
+__global__ __launch_bounds__(kThreads) void finish_split_kernel(GemmArgs g, int splits) {
+    const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t mn = (int64_t)g.M * g.N;
+    if (idx >= mn) return;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += g.ws[z * mn + idx];
+    gemm_epilogue(g, (int)(idx / g.N), (int)(idx % g.N), v);
+}
+
+// Launch: one workgroup per 64 x 64 block of C. `ws_floats` (with g.ws) is the partial-sum
+// room; the depth is split when the blocks alone would leave most of the GPU idle and the
+// depth is long (the weight gradients, whose depth is the number of rows).
+void gemm(GemmArgs g, hipStream_t st, int64_t ws_floats = 0) {
     if (g.M <= 0 || g.N <= 0) return;
-    const int64_t tiles = (int64_t)((g.M + kTile - 1) / kTile) * ((g.N + kTile - 1) / kTile);
-    const int64_t blocks = (tiles + (kThreads / 64) - 1) / (kThreads / 64);
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, st, g);
+    const int bx = (g.N + kBN - 1) / kBN, by = (g.M + kBM - 1) / kBM;
+    int splits = 1;
+    if (g.ws && ws_floats > 0 && g.K >= 4 * kBK * 16) {
+        const int64_t blocks = (int64_t)bx * by;
+        const int64_t want = (1024 + blocks - 1) / blocks;                 // ~1024 workgroups
+        const int64_t room = ws_floats / ((int64_t)g.M * g.N);
+        const int64_t depth = (g.K + 16 * kBK - 1) / (16 * kBK);            // >= 16 steps per slice
+        splits = (int)std::max<int64_t>(1, std::min({want, room, depth, (int64_t)64}));
+    }
+    if (splits == 1) {
+        g.ws = nullptr;
+        hipLaunchKernelGGL(gemm_bf16_kernel, dim3(bx, by, 1), dim3(kThreads), 0, st, g);
+        return;
+    }
+    g.kslice = ((g.K + splits - 1) / splits + kBK - 1) / kBK * kBK;
+    splits = (g.K + g.kslice - 1) / g.kslice;
+    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(bx, by, splits), dim3(kThreads), 0, st, g);
+    const int64_t mn = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(finish_split_kernel, dim3((unsigned)((mn + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g,
+                       splits);
 }
 
 __global__ void f32_to_bf16_kernel(const float* s, uint16_t* d, int64_t n) {
@@ -223,10 +307,12 @@ struct hpr_mlp {
     float* xin = nullptr;                                             // staging of X and targets
     float* tgt = nullptr;
     double* part = nullptr;
+    float* ws = nullptr;                                              // split-depth partials of dW
+    int64_t ws_floats = 0;
     int64_t step = 0;
     ~hpr_mlp() {
         if (st) (void)hipStreamSynchronize(st);
-        for (void* p : {(void*)w, (void*)grad, (void*)m, (void*)v, (void*)w16}) (void)hipFree(p);
+        for (void* p : {(void*)w, (void*)grad, (void*)m, (void*)v, (void*)w16, (void*)ws}) (void)hipFree(p);
         release_rows();
         if (own_stream && st) (void)hipStreamDestroy(st);
     }
@@ -248,6 +334,15 @@ struct hpr_mlp {
         int mx = 0;
         for (int i = 0; i <= L; ++i) mx = sizes[i] > mx ? sizes[i] : mx;
         return mx;
+    }
+    // room for up to 64 partial copies of the largest weight matrix, at most 64 MiB
+    int ensure_ws() {
+        if (ws) return HPR_OK;
+        int64_t mx = 0;
+        for (int i = 0; i < L; ++i) mx = std::max<int64_t>(mx, (int64_t)sizes[i] * sizes[i + 1]);
+        ws_floats = std::min<int64_t>(64 * mx, (int64_t)16 << 20);
+        MLP_HIP(hipMalloc(&ws, sizeof(float) * ws_floats));
+        return HPR_OK;
     }
     int ensure_rows(int64_t n) {
         if (n <= cap) return HPR_OK;
@@ -304,7 +399,9 @@ int forward_staged(hpr_mlp* q, int64_t n) {
 
 // loss and gradients into q->grad for rows staged in xin / tgt
 int gradients_staged(hpr_mlp* q, int64_t n, float* loss) {
-    int rc = forward_staged(q, n);
+    int rc = q->ensure_ws();
+    if (rc) return rc;
+    rc = forward_staged(q, n);
     if (rc) return rc;
     const int L = q->L;
     const int64_t nout = n * q->sizes[L];
@@ -327,7 +424,8 @@ int gradients_staged(hpr_mlp* q, int64_t n, float* loss) {
         gw.N = q->sizes[i + 1];
         gw.K = (int)n;
         gw.C32 = q->grad + q->woff[i];
-        gemm(gw, q->st);
+        gw.ws = q->ws;
+        gemm(gw, q->st, q->ws_floats);
         hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(q->sizes[i + 1])), dim3(kThreads), 0, q->st, g, (int)n,
                            q->sizes[i + 1], q->grad + q->boff[i]);
         if (i > 0) {

@@ -191,3 +191,27 @@ def test_stored_fixings_give_feasible_reduced_lps():
         assert np.isfinite(obj)
     with pytest.raises(ValueError):                        # a record for another parent or seed
         fixing.reduced_lp(fixing.BATCH_PARENTS[1], 100, 0.5, fixing=recs[0])
+
+
+def _highs_status(lp) -> int:
+    import scipy.sparse as sp
+    from scipy.optimize import linprog
+    A = lp.to_scipy()
+    eq = lp.row_lo == lp.row_hi
+    ub = np.isfinite(lp.row_hi) & ~eq
+    lb = np.isfinite(lp.row_lo) & ~eq
+    res = linprog(lp.c, A_ub=sp.vstack([A[ub], -A[lb]]).tocsr(), b_ub=np.r_[lp.row_hi[ub], -lp.row_lo[lb]],
+                  A_eq=A[eq], b_eq=lp.row_lo[eq], bounds=np.c_[lp.col_lo, lp.col_hi], method="highs")
+    return int(res.status)
+
+
+def test_some_stored_fixings_make_the_lp_infeasible():
+    """Rounding and fixing a relaxed solution can leave no feasible dispatch (Section IV's
+    intermediate models): HiGHS finds members 45, 55 and 60 of the mixed batch (30-bus
+    parents, 73-81% of u fixed) infeasible and members 40 and 50 feasible."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "fixing_masks_mixed.json")
+    recs = fixing.load_fixings(path)
+    for i, status in ((40, 0), (45, 2), (50, 0), (55, 2), (60, 2)):
+        parent = fixing.BATCH_PARENTS[i % len(fixing.BATCH_PARENTS)]
+        pre = fixing.reduced_lp(parent, 100 + i, 0.0, fixing=recs[i])
+        assert _highs_status(pre.lp) == status, i

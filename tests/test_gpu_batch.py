@@ -244,3 +244,18 @@ def test_stored_fixings_batch_reaches_tolerance():
     for lp, info, (x, y, z) in zip(lps, infos, sols):
         assert info.term == "solved", (lp.meta["parent"], info)
         assert oracle.kkt(lp, x, y, z)["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_stored_fixings_infeasible_members_are_certified():
+    """Members 40-60 (step 5) of the mixed batch, 30-bus parents: the batch certifies primal
+    infeasibility exactly for the members HiGHS finds infeasible (45, 55, 60) and solves the
+    others."""
+    import os
+    from tests.test_fixing import _highs_status
+    recs = fixing.load_fixings(os.path.join(os.path.dirname(__file__), "golden", "fixing_masks_mixed.json"))
+    idx = [40, 45, 50, 55, 60]
+    lps = [fixing.reduced_lp(fixing.BATCH_PARENTS[0], 100 + i, 0.0, fixing=recs[i]).lp for i in idx]
+    infos = [r[0] for r in hprlp.batch_solve(lps, hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=100000))]
+    for i, lp, info in zip(idx, lps, infos):
+        expect = "solved" if _highs_status(lp) == 0 else "primal_infeasible"
+        assert info.term == expect, (i, info)
