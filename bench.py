@@ -345,6 +345,38 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
     return out
 
 
+def mlp_leg(steps, stream, rows=8192):
+    """Training-step throughput of the warm-start network (the unit-hour network's shape,
+    BF16 MFMA products with FP32 accumulation): `steps` Adam steps on `rows` synthetic rows,
+    timed after one warm-up step; FLOPs = 2 rows (sum K N) for the forward products and twice
+    that for the backward ones (dW and, except for the first layer, dh)."""
+    import numpy as np
+    import torch
+
+    from paper_2510_10891_amd import mlp, warmstart
+
+    sizes = warmstart.GEN_SIZES
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((rows, sizes[0])).astype(np.float32)
+    T = rng.standard_normal((rows, sizes[-1])).astype(np.float32)
+    net = mlp.MLP(sizes, mlp.init_params(sizes, 0), stream=stream)
+    net.train_step(X, T, 1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(X, T, 1e-3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kn = [sizes[i] * sizes[i + 1] for i in range(len(sizes) - 1)]
+    flops = 2.0 * rows * (sum(kn) + sum(kn) + sum(kn[1:]))
+    out = dict(workload=f"Adam steps of the unit-hour network {sizes} on {rows} rows (BF16 MFMA, FP32 accumulation)",
+               ms_per_step=round(dt * 1e3, 3), tflops=round(flops / dt / 1e12, 2),
+               frac_of_bf16_peak=round(flops / dt / 2.5e15, 5),
+               note="host-staged inputs: each step copies its rows to the device and reads the loss back")
+    log(f"mlp: {out}")
+    return out
+
+
 def warmstart_leg(n_train, n_eval, stream):
     """Learned warm start: train the two networks on the GPU on solver-produced solutions of
     `n_train` training LPs, then solve the evaluation batch (the batch leg's reduced LPs)
@@ -533,6 +565,8 @@ def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
         kname, kbytes, kalg, kms, other = f"dual_step_{tag}", db, da, ks["dual_ms"], ks["primal_ms"]
     else:
         kname, kbytes, kalg, kms, other = f"primal_step_{tag}", pb, pa, ks["primal_ms"], ks["dual_ms"]
+    if not kms > 0:      # no sampled launch (a run shorter than the sampling interval)
+        return None
     achieved = kbytes / (kms * 1e-3) / 1e9
     return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
@@ -576,6 +610,8 @@ def main():
                     help="rounds of the scaling/precision ablation leg (successive fixing; 0: skip)")
     ap.add_argument("--warmstart", type=int, default=0,
                     help="training LPs of the learned warm-start leg (0: skip)")
+    ap.add_argument("--mlp-steps", type=int, default=0,
+                    help="timed training steps of the warm-start network's throughput leg (0: skip)")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="iteration cap (lower it only for profiler runs; the line is then not a tolerance time)")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
@@ -652,6 +688,7 @@ def main():
     batch = (batch_leg(args.batch, stream, args.batch_parent, not args.batch_no_seq, args.batch_max_iter,
                        args.batch_detail, args.stall_iters) if args.batch > 0 else None)
     warm = warmstart_leg(args.warmstart, max(args.batch, 16), stream) if args.warmstart > 0 else None
+    mlp_out = mlp_leg(args.mlp_steps, stream) if args.mlp_steps > 0 else None
     sf = None
     if args.successive > 0 and args.formulation == "compact":
         from paper_2510_10891_amd import successive
@@ -722,6 +759,7 @@ def main():
         "roofline": roof,
         "batch": batch,
         "warm_start": warm,
+        "mlp": mlp_out,
         "successive_fixing": sf,
         "large": large,
         "ablation": abl,

@@ -216,12 +216,26 @@ __global__ void relu_back_kernel(const float* z, uint16_t* g, int64_t n) {
     if (i < n && !(z[i] > 0.f)) g[i] = 0;
 }
 
-// db[j] = sum_i g[i][j] (column sums in a fixed order, FP32 accumulate)
-__global__ void bias_grad_kernel(const uint16_t* g, int rows, int cols, float* db) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// db[j] = sum_i g[i][j] (column sums in a fixed order, FP32 accumulate) in two passes: block
+// (c, b) sums rows c*kBiasRows.. of columns b*kThreads.. into part[c][j] (consecutive threads on
+// consecutive columns), then bias_grad_finish adds the chunks in order.
+constexpr int kBiasRows = 128;
+
+__global__ __launch_bounds__(kThreads) void bias_grad_kernel(const uint16_t* g, int rows, int cols, float* part) {
+    const int j = blockIdx.y * kThreads + threadIdx.x;
+    if (j >= cols) return;
+    const int i0 = blockIdx.x * kBiasRows;
+    const int i1 = min(rows, i0 + kBiasRows);
+    float s = 0.f;
+    for (int i = i0; i < i1; ++i) s += from_bf16(g[(int64_t)i * cols + j]);
+    part[(int64_t)blockIdx.x * cols + j] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void bias_grad_finish(const float* part, int chunks, int cols, float* db) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
     if (j >= cols) return;
     float s = 0.f;
-    for (int i = 0; i < rows; ++i) s += from_bf16(g[(int64_t)i * cols + j]);
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * cols + j];
     db[j] = s;
 }
 
@@ -309,6 +323,7 @@ struct hpr_mlp {
     double* part = nullptr;
     float* ws = nullptr;                                              // split-depth partials of dW
     int64_t ws_floats = 0;
+    float* ws_bias = nullptr;                                         // row-chunk partials of db
     int64_t step = 0;
     ~hpr_mlp() {
         if (st) (void)hipStreamSynchronize(st);
@@ -325,6 +340,8 @@ struct hpr_mlp {
         (void)hipFree(xin);
         (void)hipFree(tgt);
         (void)hipFree(part);
+        (void)hipFree(ws_bias);
+        ws_bias = nullptr;
         x16 = g16 = g16b = nullptr;
         xin = tgt = nullptr;
         part = nullptr;
@@ -356,6 +373,7 @@ struct hpr_mlp {
         MLP_HIP(hipMalloc(&g16, sizeof(uint16_t) * n * W));
         MLP_HIP(hipMalloc(&g16b, sizeof(uint16_t) * n * W));
         MLP_HIP(hipMalloc(&part, sizeof(double) * 1024));
+        MLP_HIP(hipMalloc(&ws_bias, sizeof(float) * ((n + kBiasRows - 1) / kBiasRows) * W));
         cap = n;
         return HPR_OK;
     }
@@ -426,8 +444,15 @@ int gradients_staged(hpr_mlp* q, int64_t n, float* loss) {
         gw.C32 = q->grad + q->woff[i];
         gw.ws = q->ws;
         gemm(gw, q->st, q->ws_floats);
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks_for(q->sizes[i + 1])), dim3(kThreads), 0, q->st, g, (int)n,
-                           q->sizes[i + 1], q->grad + q->boff[i]);
+        {   // db_i: row chunks into the workspace (free again once the dW product is done)
+            const int cols = q->sizes[i + 1];
+            const int chunks = (int)((n + kBiasRows - 1) / kBiasRows);
+            float* part = q->ws_bias;
+            hipLaunchKernelGGL(bias_grad_kernel, dim3(chunks, (cols + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                               q->st, g, (int)n, cols, part);
+            hipLaunchKernelGGL(bias_grad_finish, dim3((cols + kThreads - 1) / kThreads), dim3(kThreads), 0, q->st,
+                               part, chunks, cols, q->grad + q->boff[i]);
+        }
         if (i > 0) {
             // dh_i = g W_i^T, then ReLU mask with z_{i-1}
             GemmArgs gh{};

@@ -51,13 +51,6 @@ __global__ void column_ends_kernel(const uint32_t* keys, int64_t nnz, int64_t* t
     (void)n;
 }
 
-// columns without entries take the end of the previous column (running maximum, one thread)
-__global__ void fill_empty_columns_kernel(int64_t* tptr, int32_t n) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    tptr[0] = 0;
-    for (int32_t j = 0; j < n; ++j)
-        if (tptr[j + 1] < tptr[j]) tptr[j + 1] = tptr[j];
-}
 
 // One scaling pass over rows (A in the caller's order) or columns (through the sorted entry list):
 // out[i] = sum or max of |v dr dc| over the row's entries in order (the host forms the factors).
@@ -159,6 +152,14 @@ __global__ void tile_runs_kernel(const int64_t* start, const int32_t* col, int32
     } while (0)
 
 // exclusive scan of in[0..count) into out[0..count], out[count] = total
+// out[0..count] = running maximum of in[0..count]
+hipError_t max_scan(const int64_t* in, int64_t* out, int32_t count, hipStream_t st, DevScratch& tmp) {
+    size_t bytes = 0;
+    SETUP_HIP(rocprim::inclusive_scan(nullptr, bytes, in, out, (size_t)count + 1, rocprim::maximum<int64_t>(), st));
+    SETUP_HIP(tmp.reserve(bytes));
+    return rocprim::inclusive_scan(tmp.p, bytes, in, out, (size_t)count + 1, rocprim::maximum<int64_t>(), st);
+}
+
 hipError_t exclusive_scan(const int64_t* in, int64_t* out, int32_t count, hipStream_t st, DevScratch& tmp) {
     size_t bytes = 0;
     SETUP_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, int64_t(0), (size_t)count + 1, rocprim::plus<int64_t>(),
@@ -210,7 +211,16 @@ hipError_t device_setup(const DevSetupIn& in, DevSetupOut& out, hipStream_t st) 
     int64_t* tptr = static_cast<int64_t*>(out.tptr.p);
     SETUP_HIP(hipMemsetAsync(tptr, 0xFF, sizeof(int64_t) * ((size_t)n + 1), st));   // -1: no entry yet
     if (nnz > 0) hipLaunchKernelGGL(column_ends_kernel, dim3(grid_for(nnz)), dim3(kT), 0, st, keys, nnz, tptr, n);
-    hipLaunchKernelGGL(fill_empty_columns_kernel, dim3(1), dim3(1), 0, st, tptr, n);
+    // columns without entries take the end of the previous column: tptr[0] = 0, then a running
+    // maximum (through a copy: the scan does not work in place)
+    SETUP_HIP(hipMemsetAsync(tptr, 0, sizeof(int64_t), st));
+    {
+        DevScratch ends;
+        SETUP_HIP(ends.reserve(sizeof(int64_t) * ((size_t)n + 1)));
+        SETUP_HIP(hipMemcpyAsync(ends.p, tptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, st));
+        SETUP_HIP(max_scan(static_cast<const int64_t*>(ends.p), tptr, n, st, tmp));
+        SETUP_HIP(hipStreamSynchronize(st));   // `ends` is freed at the end of this scope
+    }
     // 2. scaling: the device reduces, the host forms the factors f *= (r > 0 ? 1 / sqrt(r) : 1)
     double* dr = in.dr;
     double* dc = in.dc;

@@ -45,7 +45,7 @@ def reference(params, sizes, X):
 
 # widths and row counts off the 16-wide tiles on purpose (M, N and K of every product)
 SHAPES = [([12, 256, 256, 4], 1000), ([9, 256, 256, 1], 333), ([16, 32, 5], 17), ([3, 7], 64),
-          ([20, 48, 33, 7], 45)]
+          ([20, 48, 33, 7], 45), ([12, 70, 40, 3], 5000)]   # the last: dW products split over the depth
 
 
 @pytest.mark.parametrize("sizes,rows", SHAPES)
