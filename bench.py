@@ -257,7 +257,7 @@ def reduced_batch(count, big, stream):
     return lps
 
 
-def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, detail=None, stall_iters=8192):
+def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, detail=None, stall_iters=-1):
     """The reduced LPs of successive-fixing rounds (uneven sizes) solved as one batch with FP32
     storage, against the same LPs solved one after another with the same options. `parent`:
     "mixed" = parents of 30 to 1,000 buses; "medium" = 2,000-bus parents (seeds 100 + i), each
@@ -275,6 +275,8 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
         f"nnz total {sum(lp.nnz for lp in lps)} ({time.perf_counter() - t:.1f} s)")
     # the 2,000-bus batch is one long library call: a time limit bounds it (members still running
     # then end as time_limit and are counted as unsolved)
+    if stall_iters < 0:
+        stall_iters = 8192 if big else 0
     opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=max_iter, stream=stream,
                          time_limit_s=150.0 if big else 0.0, stall_iters=stall_iters)
     t = time.perf_counter()
@@ -600,8 +602,10 @@ def main():
                     help="skip the one-by-one solves of the batch's LPs")
     ap.add_argument("--batch-max-iter", type=int, default=100000)
     ap.add_argument("--batch-detail", default=None, help="write per-LP batch results to this JSON file")
-    ap.add_argument("--stall-iters", type=int, default=8192,
-                    help="FP32 stall-test span of the batch leg (stalled members continue in FP64; 0: off)")
+    ap.add_argument("--stall-iters", type=int, default=-1,
+                    help="FP32 stall-test span of the batch leg (stalled members continue in FP64; 0: off; "
+                         "default: 8192 for 2,000-bus parents, off for the mixed parents, whose members all "
+                         "converge in FP32 and where the continuation, run after the batch, only adds time)")
     ap.add_argument("--successive", type=int, default=4,
                     help="rounds of the successive-fixing leg on the bench instance (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2,
