@@ -278,7 +278,7 @@ def batch_leg(count, stream, parent="mixed", sequential=True, max_iter=100000, d
     if stall_iters < 0:
         stall_iters = 8192 if big else 0
     opts = hprlp.Options(tol=1e-4, precision=hprlp.HPR_FP32, max_iter=max_iter, stream=stream,
-                         time_limit_s=150.0 if big else 0.0, stall_iters=stall_iters)
+                         time_limit_s=400.0 if big else 0.0, stall_iters=stall_iters)
     t = time.perf_counter()
     b = hprlp.hpr_batch_create(lps, opts)
     log(f"batch engine created in {time.perf_counter() - t:.1f} s")

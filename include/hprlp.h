@@ -72,7 +72,8 @@ enum {
                                    halving and to at least stall_iters. FP32 rounding of the
                                    scaled matrix and of the iterates puts a floor under the
                                    residuals (of the order of 2^-24 ||A~^T|y~| || / ||c~|| for
-                                   the dual one), so such an LP is to be continued with FP64
+                                   the dual one) and can hold the iteration on a plateau above
+                                   the tolerance, so such an LP is to be continued with FP64
                                    storage from the returned point (hpr_set_start on an
                                    HPR_FP64 handle of the same LP). */
 };

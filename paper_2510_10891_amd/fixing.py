@@ -1,7 +1,7 @@
 """Successive fixing around the LP solver (Section IV): Round, the logic-driven
 Fixing-Strategy of Algorithm 1, a minimal LP presolve (fixed columns, implied-free column
-singletons), and the batch of reduced LPs that
-successive-fixing rounds hand to the solver.
+singletons), and the batch of reduced LPs that successive-fixing rounds hand to the solver
+(built from stored fixings of solved relaxations, or from synthetic relaxations).
 
 Host-side support code: it decides which binaries are fixed and rewrites the LP; it holds
 none of the LP iteration's arithmetic.

@@ -1,14 +1,15 @@
 """FP32 storage with an FP64 continuation of stalled LPs.
 
 FP32 storage (the FP32 variant of the GPU solver in Section III-B) rounds the scaled matrix and
-the iterates to 24 bits, which puts a floor under the residuals of the order of
-2^-24 ||A~^T |y~| || / ||c~|| for the dual one: an LP whose duals are large next to its cost
-cannot reach a tight tolerance that way. With hpr_opts.stall_iters set the library ends a solve
-whose residuals stop falling as "stalled" (a plateau of the method itself can end that way
-too; its continuation costs FP64 iterations, not accuracy); the functions here continue those LPs with FP64 storage from the point
-the FP32 run returned (a warm start that skips the start-point race: that point is the FP32
-run's best estimate), so that every LP ends at the requested tolerance or at a genuine
-iteration or time limit. All arithmetic runs in the library.
+the iterates to 24 bits. That puts a floor under the residuals (of the order of
+2^-24 ||A~^T |y~| || / ||c~|| for the dual one), and an FP32 run can also settle on a plateau above
+the tolerance that FP64 storage leaves (seen on a reduced LP at rel_kkt 1e-3, far above its rounding
+floor). With hpr_opts.stall_iters set the library ends a solve whose residuals stop falling as
+"stalled" (a plateau that FP32 would leave later ends that way too: its continuation costs FP64
+iterations, not accuracy); the functions here continue those LPs with FP64 storage from the point
+the FP32 run returned (a warm start that skips the start-point race: that point is the FP32 run's
+best estimate), so that every LP ends at the requested tolerance or at a genuine iteration or time
+limit. All arithmetic runs in the library.
 """
 from __future__ import annotations
 

@@ -65,7 +65,7 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
     lo, hi = lp.col_lo.copy(), lp.col_hi.copy()
     fixed = np.zeros((G, T), bool)
     x_full = y_full = None
-    h = None
+    h = hs = None   # the round's handle, and the FP64 continuation's when its FP32 solve stalled
     try:
         for i in range(1, rounds + 1):
             setup = 0.0
@@ -78,6 +78,7 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
                 cur, kc, kr = pre.lp, pre.cols, pre.rows
                 if h is not None:
                     hprlp.hpr_destroy(h)
+                    h = hs = None
                 t0 = time.perf_counter()
                 h = hprlp.hpr_create(cur, opts)
                 setup = time.perf_counter() - t0
@@ -91,16 +92,15 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
                     hprlp.hpr_set_bounds(h, lo, hi)
             if warm and x_full is not None:
                 hprlp.hpr_set_start(h, x_full[kc], y_full[kr])
+            hs = h
             t0 = time.perf_counter()
             info = hprlp.hpr_solve(h)
-            hs = h                      # the handle whose bar point the round ends with
-            if info.term == "stalled":  # FP32 floor above tol: go on in FP64 from this point
+            if info.term == "stalled":  # FP32 plateau above tol: go on in FP64 from this point
                 x, y, _ = hprlp.hpr_get_solution(h)
-                h64 = hprlp.hpr_create(cur, mixed.fp64_options(opts, info.iters))
-                hprlp.hpr_set_start(h64, x, y)
+                hs = hprlp.hpr_create(cur, mixed.fp64_options(opts, info.iters))
+                hprlp.hpr_set_start(hs, x, y)
                 offset = time.perf_counter() - t0
-                info = mixed.merge(info, hprlp.hpr_solve(h64), offset)
-                hs = h64
+                info = mixed.merge(info, hprlp.hpr_solve(hs), offset)
             dt = time.perf_counter() - t0
             x, y, _ = hprlp.hpr_get_solution(hs)
             x_full = np.where(lo == hi, lo, 0.0)
@@ -108,11 +108,10 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
             y_full = np.zeros(lp.m)
             y_full[kr] = y
             shape = dict(setup_s=setup, n=cur.n, m=cur.m, nnz=cur.nnz)
+            continued = hs is not h
             if info.term != "solved":
-                if hs is not h:
-                    hprlp.hpr_destroy(hs)
                 res.rounds.append(Round(i, info.term, info.iters, dt, info.pobj, info.rel_kkt,
-                                        float(fixed.mean()), 0, fixed=fixed.copy(), continued=hs is not h,
+                                        float(fixed.mean()), 0, fixed=fixed.copy(), continued=continued,
                                         **shape))
                 break
             # Round and Algorithm 1 over the bar point in HBM: columns of the solved LP, and the
@@ -120,9 +119,9 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
             pos = np.full(lp.n, -1, np.int64)
             pos[kc] = np.arange(len(kc))
             new, rounded = hprlp.hpr_fix_binaries(hs, pos[cols].astype(np.int32), tau, fixval=lo[cols])
-            continued = hs is not h
             if continued:
                 hprlp.hpr_destroy(hs)
+                hs = h
             add = new & ~fixed
             gg, tt = np.nonzero(add)
             for k in range(3):
@@ -137,6 +136,8 @@ def run(data: scuc.SCUCData, lp: scuc.LP, rounds: int = 4, tau: float = 0.1,
                 log(f"round {i}: {info.term}, {info.iters} iterations, {dt:.2f} s solve, {setup:.2f} s setup, "
                     f"n {cur.n}, {fixed.mean():.3f} of u fixed")
     finally:
+        if hs is not None and hs is not h:
+            hprlp.hpr_destroy(hs)
         if h is not None:
             hprlp.hpr_destroy(h)
     res.col_lo, res.col_hi, res.x = lo, hi, x_full

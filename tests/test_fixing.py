@@ -1,7 +1,7 @@
 """Algorithm 1 (Fixing-Strategy), the Round operator and the LP presolve of the
 successive-fixing loop (Section IV), on hand-worked cases and invariants: the oracle's
-reference (oracle/fixing.py) against the paper's text, and the product's host versions (used
-to synthesise the reduced-LP batches) against the oracle."""
+reference (oracle/fixing.py) against the paper's text, the product's host versions (used to
+build the reduced-LP batches) against the oracle, and the stored fixings of the mixed batch."""
 import json
 import os
 
