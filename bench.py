@@ -146,17 +146,20 @@ def algorithmic_bytes(lp, fp32: bool):
     return primal, dual
 
 
-def layout_bytes(lp, fp32: bool):
+def layout_bytes(lp, fp32: bool, ks=None):
     """Bytes one launch of each fused kernel must move in the layout the library streams (the
     figure the roofline fraction is computed from): every row padded to a multiple of 4 entries,
-    each stored entry a value plus a 16-bit column offset (4-byte index for rows spanning 65,536
-    columns or more), one 16-byte row descriptor per row, and the same vector traffic as
+    each stored entry a value; per quad (4 entries) of a row spanning fewer than 65,536 columns a
+    4-byte packed word (offset of the first entry and three 5-bit gaps), plus the four 16-bit
+    offsets when a gap does not fit (counts of packed quads from the library's kernel stats `ks`;
+    without them every such quad is counted as unpacked, 12 bytes); 4-byte indices for
+    wider rows; one 16-byte row descriptor per row; and the same vector traffic as
     algorithmic_bytes (each gathered entry read once). Returns (primal, dual)."""
     import numpy as np
     sv = 4 if fp32 else 8
     A = lp.to_scipy().tocsr()
 
-    def matrix_bytes(M):
+    def matrix_bytes(M, narrow_quads, packed_quads):
         M = M.tocsr()
         M.sort_indices()
         lens = np.diff(M.indptr)
@@ -167,11 +170,16 @@ def layout_bytes(lp, fp32: bool):
         lo[nz] = M.indices[M.indptr[:-1][nz]]
         hi[nz] = M.indices[M.indptr[1:][nz] - 1]
         wide = (hi - lo) >= 65536
-        return int((padded * (sv + np.where(wide, 4, 2))).sum() + 16 * M.shape[0])
+        narrow = int(padded[~wide].sum()) // 4
+        if narrow_quads != narrow:        # no (or other) counts: every narrow quad unpacked
+            packed_quads = 0
+        idx = 16 * (int(padded[wide].sum()) // 4) + 4 * packed_quads + 12 * (narrow - packed_quads)
+        return int(padded.sum() * sv + idx + 16 * M.shape[0])
 
+    ks = ks or {}
     m, n = lp.m, lp.n
-    dual = matrix_bytes(A) + sv * (5 * m) + sv * n
-    primal = matrix_bytes(A.T) + sv * (7 * n) + sv * m
+    dual = matrix_bytes(A, ks.get("narrow_quads_a"), ks.get("packed_quads_a")) + sv * (5 * m) + sv * n
+    primal = matrix_bytes(A.T, ks.get("narrow_quads_at"), ks.get("packed_quads_at")) + sv * (7 * n) + sv * m
     return primal, dual
 
 
@@ -560,7 +568,7 @@ def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
     """Roofline record of the dominant fused kernel (the slower of the two steps, event-timed):
     the bytes its layout makes it move per launch (layout_bytes) over its average launch time,
     against 8 TB/s; the plain-CSR count (4-byte indices and offsets) beside it."""
-    pb, db = layout_bytes(lp, fp32)
+    pb, db = layout_bytes(lp, fp32, ks)
     pa, da = algorithmic_bytes(lp, fp32)
     tag = "fp32" if fp32 else "fp64"
     if ks["dual_ms"] >= ks["primal_ms"]:
@@ -574,6 +582,8 @@ def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round(other * 1e3, 2),
+                packed_quad_share={"A": round(ks["packed_quads_a"] / max(1, ks["narrow_quads_a"]), 4),
+                                   "At": round(ks["packed_quads_at"] / max(1, ks["narrow_quads_at"]), 4)},
                 plain_csr_bytes_per_launch=int(kalg),
                 plain_csr_gbs=round(kalg / (kms * 1e-3) / 1e9, 1),
                 schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
