@@ -149,17 +149,17 @@ def algorithmic_bytes(lp, fp32: bool):
 def layout_bytes(lp, fp32: bool, ks=None):
     """Bytes one launch of each fused kernel must move in the layout the library streams (the
     figure the roofline fraction is computed from): every row padded to a multiple of 4 entries,
-    each stored entry a value; per quad (4 entries) of a row spanning fewer than 65,536 columns a
-    4-byte packed word (offset of the first entry and three 5-bit gaps), plus the four 16-bit
-    offsets when a gap does not fit (counts of packed quads from the library's kernel stats `ks`;
-    without them every such quad is counted as unpacked, 12 bytes); 4-byte indices for
+    each stored entry a value; per quad (4 entries) of a row spanning fewer than 65,536 columns
+    either its four 16-bit offsets or, when the matrix reads packed words (kernel stats `ks`), a
+    4-byte word (offset of the first entry and three 5-bit gaps) plus the 16-bit offsets of the
+    quads whose gaps do not fit; 4-byte indices for
     wider rows; one 16-byte row descriptor per row; and the same vector traffic as
     algorithmic_bytes (each gathered entry read once). Returns (primal, dual)."""
     import numpy as np
     sv = 4 if fp32 else 8
     A = lp.to_scipy().tocsr()
 
-    def matrix_bytes(M, narrow_quads, packed_quads):
+    def matrix_bytes(M, narrow_quads, packed_quads, used):
         M = M.tocsr()
         M.sort_indices()
         lens = np.diff(M.indptr)
@@ -171,15 +171,19 @@ def layout_bytes(lp, fp32: bool, ks=None):
         hi[nz] = M.indices[M.indptr[1:][nz] - 1]
         wide = (hi - lo) >= 65536
         narrow = int(padded[~wide].sum()) // 4
-        if narrow_quads != narrow:        # no (or other) counts: every narrow quad unpacked
-            packed_quads = 0
-        idx = 16 * (int(padded[wide].sum()) // 4) + 4 * packed_quads + 12 * (narrow - packed_quads)
+        if used and narrow_quads == narrow:
+            narrow_idx = 4 * packed_quads + 12 * (narrow - packed_quads)
+        else:                             # 16-bit offsets only
+            narrow_idx = 8 * narrow
+        idx = 16 * (int(padded[wide].sum()) // 4) + narrow_idx
         return int(padded.sum() * sv + idx + 16 * M.shape[0])
 
     ks = ks or {}
     m, n = lp.m, lp.n
-    dual = matrix_bytes(A, ks.get("narrow_quads_a"), ks.get("packed_quads_a")) + sv * (5 * m) + sv * n
-    primal = matrix_bytes(A.T, ks.get("narrow_quads_at"), ks.get("packed_quads_at")) + sv * (7 * n) + sv * m
+    dual = (matrix_bytes(A, ks.get("narrow_quads_a"), ks.get("packed_quads_a"), ks.get("packed_a"))
+            + sv * (5 * m) + sv * n)
+    primal = (matrix_bytes(A.T, ks.get("narrow_quads_at"), ks.get("packed_quads_at"), ks.get("packed_at"))
+              + sv * (7 * n) + sv * m)
     return primal, dual
 
 
@@ -582,8 +586,9 @@ def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(kname, workload),
                 bytes_per_launch=int(kbytes), launch_us=round(kms * 1e3, 2),
                 other_kernel_us=round(other * 1e3, 2),
-                packed_quad_share={"A": round(ks["packed_quads_a"] / max(1, ks["narrow_quads_a"]), 4),
-                                   "At": round(ks["packed_quads_at"] / max(1, ks["narrow_quads_at"]), 4)},
+                packed_quads={"share_A": round(ks["packed_quads_a"] / max(1, ks["narrow_quads_a"]), 4),
+                              "share_At": round(ks["packed_quads_at"] / max(1, ks["narrow_quads_at"]), 4),
+                              "read_A": ks["packed_a"], "read_At": ks["packed_at"]},
                 plain_csr_bytes_per_launch=int(kalg),
                 plain_csr_gbs=round(kalg / (kms * 1e-3) / 1e9, 1),
                 schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],

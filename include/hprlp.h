@@ -223,6 +223,14 @@ typedef struct {
     double setup_upload_s;      /* ... transfers, FP32 casts, allocation of the iterates */
     double setup_tune_s;        /* ... schedule tuner */
     double setup_power_s;       /* ... power method */
+    int64_t narrow_quads_a;     /* stored quads (4 entries) of A's rows with 16-bit column offsets */
+    int64_t packed_quads_a;     /* ... of which packed into one 32-bit word (16-bit offset of the
+                                   first entry, three 5-bit gaps to the next ones) */
+    int64_t narrow_quads_at;    /* the same for A^T */
+    int64_t packed_quads_at;
+    int32_t packed_a;           /* 1: A's products read the packed words (from 90% packed quads
+                                   on; otherwise the 16-bit offsets only) */
+    int32_t packed_at;
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

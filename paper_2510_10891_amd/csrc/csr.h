@@ -80,6 +80,21 @@ __device__ __forceinline__ int4 load_idx16(const uint16_t* p, int base) {
                      base + (int)(v.y >> 16));
 }
 
+// A packed quad (DevCsr::qpack, bit 31 set): the first entry's 16-bit offset and the three 5-bit
+// gaps to the entries after it.
+__device__ __forceinline__ int4 unpack_quad(uint32_t w, int base) {
+    const int c0 = base + (int)(w & 0xFFFFu);
+    const int c1 = c0 + (int)((w >> 16) & 31u);
+    const int c2 = c1 + (int)((w >> 21) & 31u);
+    return make_int4(c0, c1, c2, c2 + (int)((w >> 26) & 31u));
+}
+
+template <bool NT>
+__device__ __forceinline__ uint32_t load_pack(const uint32_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // Lane moves within rows of 16 lanes (DPP): each lane reads the value of the lane that the
 // control word names (quad permutations, half-row and row mirrors).
 constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
@@ -193,7 +208,9 @@ struct FromOutside {
 // Dot products of stored row [b, e) with one or two gathered vectors. Lane `lane` of a
 // group of G lanes takes quads b + 4*(lane + G*t); each pass issues the loads of U quads
 // before any gather so U 16-byte loads per array are in flight per lane.
-template <int G, int U, bool NT, bool WIDE, int NV, typename Tm, typename S0, typename S1, typename Acc>
+// PK (narrow rows of a matrix that reads packed words): each quad's index comes from its packed
+// word, or from its 16-bit offsets when the word is not packed.
+template <int G, int U, bool NT, bool WIDE, int NV, bool PK, typename Tm, typename S0, typename S1, typename Acc>
 __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_t e, int base, int lane,
                                           const S0& g0, const S1& g1, Acc& s0, Acc& s1) {
     s0 = Acc(0);
@@ -201,13 +218,24 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
     for (int64_t p = b + kVec * lane; p < e; p += (int64_t)kVec * G * U) {
         int4 c[U];
         Quad<Tm> v[U];
+        uint32_t w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t q = p + (int64_t)kVec * G * u;
             if (q < e) {
                 if constexpr (WIDE) c[u] = load_idx<NT>(A.col + q);
+                else if constexpr (PK) w[u] = load_pack<NT>(A.qpack + (q >> 2));
                 else c[u] = load_idx16<NT>(A.col16 + q, base);
                 v[u] = Quad<Tm>::template load<NT>(A.val + q);
+            }
+        }
+        if constexpr (!WIDE && PK) {
+            // a packed quad costs 4 bytes of index stream instead of 8; the others (a gap of 32 or
+            // more) read their 16-bit offsets as well
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = p + (int64_t)kVec * G * u;
+                if (q < e) c[u] = (w[u] >> 31) ? unpack_quad(w[u], base) : load_idx16<NT>(A.col16 + q, base);
             }
         }
 #pragma unroll
@@ -224,6 +252,15 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
         }
     }
 }
+
+// A fused step on a matrix that reads packed words (DevCsr::qpack): the same op, instantiated
+// apart so that matrices without them keep the plain offset path.
+template <typename Base>
+struct Packed : Base {};
+template <typename Op>
+struct PackOf { static constexpr bool value = false; };
+template <typename Base>
+struct PackOf<Packed<Base>> { static constexpr bool value = true; };
 
 // One block: each group of G lanes takes one row of the block's slice of the row list.
 // MODE 0: the gathered vector is read from global memory; 1: from the block's LDS window
@@ -245,15 +282,15 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
         const int64_t e = b + (int64_t)kVec * (rr.quads & ~kWide);
         if constexpr (MODE == 1) {
             const FromWindow<Tx> w{(LdsPtr<Tx>)win};
-            group_dot<G, U, NT, false, 1>(A, b, e, rr.base - d.wlo, lane, w, w, s0, s1);
+            group_dot<G, U, NT, false, 1, PackOf<Op>::value>(A, b, e, rr.base - d.wlo, lane, w, w, s0, s1);
         } else if constexpr (MODE == 2) {
             const FromSplit<Tx> w{(LdsPtr<Tx>)win, op.g0, d.wlo, -d.wlen};
-            if (rr.quads & kWide) group_dot<G, U, NT, true, 1>(A, b, e, rr.base, lane, w, w, s0, s1);
-            else group_dot<G, U, NT, false, 1>(A, b, e, rr.base, lane, w, w, s0, s1);
+            if (rr.quads & kWide) group_dot<G, U, NT, true, 1, false>(A, b, e, rr.base, lane, w, w, s0, s1);
+            else group_dot<G, U, NT, false, 1, PackOf<Op>::value>(A, b, e, rr.base, lane, w, w, s0, s1);
         } else {
             const FromGlobal<Tx> g0{op.g0}, g1{op.g1};
-            if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV>(A, b, e, rr.base, lane, g0, g1, s0, s1);
-            else group_dot<G, U, NT, false, Op::NV>(A, b, e, rr.base, lane, g0, g1, s0, s1);
+            if (rr.quads & kWide) group_dot<G, U, NT, true, Op::NV, false>(A, b, e, rr.base, lane, g0, g1, s0, s1);
+            else group_dot<G, U, NT, false, Op::NV, PackOf<Op>::value>(A, b, e, rr.base, lane, g0, g1, s0, s1);
         }
         s0 = group_sum<G>(s0);
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
@@ -292,8 +329,8 @@ __device__ __forceinline__ void run_bin_sliced(const DevCsr<typename Op::Tm>& A,
             const int qa = cum[k] >> 2, qb = min(quads, (cum[k + 1] + 3) >> 2);
             if (qb > qa) {
                 const FromSlice<Tx> src{(LdsPtr<Tx>)win, lo, len};
-                if (wide) group_dot<G, U, NT, true, 1>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
-                else group_dot<G, U, NT, false, 1>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
+                if (wide) group_dot<G, U, NT, true, 1, false>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
+                else group_dot<G, U, NT, false, 1, PackOf<Op>::value>(A, b + kVec * qa, b + kVec * qb, rr.base, lane, src, src, part, unused);
                 s0 += part;
             }
         }
@@ -302,14 +339,14 @@ __device__ __forceinline__ void run_bin_sliced(const DevCsr<typename Op::Tm>& A,
         const FromOutside<Tx> src{op.g0, d.wlo, d.wlo + d.ns * W};
         const int q_low = min(quads, (cum[0] + 3) >> 2), q_high = cum[d.ns] >> 2;
         if (q_low > 0) {
-            if (wide) group_dot<G, U, NT, true, 1>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
-            else group_dot<G, U, NT, false, 1>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
+            if (wide) group_dot<G, U, NT, true, 1, false>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
+            else group_dot<G, U, NT, false, 1, PackOf<Op>::value>(A, b, b + kVec * q_low, rr.base, lane, src, src, part, unused);
             s0 += part;
         }
         if (q_high < quads) {
             const int qa = max(q_high, q_low);   // a quad below every window is not read twice
-            if (wide) group_dot<G, U, NT, true, 1>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
-            else group_dot<G, U, NT, false, 1>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
+            if (wide) group_dot<G, U, NT, true, 1, false>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
+            else group_dot<G, U, NT, false, 1, PackOf<Op>::value>(A, b + kVec * qa, b + kVec * quads, rr.base, lane, src, src, part, unused);
             s0 += part;
         }
     }
@@ -432,6 +469,12 @@ static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream
     if constexpr (Op::NV == 0) {   // no matrix stream: one variant serves every schedule
         launch_csr_kernel<Op, 1, false, false>(A, op, st, start, stop);
         return;
+    }
+    if constexpr (Op::STREAM && !PackOf<Op>::value) {   // the fused steps read packed words when there are
+        if (A.qpack) {                                    // any (other ops read the 16-bit offsets)
+            launch_csr(A, Packed<Op>{op}, st, start, stop);
+            return;
+        }
     }
     if (A.nontemporal && Op::STREAM) {
         switch (A.unroll) {

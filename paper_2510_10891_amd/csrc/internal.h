@@ -67,6 +67,10 @@ template <typename Tm>
 struct DevCsr {
     const int32_t* col;        // [padded nnz] 32-bit column indices
     const uint16_t* col16;     // [padded nnz] column - row base (narrow rows)
+    const uint32_t* qpack;     // [padded nnz / 4] per quad of a narrow row: bit 31 set = packed
+                               // (bits 0-15 first offset, 16-20 / 21-25 / 26-30 the gaps to the
+                               // second, third and fourth entry); clear = read col16. Null: the
+                               // matrix reads col16 only (too few quads pack)
     const Tm* val;             // [padded nnz]
     const RowRef* rows;        // row list in schedule order
     const BlockDesc* sched;    // [nblocks]
@@ -240,5 +244,10 @@ hipError_t device_setup(const DevSetupIn& in, DevSetupOut& out, hipStream_t st);
 // FP64 -> T copy
 template <typename T>
 void launch_cast(const double* src, T* dst, int64_t n, hipStream_t st);
+
+// qpack of a layout (DevCsr::qpack) from its 16-bit offsets, row starts and wide-row flags;
+// count[0] and count[1] (device, zeroed by the caller) receive the narrow and packed quads.
+void launch_pack_quads(const uint16_t* col16, const int64_t* start, const uint8_t* wide, int32_t rows,
+                       int64_t nquads, uint32_t* qpack, unsigned long long* count, hipStream_t st);
 
 }  // namespace hpr

@@ -361,6 +361,53 @@ void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, co
     hipLaunchKernelGGL(seg_scale_kernel, dim3(max_chunks, nlp), dim3(kBlock), 0, st, v, seg, factor);
 }
 
+// Packed quads: quad q (entries 4q..4q+3) of a narrow row, whose entries are in column order,
+// gets bit 31, its first 16-bit offset and the three gaps to the next entries when each gap is
+// below 32; quads of wide rows and quads with a larger gap get 0 (read from col16). The row of a
+// quad is found by bisection of the row starts. count[0] += narrow quads, count[1] += packed.
+__global__ __launch_bounds__(kBlock) void pack_quads_kernel(const uint16_t* col16, const int64_t* start,
+                                                            const uint8_t* wide, int32_t rows, int64_t nquads,
+                                                            uint32_t* qpack, unsigned long long* count) {
+    __shared__ unsigned n_narrow, n_packed;
+    if (threadIdx.x == 0) n_narrow = n_packed = 0;
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned narrow = 0, packed = 0;
+    if (q < nquads) {
+        const int64_t k = 4 * q;
+        int32_t lo = 0, hi = rows - 1;                 // last row with start <= k
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo + 1) / 2;
+            if (start[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        uint32_t w = 0;
+        if (!wide[lo] && k < start[lo + 1]) {
+            narrow = 1;
+            const uint32_t c0 = col16[k], c1 = col16[k + 1], c2 = col16[k + 2], c3 = col16[k + 3];
+            if (c1 >= c0 && c2 >= c1 && c3 >= c2 && c1 - c0 < 32u && c2 - c1 < 32u && c3 - c2 < 32u) {
+                w = 0x80000000u | c0 | ((c1 - c0) << 16) | ((c2 - c1) << 21) | ((c3 - c2) << 26);
+                packed = 1;
+            }
+        }
+        qpack[q] = w;
+    }
+    if (narrow) atomicAdd(&n_narrow, narrow);
+    if (packed) atomicAdd(&n_packed, packed);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (n_narrow) atomicAdd(count, (unsigned long long)n_narrow);
+        if (n_packed) atomicAdd(count + 1, (unsigned long long)n_packed);
+    }
+}
+
+void launch_pack_quads(const uint16_t* col16, const int64_t* start, const uint8_t* wide, int32_t rows,
+                       int64_t nquads, uint32_t* qpack, unsigned long long* count, hipStream_t st) {
+    if (nquads <= 0 || rows <= 0) return;
+    hipLaunchKernelGGL(pack_quads_kernel, dim3((unsigned)((nquads + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       col16, start, wide, rows, nquads, qpack, count);
+}
+
 // ---------------------------------------------------------------- instantiations
 
 #define HPR_INST(T)                                                                                          \

@@ -728,7 +728,9 @@ static int slice_cap_of(int mode) { return mode == 4 ? 4 : (mode == 5 ? 3 : -1);
 static int lane_cap_of(int mode) { return mode == 6 ? 4 : (mode == 7 ? 3 : -1); }
 
 struct DevMatrix {
-    DBuf start, col, col16, rows, sched, seg, val64, val32, slice_cum;
+    DBuf start, col, col16, qpack, rows, sched, seg, val64, val32, slice_cum;
+    int64_t narrow_quads = 0, packed_quads = 0;  // quads of 16-bit-offset rows, and those packed
+    bool use_pack = false;                       // the products read the packed words
     DBuf sched_act, seg_act;                 // compacted schedule: the blocks of running LPs only
     std::vector<int64_t> start_h, lp_rows;   // host copies for rescheduling
     std::vector<int32_t> base_h, top_h;
@@ -767,7 +769,7 @@ struct DevMatrix {
         upload(start, L.start, st);
         upload(col, L.col, st);
         upload(col16, c16, st);
-        sync_stream(st);
+        pack(st);
         HostVec<uint16_t>().swap(c16);
         upload(val64, L.val, st);
         if (fp32) {
@@ -819,7 +821,30 @@ struct DevMatrix {
         take(col16, L.col16);
         take(val64, L.val64);
         if (fp32) take(val32, L.val32);
+        pack(st);
         set_unroll(4, st);
+    }
+    // qpack from col16 (start, col16 and wide_h in place); waits for the stream
+    void pack(hipStream_t st) {
+        const int64_t nq = padded / kVec;
+        qpack.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nq, 1));
+        DBuf wd, cnt;
+        upload(wd, wide_h, st);
+        cnt.alloc(2 * sizeof(unsigned long long));
+        HIP_OK(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), st));
+        launch_pack_quads(col16.as<uint16_t>(), start.as<int64_t>(), wd.as<uint8_t>(), nrows, nq,
+                          qpack.as<uint32_t>(), static_cast<unsigned long long*>(cnt.p), st);
+        HIP_OK(hipGetLastError());
+        unsigned long long h[2] = {0, 0};
+        HIP_OK(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, st));
+        sync_stream(st);
+        narrow_quads = (int64_t)h[0];
+        packed_quads = (int64_t)h[1];
+        // an unpacked quad costs its packed word and its 16-bit offsets (12 bytes instead of 8)
+        // and a dependent load: measured, 82% packed quads made the 13,500-bus dual step slower
+        // and 98% made the 2,000-bus one faster, so the words are read only from 90% on
+        use_pack = narrow_quads > 0 && packed_quads >= 0.9 * (double)narrow_quads;
+        if (!use_pack) qpack.release();
     }
     void count_tiles(const Layout& L, int32_t tile, int threads) {
         // rows are in column order: a row's tiles are runs of equal col / tile; counted first,
@@ -944,6 +969,7 @@ struct DevMatrix {
         DevCsr<T> d;
         d.col = col.as<int32_t>();
         d.col16 = col16.as<uint16_t>();
+        d.qpack = use_pack ? qpack.as<uint32_t>() : nullptr;
         d.val = std::is_same<T, float>::value ? (const T*)val32.p : (const T*)val64.p;
         d.rows = rows.as<RowRef>();
         d.sched = use_act ? sched_act.as<BlockDesc>() : sched.as<BlockDesc>();
@@ -2139,6 +2165,12 @@ static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     out->setup_power_s = e->t_power;
     e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->sliced_blocks_a, out->blocks_a);
     e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->sliced_blocks_at, out->blocks_at);
+    out->narrow_quads_a = e->A.narrow_quads;
+    out->packed_quads_a = e->A.packed_quads;
+    out->narrow_quads_at = e->At.narrow_quads;
+    out->packed_quads_at = e->At.packed_quads;
+    out->packed_a = e->A.use_pack ? 1 : 0;
+    out->packed_at = e->At.use_pack ? 1 : 0;
     if (out->samples > 0) {
         out->primal_ms /= (double)out->samples;
         out->dual_ms /= (double)out->samples;

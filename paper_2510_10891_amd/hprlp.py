@@ -55,7 +55,9 @@ class hpr_kernel_stats(C.Structure):
                 ("full_blocks_at", C.c_int32), ("split_blocks_at", C.c_int32), ("blocks_a", C.c_int32),
                 ("blocks_at", C.c_int32), ("sliced_blocks_a", C.c_int32), ("sliced_blocks_at", C.c_int32),
                 ("setup_prep_s", C.c_double), ("setup_upload_s", C.c_double), ("setup_tune_s", C.c_double),
-                ("setup_power_s", C.c_double)]
+                ("setup_power_s", C.c_double), ("narrow_quads_a", C.c_int64), ("packed_quads_a", C.c_int64),
+                ("narrow_quads_at", C.c_int64), ("packed_quads_at", C.c_int64), ("packed_a", C.c_int32),
+                ("packed_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -140,7 +142,10 @@ def _kstats(s: hpr_kernel_stats) -> dict:
                 split_blocks_at=s.split_blocks_at, blocks_a=s.blocks_a, blocks_at=s.blocks_at,
                 sliced_blocks_a=s.sliced_blocks_a, sliced_blocks_at=s.sliced_blocks_at,
                 setup_phases_s=dict(prep=round(s.setup_prep_s, 4), upload=round(s.setup_upload_s, 4),
-                                    tune=round(s.setup_tune_s, 4), power=round(s.setup_power_s, 4)))
+                                    tune=round(s.setup_tune_s, 4), power=round(s.setup_power_s, 4)),
+                narrow_quads_a=s.narrow_quads_a, packed_quads_a=s.packed_quads_a,
+                narrow_quads_at=s.narrow_quads_at, packed_quads_at=s.packed_quads_at,
+                packed_a=s.packed_a, packed_at=s.packed_at)
 
 
 def hpr_default_opts() -> hpr_opts:

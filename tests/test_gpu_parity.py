@@ -300,6 +300,31 @@ def test_lane_capped_window_modes_match_oracle(mode):
     assert_parity(o, info, x, y, z, FP64_RTOL)
 
 
+def test_packed_quads_cover_both_index_paths():
+    """Quads of narrow rows whose gaps fit 5 bits can be read as one packed word, the others
+    through their 16-bit offsets as well; a matrix reads the packed words only from 90% packed
+    quads on. The 2,000-bus matrices pack ~98% (their parity and bitwise-mode tests above run on
+    packed words with the 2% read through offsets); a ragged LP packs some quads, stays below the
+    threshold and reads offsets only, and matches the oracle too."""
+    _, lp = scuc.make_instance("medium", 0)
+    h = hprlp.hpr_create(lp, hprlp.Options(max_iter=1))
+    try:
+        ks = hprlp.hpr_get_kernel_stats(h)
+    finally:
+        hprlp.hpr_destroy(h)
+    for side in ("a", "at"):
+        assert ks[f"packed_quads_{side}"] >= 0.95 * ks[f"narrow_quads_{side}"] > 0
+        assert ks[f"packed_{side}"] == 1
+    lp = ragged_lp(2)
+    K = 65
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, lambda_in=1.0))
+    info, x, y, z, ks = _run_mode(lp, K, 0, hprlp.HPR_FP64)
+    for side in ("a", "at"):
+        assert 0 < ks[f"packed_quads_{side}"] < ks[f"narrow_quads_{side}"]
+        assert ks[f"packed_{side}"] == int(ks[f"packed_quads_{side}"] >= 0.9 * ks[f"narrow_quads_{side}"])
+    assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 3])
 def test_rows_given_out_of_column_order(mode):
     """CSR rows whose entries are not in column order (allowed by the interface) are stored in
