@@ -80,7 +80,7 @@ def write_traffic_record(fetch_dir, write_dir, kernel="dual_step_fp32", workload
         return rows
 
     def solve_mean(rows):
-        mine = [r for r in rows if r[1].startswith(f"csr_kernel<{op}")][-64:]
+        mine = [r for r in rows if r[1].startswith((f"csr_kernel<{op}", f"csr_kernel<Packed<{op}"))][-64:]
         names = sorted({r[1] for r in mine})
         return sum(r[2] for r in mine) / len(mine), names, len(mine)
 
