@@ -89,6 +89,7 @@ def write_traffic_record(fetch_dir, write_dir, kernel="dual_step_fp32", workload
         return sum(v) / len(v)
 
     fr, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    fetch_dir, write_dir = (os.path.relpath(os.path.abspath(d), ROOT) for d in (fetch_dir, write_dir))
     known = float(1 << 20)   # KiB in 1 GiB
     cfk, cwk = copy_mean(fr), copy_mean(wr)
     cf, cw = known / cfk, known / cwk
@@ -101,12 +102,13 @@ def write_traffic_record(fetch_dir, write_dir, kernel="dual_step_fp32", workload
 Kernel: `csr_kernel<{op}, ...>`, one launch = one {what}; the solve's last {fn} / {wn} launches in the
 FETCH / WRITE runs (variants {", ".join(f"`{x}`" for x in fnames)} / {", ".join(f"`{x}`" for x in wnames)}).
 
-Commands (repository root on the GPU machine; each counter in a run of its own, then this record):
+Commands (R = the repository root; each counter in a run of its own, then this record from the
+repository root):
 
 ```
-cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_fetch -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
-cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $GRAFT_REPO_ROOT/gpurun_out/pmc_write -o run -- python3 $GRAFT_REPO_ROOT/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
-python bench.py --traffic-record gpurun_out/pmc_fetch gpurun_out/pmc_write --traffic-kernel {kernel} --config {config}
+cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/{fetch_dir} -o run -- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
+cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/{write_dir} -o run -- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --batch 0 --successive 0 --large-steps 0 --max-iter 129 --precision fp32 --config {config}
+python bench.py --traffic-record {fetch_dir} {write_dir} --traffic-kernel {kernel} --config {config}
 ```
 
 Calibration: the stream probe's copy kernel reads and writes 1,048,576 KiB per dispatch; FETCH_SIZE

@@ -54,7 +54,7 @@ def test_learned_warm_start_against_cold_start():
                    gen_loss=[float(np.mean(lg[:5])), float(np.mean(lg[-50:]))],
                    line_loss=[float(np.mean(ll[:5])), float(np.mean(ll[-50:]))])
     print(json.dumps(summary))
-    out = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("HPR_TEST_OUTPUT_DIR")   # optional: where to keep the per-LP record
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "warmstart_eval.json"), "w") as f:
             json.dump(summary, f, indent=1)
