@@ -16,7 +16,6 @@ from paper_2510_10891_amd import fixing, hprlp, warmstart
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _train_lps(n):
