@@ -141,7 +141,9 @@ typedef struct {
                                    iterations with HIP events (hpr_get_kernel_stats) */
     int32_t unroll;             /* quads (4 entries) per lane and pass in the matrix products:
                                    1, 2, 4 or 8; 0 (default) = pick per matrix by timing at
-                                   hpr_create (U = 1, 2, 4; ordinary or non-temporal loads).
+                                   hpr_create (U = 1, 2, 4; ordinary or non-temporal loads),
+                                   or reuse the pick made earlier in the process for a matrix of
+                                   the same coarse signature (size and row-length profile).
                                    The choice fixes the summation order. */
     int32_t lds_windows;        /* LDS windows of the gathered vector in the matrix products:
                                    0 = none; 1 = "full" windows only (a block whose rows use at

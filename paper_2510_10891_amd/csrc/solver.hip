@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -20,10 +21,13 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include <sys/mman.h>
@@ -1149,9 +1153,49 @@ static void put_ctrl(Engine* e) {
     e->sync();
 }
 
+// Choices of the schedule tuner, kept for the life of the process and keyed by a coarse signature
+// of the matrix (which step streams it, value width, window size, whether it reads packed words,
+// its stored entries and rows on a 1/8-octave grid, and the share of its entries in rows of each
+// length class to 1%): the LPs of successive-fixing rounds and of a batch's members repeat such
+// signatures, and re-timing them would cost a tenth of a second per handle.
+struct TuneKey {
+    int32_t which, vbytes, win, pack, entries_q, rows_q;
+    std::array<int16_t, 12> share;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(which, vbytes, win, pack, entries_q, rows_q, share) <
+               std::tie(o.which, o.vbytes, o.win, o.pack, o.entries_q, o.rows_q, o.share);
+    }
+};
+struct TuneChoice {
+    int32_t U, mode, nt;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneChoice> g_tune_cache;
+
+static TuneKey tune_key(const DevMatrix& M, int which, int vbytes) {
+    TuneKey k{};
+    k.which = which;
+    k.vbytes = vbytes;
+    k.win = M.win_max;
+    k.pack = M.use_pack ? 1 : 0;
+    k.entries_q = (int32_t)std::lround(8.0 * std::log2(1.0 + (double)M.padded));
+    k.rows_q = (int32_t)std::lround(8.0 * std::log2(1.0 + (double)M.nrows));
+    std::array<int64_t, 12> ent{};
+    for (int32_t i = 0; i < M.nrows; ++i) {
+        const int64_t quads = (M.start_h[i + 1] - M.start_h[i]) / kVec;
+        int b = 0;
+        while (b < 10 && (int64_t(1) << b) < quads) ++b;
+        ent[M.wide_h[i] ? 11 : b] += quads;
+    }
+    const double tot = std::max<double>(1.0, (double)(M.padded / kVec));
+    for (int b = 0; b < 12; ++b) k.share[b] = (int16_t)std::lround(100.0 * (double)ent[b] / tot);
+    return k;
+}
+
 // Schedule tuner: for each pooled matrix, time the fused step kernel that streams it (dual
 // step for A~, primal step for A~^T) with U = 1, 2, 4 quads per lane and pass, then the best U
-// with ordinary and with non-temporal loads of the matrix, and keep the fastest. A forced
+// with ordinary and with non-temporal loads of the matrix, and keep the fastest (or take the
+// choice made for a matrix of the same signature earlier in the process). A forced
 // opts.unroll skips all timing (ordinary loads), so two engines with the same forced options
 // run the same schedule (same summation order, bitwise equal results).
 template <typename T>
@@ -1184,6 +1228,23 @@ static void autotune(Engine* e) {
             Mx.drop_built();
             continue;
         }
+        const bool tune_split = e->opts.lds_windows < 0;
+        const TuneKey key = tune_key(Mx, which, (int)sizeof(T));
+        if (tune_split) {
+            TuneChoice hit{0, 0, 0};
+            {
+                std::lock_guard<std::mutex> lock(g_tune_mu);
+                const auto it = g_tune_cache.find(key);
+                if (it != g_tune_cache.end()) hit = it->second;
+            }
+            if (hit.U) {
+                Mx.win_mode = hit.mode;
+                Mx.set_unroll(hit.U, st);
+                Mx.nontemporal = hit.nt;
+                Mx.drop_built();
+                continue;
+            }
+        }
         auto time_it = [&]() {
             const DevCsr<T> view = Mx.view<T>();
             auto launch = [&]() {
@@ -1202,7 +1263,6 @@ static void autotune(Engine* e) {
         // candidates (U, and split windows on/off when the option leaves that open) timed in
         // interleaved rounds, each keeping its fastest round, so that a clock ramp during the
         // first rounds does not favour the later candidates
-        const bool tune_split = e->opts.lds_windows < 0;
         struct Cand {
             int U, mode;
             float ms;
@@ -1264,6 +1324,10 @@ static void autotune(Engine* e) {
             ms_nt = std::min(ms_nt, time_it());
         }
         Mx.nontemporal = ms_nt < ms_plain ? 1 : 0;
+        if (tune_split) {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune_cache[key] = TuneChoice{best->U, best->mode, Mx.nontemporal};
+        }
         Mx.drop_built();
     }
     (void)hipEventDestroy(e0);

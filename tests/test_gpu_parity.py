@@ -534,3 +534,25 @@ def test_create_from_device_arrays_matches_host_arrays():
     assert np.array_equal(x, x2) and np.array_equal(y, y2) and np.array_equal(z, z2)
     with pytest.raises(ValueError):
         hprlp.DeviceLP(lp.m, lp.n, arrays[0].to(torch.int32), *arrays[1:], lp.obj_offset)
+
+
+def test_tuner_choice_is_reused_for_a_matrix_of_the_same_signature():
+    """The schedule tuner's pick (U, window mode, load kind) is kept per coarse matrix signature:
+    a second handle of the same LP takes it without timing anything, and solves bit for bit as
+    the first."""
+    lp = ragged_lp(123, m=700, n=1500)
+    runs = []
+    for _ in range(2):
+        h = hprlp.hpr_create(lp, hprlp.Options(tol=0.0, max_iter=65))
+        try:
+            info = hprlp.hpr_solve(h)
+            x, y, z = hprlp.hpr_get_solution(h)
+            runs.append((info, x, y, hprlp.hpr_get_kernel_stats(h)))
+        finally:
+            hprlp.hpr_destroy(h)
+    (i1, x1, y1, k1), (i2, x2, y2, k2) = runs
+    assert k2["setup_phases_s"]["tune"] < k1["setup_phases_s"]["tune"]
+    for key in ("unroll_a", "unroll_at", "nt_a", "nt_at", "full_blocks_a", "split_blocks_a", "sliced_blocks_a",
+                "full_blocks_at", "split_blocks_at", "sliced_blocks_at"):
+        assert k1[key] == k2[key], key
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
