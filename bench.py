@@ -153,7 +153,7 @@ def layout_bytes(lp, fp32: bool, ks=None):
     figure the roofline fraction is computed from): every row padded to a multiple of 4 entries,
     each stored entry a value; per quad (4 entries) of a row spanning fewer than 65,536 columns
     either its four 16-bit offsets or, when the matrix reads packed words (kernel stats `ks`), a
-    4-byte word (offset of the first entry and three 5-bit gaps) plus the 16-bit offsets of the
+    4-byte word (13-bit offset of the first entry and three 6-bit gaps) plus the 16-bit offsets of the
     quads whose gaps do not fit; 4-byte indices for
     wider rows; one 16-byte row descriptor per row; and the same vector traffic as
     algorithmic_bytes (each gathered entry read once). Returns (primal, dual)."""

@@ -226,8 +226,8 @@ typedef struct {
     double setup_tune_s;        /* ... schedule tuner */
     double setup_power_s;       /* ... power method */
     int64_t narrow_quads_a;     /* stored quads (4 entries) of A's rows with 16-bit column offsets */
-    int64_t packed_quads_a;     /* ... of which packed into one 32-bit word (16-bit offset of the
-                                   first entry, three 5-bit gaps to the next ones) */
+    int64_t packed_quads_a;     /* ... of which packed into one 32-bit word (13-bit offset of the
+                                   first entry, three 6-bit gaps to the next ones) */
     int64_t narrow_quads_at;    /* the same for A^T */
     int64_t packed_quads_at;
     int32_t packed_a;           /* 1: A's products read the packed words (from 90% packed quads

@@ -80,13 +80,13 @@ __device__ __forceinline__ int4 load_idx16(const uint16_t* p, int base) {
                      base + (int)(v.y >> 16));
 }
 
-// A packed quad (DevCsr::qpack, bit 31 set): the first entry's 16-bit offset and the three 5-bit
+// A packed quad (DevCsr::qpack, bit 31 set): the first entry's 13-bit offset and the three 6-bit
 // gaps to the entries after it.
 __device__ __forceinline__ int4 unpack_quad(uint32_t w, int base) {
-    const int c0 = base + (int)(w & 0xFFFFu);
-    const int c1 = c0 + (int)((w >> 16) & 31u);
-    const int c2 = c1 + (int)((w >> 21) & 31u);
-    return make_int4(c0, c1, c2, c2 + (int)((w >> 26) & 31u));
+    const int c0 = base + (int)(w & 0x1FFFu);
+    const int c1 = c0 + (int)((w >> 13) & 63u);
+    const int c2 = c1 + (int)((w >> 19) & 63u);
+    return make_int4(c0, c1, c2, c2 + (int)((w >> 25) & 63u));
 }
 
 template <bool NT>
@@ -230,8 +230,8 @@ __device__ __forceinline__ void group_dot(const DevCsr<Tm>& A, int64_t b, int64_
             }
         }
         if constexpr (!WIDE && PK) {
-            // a packed quad costs 4 bytes of index stream instead of 8; the others (a gap of 32 or
-            // more) read their 16-bit offsets as well
+            // a packed quad costs 4 bytes of index stream instead of 8; the others (an offset of
+            // 8192 or more, or a gap of 64 or more) read their 16-bit offsets as well
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t q = p + (int64_t)kVec * G * u;

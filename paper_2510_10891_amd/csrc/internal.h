@@ -68,7 +68,7 @@ struct DevCsr {
     const int32_t* col;        // [padded nnz] 32-bit column indices
     const uint16_t* col16;     // [padded nnz] column - row base (narrow rows)
     const uint32_t* qpack;     // [padded nnz / 4] per quad of a narrow row: bit 31 set = packed
-                               // (bits 0-15 first offset, 16-20 / 21-25 / 26-30 the gaps to the
+                               // (bits 0-12 first offset, 13-18 / 19-24 / 25-30 the gaps to the
                                // second, third and fourth entry); clear = read col16. Null: the
                                // matrix reads col16 only (too few quads pack)
     const Tm* val;             // [padded nnz]

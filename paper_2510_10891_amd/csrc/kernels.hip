@@ -362,9 +362,9 @@ void launch_seg_scale(double* v, const int64_t* seg, int nlp, int max_chunks, co
 }
 
 // Packed quads: quad q (entries 4q..4q+3) of a narrow row, whose entries are in column order,
-// gets bit 31, its first 16-bit offset and the three gaps to the next entries when each gap is
-// below 32; quads of wide rows and quads with a larger gap get 0 (read from col16). The row of a
-// quad is found by bisection of the row starts. count[0] += narrow quads, count[1] += packed.
+// gets bit 31, its first offset (13 bits) and the three gaps to the next entries (6 bits each)
+// when they fit; quads of wide rows and the others get 0 (read from col16). The row of a quad is
+// found by bisection of the row starts. count[0] += narrow quads, count[1] += packed.
 __global__ __launch_bounds__(kBlock) void pack_quads_kernel(const uint16_t* col16, const int64_t* start,
                                                             const uint8_t* wide, int32_t rows, int64_t nquads,
                                                             uint32_t* qpack, unsigned long long* count) {
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(kBlock) void pack_quads_kernel(const uint16_t* col1
         if (!wide[lo] && k < start[lo + 1]) {
             narrow = 1;
             const uint32_t c0 = col16[k], c1 = col16[k + 1], c2 = col16[k + 2], c3 = col16[k + 3];
-            if (c1 >= c0 && c2 >= c1 && c3 >= c2 && c1 - c0 < 32u && c2 - c1 < 32u && c3 - c2 < 32u) {
-                w = 0x80000000u | c0 | ((c1 - c0) << 16) | ((c2 - c1) << 21) | ((c3 - c2) << 26);
+            if (c0 < 8192u && c1 >= c0 && c2 >= c1 && c3 >= c2 && c1 - c0 < 64u && c2 - c1 < 64u && c3 - c2 < 64u) {
+                w = 0x80000000u | c0 | ((c1 - c0) << 13) | ((c2 - c1) << 19) | ((c3 - c2) << 25);
                 packed = 1;
             }
         }

@@ -846,7 +846,7 @@ struct DevMatrix {
         packed_quads = (int64_t)h[1];
         // an unpacked quad costs its packed word and its 16-bit offsets (12 bytes instead of 8)
         // and a dependent load: measured, 82% packed quads made the 13,500-bus dual step slower
-        // and 98% made the 2,000-bus one faster, so the words are read only from 90% on
+        // (5-bit gaps) and 98% made the 2,000-bus one faster, so the words are read only from 90% on
         use_pack = narrow_quads > 0 && packed_quads >= 0.9 * (double)narrow_quads;
         if (!use_pack) qpack.release();
     }

@@ -301,9 +301,9 @@ def test_lane_capped_window_modes_match_oracle(mode):
 
 
 def test_packed_quads_cover_both_index_paths():
-    """Quads of narrow rows whose gaps fit 5 bits can be read as one packed word, the others
-    through their 16-bit offsets as well; a matrix reads the packed words only from 90% packed
-    quads on. The 2,000-bus matrices pack ~98% (their parity and bitwise-mode tests above run on
+    """Quads of narrow rows whose first offset fits 13 bits and gaps 6 bits can be read as one
+    packed word, the others through their 16-bit offsets as well; a matrix reads the packed words
+    only from 90% packed quads on. The 2,000-bus matrices pack ~98% (their parity and bitwise-mode tests above run on
     packed words with the 2% read through offsets); a ragged LP packs some quads, stays below the
     threshold and reads offsets only, and matches the oracle too."""
     _, lp = scuc.make_instance("medium", 0)
