@@ -47,11 +47,13 @@ KERNEL_SOURCES = ("csr.h", "kernels_dual32.hip", "kernels_primal32.hip", "solver
 
 def sources_sha256():
     """SHA-256 of the sources that decide what the fused FP32 steps move: the kernel template,
-    their instantiations and the runtime that builds the layouts and schedules."""
+    their instantiations, the runtime that builds the layouts and schedules, and the instance
+    generator (its row and column order shapes the layouts)."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2510_10891_amd", "csrc", name), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2510_10891_amd", "scuc.py"), "rb").read())
     return h.hexdigest()
 
 
@@ -120,7 +122,7 @@ reports {cfk:,.1f} KiB for it (factor {cf:.4f}), WRITE_SIZE {cwk:,.1f} KiB (fact
 | WRITE_SIZE | {wk:,.1f} | {wk * cw * 1024:,.0f} |
 
 traffic_bytes_per_launch: {traffic:.0f}
-sources_sha256: {sources_sha256()}   (SHA-256 of {", ".join(KERNEL_SOURCES)} under paper_2510_10891_amd/csrc, in that order)
+sources_sha256: {sources_sha256()}   (SHA-256 of {", ".join(KERNEL_SOURCES)} under paper_2510_10891_amd/csrc, in that order, then paper_2510_10891_amd/scuc.py)
 """
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     with open(path, "w") as fh:

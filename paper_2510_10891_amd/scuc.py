@@ -357,9 +357,12 @@ def _status_rows(add, data: SCUCData, t: int, nrow: int, lo, hi, kind, KIND) -> 
 def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
     """Assemble the LP relaxation (rows hour by hour) from generated data.
 
-    Rows of hour t, in order: balance; security (ranged); per generator: p - p_min u >= 0,
-    p - p_max u <= 0, ramp up / ramp down (t >= 2), logic u_t - u_{t-1} - v_t + w_t = 0
-    (u_0 = 1 at t = 1), v_t + w_t <= 1, min-up window, min-down window.
+    Rows of hour t, in order: balance; per generator: ramp up / ramp down (t >= 2),
+    p - p_min u >= 0, p - p_max u <= 0, logic u_t - u_{t-1} - v_t + w_t = 0 (u_0 = 1 at t = 1),
+    v_t + w_t <= 1, min-up window, min-down window; security (ranged) last. A unit's output column
+    of hour t then meets rows from the start of hour t's block to the ramp rows near the start of
+    hour t + 1's, so its column of A spans about one hour of rows (with the security rows first
+    it spanned into the next hour's security block).
     With ``instance_scaling`` the production data are divided by eta^P = max p_max and
     costs scaled by eta^P/eta^C (production) and 1/eta^C (start-up), eta^C = max cost.
     """
@@ -401,16 +404,6 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
         hi_parts.append(np.array([dem[t]]))
         row_kind_parts.append(np.array([KIND["balance"]], np.int8))
         row_sec_parts.append(np.array([-1], np.int32))
-        # security (ranged rows)
-        if S:
-            ptr_parts.append(np.diff(sec_ptr))
-            col_parts.append(col_index(G, t, P, sec_gen).astype(np.int32))
-            val_parts.append(sec_val)
-            mid = data.sec_const * data.demand[t] / eta_p
-            lo_parts.append(mid - F)
-            hi_parts.append(mid + F)
-            row_kind_parts.append(np.full(S, KIND["security"], np.int8))
-            row_sec_parts.append(np.arange(S, dtype=np.int32))
         # generator rows, assembled as COO then sorted into CSR
         r_list, c_list, v_list, lo, hi, kind = [], [], [], [], [], []
         nrow = 0
@@ -420,18 +413,6 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
             c_list.append(cols)
             v_list.append(vals)
 
-        # p - pmin u >= 0
-        rr = nrow + g
-        add(rr, col_index(G, t, P, g), np.ones(G))
-        add(rr, col_index(G, t, U, g), -pmin)
-        lo.append(np.zeros(G)); hi.append(np.full(G, inf)); kind.append(np.full(G, KIND["lim_lo"]))
-        nrow += G
-        # p - pmax u <= 0
-        rr = nrow + g
-        add(rr, col_index(G, t, P, g), np.ones(G))
-        add(rr, col_index(G, t, U, g), -pmax)
-        lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["lim_hi"]))
-        nrow += G
         if t >= 1:
             # p_t - p_{t-1} - RU u_{t-1} - SU v_t <= 0
             rr = nrow + g
@@ -449,6 +430,18 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
             add(rr, col_index(G, t, W, g), -su)
             lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["ramp_dn"]))
             nrow += G
+        # p - pmin u >= 0
+        rr = nrow + g
+        add(rr, col_index(G, t, P, g), np.ones(G))
+        add(rr, col_index(G, t, U, g), -pmin)
+        lo.append(np.zeros(G)); hi.append(np.full(G, inf)); kind.append(np.full(G, KIND["lim_lo"]))
+        nrow += G
+        # p - pmax u <= 0
+        rr = nrow + g
+        add(rr, col_index(G, t, P, g), np.ones(G))
+        add(rr, col_index(G, t, U, g), -pmax)
+        lo.append(np.full(G, -inf)); hi.append(np.zeros(G)); kind.append(np.full(G, KIND["lim_hi"]))
+        nrow += G
         nrow = _status_rows(add, data, t, nrow, lo, hi, kind, KIND)
 
         bptr, bcol, bval = _csr_from_coo(nrow, np.concatenate(r_list), np.concatenate(c_list),
@@ -460,6 +453,16 @@ def build_lp(data: SCUCData, instance_scaling: bool = True) -> LP:
         hi_parts.append(np.concatenate(hi))
         row_kind_parts.append(np.concatenate(kind).astype(np.int8))
         row_sec_parts.append(np.full(nrow, -1, np.int32))
+        # security (ranged rows)
+        if S:
+            ptr_parts.append(np.diff(sec_ptr))
+            col_parts.append(col_index(G, t, P, sec_gen).astype(np.int32))
+            val_parts.append(sec_val)
+            mid = data.sec_const * data.demand[t] / eta_p
+            lo_parts.append(mid - F)
+            hi_parts.append(mid + F)
+            row_kind_parts.append(np.full(S, KIND["security"], np.int8))
+            row_sec_parts.append(np.arange(S, dtype=np.int32))
         row_hour_parts.append(np.full(1 + S + nrow, t, np.int16))
 
     lens = np.concatenate(ptr_parts)

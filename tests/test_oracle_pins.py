@@ -236,13 +236,15 @@ def test_power_method_lambda_matches_eigvalsh(small_instances):
     top = np.linalg.eigvalsh(As @ As.T).max()
     assert top <= 1.0 + 1e-12           # Pock-Chambolle (alpha = 1) bounds ||A~|| by 1
     assert lam >= top * (1 - 1e-9)      # a valid step constant: lambda >= lambda_max
-    assert abs(lam - min(1.0, 1.01 * top)) <= 2e-3 * top
+    # and the estimate behind it within 0.5% of lambda_max: 200 products of the power method leave
+    # a convergence error that depends on the start vector's weight on the top eigenvector
+    assert abs(lam - min(1.0, 1.01 * top)) <= 5e-3 * top
     # without the Pock-Chambolle step nothing caps lambda at 1
     o = oracle.Options(use_pc=False)
     dr2, dc2, _, _, lam2, _ = oracle.scaling(lp, o)
     As2 = dr2[:, None] * A * dc2[None, :]
     top2 = np.linalg.eigvalsh(As2 @ As2.T).max()
-    assert abs(lam2 - 1.01 * top2) <= 2e-3 * top2
+    assert abs(lam2 - 1.01 * top2) <= 5e-3 * top2
 
 
 def test_power_start_vector_is_splitmix64():
