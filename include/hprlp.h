@@ -147,7 +147,10 @@ typedef struct {
                                    The choice fixes the summation order. */
     int32_t lds_windows;        /* LDS windows of the gathered vector in the matrix products:
                                    0 = none; 1 = "full" windows only (a block whose rows use at
-                                   most 16 KB of vector entries copies them into LDS first);
+                                   most 16 KB of vector entries copies them into LDS first; a
+                                   block of rows with 8 or more lanes each whose window spans at
+                                   least 8 KB takes up to 4 rounds of rows while that copy is
+                                   more than a quarter of its stored entries);
                                    2 = full and "split" windows (the two aligned 8 KB tiles
                                    holding most of a block's entries, the rest read from global
                                    memory); 3 = full, split and "sliced" windows (a block walks
@@ -233,6 +236,13 @@ typedef struct {
     int32_t packed_a;           /* 1: A's products read the packed words (from 90% packed quads
                                    on; otherwise the 16-bit offsets only) */
     int32_t packed_at;
+    int32_t win_mode_a;         /* LDS window mode of A's schedule (hpr_opts.lds_windows, 0 to 7;
+                                   the tuner's pick under -1) */
+    int32_t win_mode_at;
+    int32_t round_blocks_a;     /* thread blocks of A's schedule with a full window that take their
+                                   rows in more than one round (up to 4 x 256/G rows, G >= 8 lanes
+                                   per row, share one window copy) */
+    int32_t round_blocks_at;
 } hpr_kernel_stats;
 
 typedef struct hpr_handle hpr_handle;

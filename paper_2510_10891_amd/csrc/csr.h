@@ -262,16 +262,17 @@ struct PackOf { static constexpr bool value = false; };
 template <typename Base>
 struct PackOf<Packed<Base>> { static constexpr bool value = true; };
 
-// One block: each group of G lanes takes one row of the block's slice of the row list.
+// One round of a block: each group of G lanes takes one row of rows r0 .. r0 + kBlock / G of the
+// block's slice of the row list.
 // MODE 0: the gathered vector is read from global memory; 1: from the block's LDS window
 // `win`, which holds every column the block uses (columns relative to d.wlo; no wide rows in
 // such a block); 2: from the window for the columns it holds, global memory for the rest.
 template <int G, int U, bool NT, int MODE, typename Op, typename Tx>
-__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
-                                        const Tx* win) {
+__device__ __forceinline__ void run_round(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                          const Tx* win, int r0) {
     using Acc = typename Op::Acc;
     const int lane = threadIdx.x & (G - 1);
-    const int grp = threadIdx.x / G;
+    const int grp = r0 + (int)(threadIdx.x / G);
     const bool active = grp < d.count;
     const RowRef rr = active ? A.rows[d.first + grp] : RowRef{0, 0, 0, 0};
     const int row = rr.row;
@@ -296,6 +297,20 @@ __device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op
         if constexpr (Op::NV == 2) s1 = group_sum<G>(s1);
     }
     if (active && lane == 0) op.epi(row, s0, s1);
+}
+
+// One block. RD (the schedule has blocks in rounds): a block of rows with 8 or more lanes each may
+// hold more than kBlock / G rows (the schedule gives such blocks a full window), which every op
+// takes in rounds; with the window in LDS (MODE 1) all rounds gather from the one window copy.
+template <int G, int U, bool NT, int MODE, bool RD, typename Op, typename Tx>
+__device__ __forceinline__ void run_bin(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
+                                        const Tx* win) {
+    if constexpr (RD && G >= 8 && MODE != 2) {   // blocks in rounds have full windows, never split
+        for (int r0 = 0; r0 < d.count; r0 += kBlock / G)   // uniform over the block
+            run_round<G, U, NT, MODE>(A, op, d, win, r0);
+    } else {
+        run_round<G, U, NT, MODE>(A, op, d, win, 0);
+    }
 }
 
 // Sliced block (BlockDesc.ns > 0): the block walks its windows one at a time (copy into LDS,
@@ -368,17 +383,17 @@ __device__ __forceinline__ void run_block_sliced(const DevCsr<typename Op::Tm>& 
     }
 }
 
-template <int U, bool NT, int MODE, typename Op, typename Tx>
+template <int U, bool NT, int MODE, bool RD, typename Op, typename Tx>
 __device__ __forceinline__ void run_block(const DevCsr<typename Op::Tm>& A, Op& op, const BlockDesc& d,
                                           const Tx* win) {
     switch (d.bin) {
-        case 0: run_bin<1, U, NT, MODE>(A, op, d, win); break;
-        case 1: run_bin<2, U, NT, MODE>(A, op, d, win); break;
-        case 2: run_bin<4, U, NT, MODE>(A, op, d, win); break;
-        case 3: run_bin<8, U, NT, MODE>(A, op, d, win); break;
-        case 4: run_bin<16, U, NT, MODE>(A, op, d, win); break;
-        case 5: run_bin<32, U, NT, MODE>(A, op, d, win); break;
-        default: run_bin<64, U, NT, MODE>(A, op, d, win); break;
+        case 0: run_bin<1, U, NT, MODE, RD>(A, op, d, win); break;
+        case 1: run_bin<2, U, NT, MODE, RD>(A, op, d, win); break;
+        case 2: run_bin<4, U, NT, MODE, RD>(A, op, d, win); break;
+        case 3: run_bin<8, U, NT, MODE, RD>(A, op, d, win); break;
+        case 4: run_bin<16, U, NT, MODE, RD>(A, op, d, win); break;
+        case 5: run_bin<32, U, NT, MODE, RD>(A, op, d, win); break;
+        default: run_bin<64, U, NT, MODE, RD>(A, op, d, win); break;
     }
 }
 
@@ -405,9 +420,10 @@ __device__ __forceinline__ void block_reduce_store(double (&q)[NQ], double* part
 // most of them), for an op with one gathered vector and a window that fits kWinBytes, copies
 // the window into LDS with coalesced loads and gathers from there: the same values in the same
 // order, so the result does not depend on which path a block takes.
-// SL: the schedule has sliced blocks. A separate instantiation, so that schedules without them
-// keep the register budget (and occupancy) of the simpler paths.
-template <typename Op, int U, bool NT, bool SL>
+// SL: the schedule has sliced blocks; RD: it has blocks in rounds. Separate instantiations, so
+// that schedules without them keep the register budget (and occupancy) and the code of the
+// simpler paths.
+template <typename Op, int U, bool NT, bool SL, bool RD>
 __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, Op op_in) {
     using Tx = typename std::remove_cv<typename std::remove_pointer<decltype(op_in.g0)>::type>::type;
     const BlockDesc d = A.sched[blockIdx.x];
@@ -430,22 +446,29 @@ __global__ __launch_bounds__(kBlock) void csr_kernel(DevCsr<typename Op::Tm> A, 
         } else if (len > 0 && len <= kWinElems) {
             copy_window(win, op.g0, d.wlo, len);
             __syncthreads();
-            if (d.wlen > 0) run_block<U, NT, 1>(A, op, d, win);
-            else run_block<U, NT, 2>(A, op, d, win);
+            if (d.wlen > 0) run_block<U, NT, 1, RD>(A, op, d, win);
+            else run_block<U, NT, 2, RD>(A, op, d, win);
             done = true;
         }
     }
-    if (!done) run_block<U, NT, 0>(A, op, d, static_cast<const Tx*>(nullptr));
+    if (!done) run_block<U, NT, 0, RD>(A, op, d, static_cast<const Tx*>(nullptr));
     if constexpr (Op::NQ > 0) block_reduce_store(op.q, op.partials);
 }
 
 // With start/stop events (timing runs only, never under capture) the kernel is launched through
 // hipExtLaunchKernelGGL, which stamps the events at the dispatch's own start and end.
-template <typename Op, int U, bool NT, bool SL>
+template <typename Op, int U, bool NT, bool SL, bool RD>
 static void launch_csr_kernel(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start,
                               hipEvent_t stop) {
-    if (start) hipExtLaunchKernelGGL((csr_kernel<Op, U, NT, SL>), dim3(A.nblocks), dim3(kBlock), 0, st, start, stop, 0, A, op);
-    else hipLaunchKernelGGL((csr_kernel<Op, U, NT, SL>), dim3(A.nblocks), dim3(kBlock), 0, st, A, op);
+    if (start) hipExtLaunchKernelGGL((csr_kernel<Op, U, NT, SL, RD>), dim3(A.nblocks), dim3(kBlock), 0, st, start, stop, 0, A, op);
+    else hipLaunchKernelGGL((csr_kernel<Op, U, NT, SL, RD>), dim3(A.nblocks), dim3(kBlock), 0, st, A, op);
+}
+
+template <typename Op, int U, bool NT, bool SL>
+static void launch_csr_rounds(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start,
+                              hipEvent_t stop) {
+    if (A.has_rounds) launch_csr_kernel<Op, U, NT, SL, true>(A, op, st, start, stop);
+    else launch_csr_kernel<Op, U, NT, SL, false>(A, op, st, start, stop);
 }
 
 template <typename Op, int U, bool NT>
@@ -453,11 +476,11 @@ static void launch_csr_variant(const DevCsr<typename Op::Tm>& A, const Op& op, h
                                hipEvent_t stop) {
     if constexpr (Op::NV == 1) {
         if (A.has_sliced) {
-            launch_csr_kernel<Op, U, NT, true>(A, op, st, start, stop);
+            launch_csr_rounds<Op, U, NT, true>(A, op, st, start, stop);
             return;
         }
     }
-    launch_csr_kernel<Op, U, NT, false>(A, op, st, start, stop);
+    launch_csr_rounds<Op, U, NT, false>(A, op, st, start, stop);
 }
 
 // Op::STREAM: the op is one of the iteration's fused steps, the only ones whose schedule may ask
@@ -466,8 +489,9 @@ template <typename Op>
 static void launch_csr(const DevCsr<typename Op::Tm>& A, const Op& op, hipStream_t st, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr) {
     if (A.nblocks <= 0) return;
-    if constexpr (Op::NV == 0) {   // no matrix stream: one variant serves every schedule
-        launch_csr_kernel<Op, 1, false, false>(A, op, st, start, stop);
+    if constexpr (Op::NV == 0) {   // no matrix stream: one variant per row layout (rounds or not)
+        if (A.has_rounds) launch_csr_kernel<Op, 1, false, false, true>(A, op, st, start, stop);
+        else launch_csr_kernel<Op, 1, false, false, false>(A, op, st, start, stop);
         return;
     }
     if constexpr (Op::STREAM && !PackOf<Op>::value) {   // the fused steps read packed words when there are

@@ -23,8 +23,9 @@ constexpr int kChunk = 8192;     // entries per block of the segmented vector ke
 constexpr int kMaxBatch = 1024;  // LPs per engine (one control thread each)
 
 // One thread block of a matrix product: rows list[first .. first + count) of bin `bin`
-// (2^bin lanes per row), all belonging to LP `lp`. LDS windows of the gathered vector (products
-// with one gathered vector):
+// (2^bin lanes per row), all belonging to LP `lp`; count is at most kBlock / 2^bin rows, or up to
+// kMaxRounds times that for a block with a full window and bin >= 3 (its rows taken in rounds).
+// LDS windows of the gathered vector (products with one gathered vector):
 //   wlen > 0: "full", every column the block's rows use lies in [wlo, wlo + wlen);
 //   wlen < 0: "split", the window [wlo, wlo - wlen) holds most of them, the rest are read from
 //             global memory;
@@ -44,6 +45,7 @@ struct BlockDesc {
     int32_t cum_first;
 };
 constexpr int kMaxSlices = 8;       // windows per sliced block
+constexpr int kMaxRounds = 4;       // rounds of rows per block with a full window
 constexpr int kWinBytes = 16384;   // LDS per block for a staged window
 constexpr int kXcds = 8;           // accelerator complex dies of the MI355X, each with its own L2
 
@@ -78,6 +80,7 @@ struct DevCsr {
     int32_t slice_w;           // columns per window of a sliced block
     int32_t ncols;             // length of the gathered vector
     int32_t has_sliced;        // 1: some block of the schedule is sliced
+    int32_t has_rounds;        // 1: some block of the schedule takes its rows in rounds
     int32_t nblocks;
     int32_t unroll;            // U: 1, 2, 4 or 8 quads per lane and pass
     int32_t nontemporal;       // 1: stream the matrix with non-temporal loads

@@ -610,12 +610,12 @@ static void slice_block(BlockDesc& d, const int32_t* rows_of_block,
 // window copy) before their windows are sliced; rows stay in index order. With lane_cap >= 0
 // every row of a bin above lane_cap goes to bin lane_cap (at most 2^lane_cap lanes per row)
 // before blocks are formed, so full and split windows are shared by more rows too.
-static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
-                          const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
-                          const TileCounts& tc, int64_t ncols,
-                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
-                          int slice_cap, int lane_cap, std::vector<RowRef>& rows, std::vector<BlockDesc>& sched,
-                          std::vector<int32_t>& seg, std::vector<int32_t>& cum) {
+static void make_schedule_pass(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
+                               const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
+                               const TileCounts& tc, int64_t ncols,
+                               const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
+                               int slice_cap, int lane_cap, bool rounds, std::vector<RowRef>& rows,
+                               std::vector<BlockDesc>& sched, std::vector<int32_t>& seg, std::vector<int32_t>& cum) {
     std::vector<std::pair<int32_t, int64_t>> tiles;
     cum.clear();
     const int L = (int)lp_rows.size() - 1;
@@ -694,6 +694,46 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
         sched.push_back(d);
         return true;
     };
+    // Rows per block: `count` rows (one round), or, for rows of at least 8 lanes (bin >= 3),
+    // further rounds of per_block rows while the block's full window (every column of its rows,
+    // at most win_max) spans at least win_max / 2 columns and is more than a quarter of its stored
+    // entries, so that one large window copy serves more gathers; at most kMaxRounds rounds, and
+    // only when the longer block still gets its full window. Blocks of shorter rows, or with
+    // smaller windows, keep one round: rounds run the rows' latency chains (row entry, quads,
+    // gathers, epilogue) one after another, which only a large copy saved pays for (measured:
+    // rounds on the 2 KB windows of the 2,000-bus relaxation's security rows slowed its dual
+    // step, on the 16 KB windows of the 13,500-bus one they sped it up).
+    auto with_rounds = [&](int b, const int32_t* list, int32_t count, size_t left, int per_block) -> int32_t {
+        if (!rounds || win_max <= 0 || b < 3) return count;
+        struct Ext {
+            int64_t lo = INT64_MAX, hi = -1, entries = 0;
+            bool wide = false;
+            int64_t span() const { return hi < 0 ? 0 : hi - (lo - lo % 4) + 1; }
+        };
+        auto add = [&](Ext x, int32_t from, int32_t to) {
+            for (int32_t r = from; r < to; ++r) {
+                const int32_t i = list[r];
+                const int64_t quads = (start[i + 1] - start[i]) / kVec;
+                if (quads == 0) continue;
+                x.wide = x.wide || wide[i];
+                x.lo = std::min<int64_t>(x.lo, base[i]);
+                x.hi = std::max<int64_t>(x.hi, top[i]);
+                x.entries += quads * kVec;
+            }
+            return x;
+        };
+        Ext cur = add(Ext{}, 0, count);
+        if (cur.wide || cur.hi < 0 || cur.span() > win_max || 2 * cur.span() < win_max) return count;
+        int32_t n = count;
+        for (int round = 1; round < kMaxRounds && 4 * cur.span() > cur.entries && (size_t)n < left; ++round) {
+            const int32_t m = (int32_t)std::min<size_t>((size_t)n + (size_t)per_block, left);
+            const Ext next = add(cur, n, m);
+            if (next.wide || next.span() > win_max) break;
+            cur = next;
+            n = m;
+        }
+        return (n > count && cur.span() > cur.entries) ? count : n;
+    };
     for (int l = 0; l < L; ++l) {
         seg[l] = (int32_t)sched.size();
         for (auto& v : by_bin) v.clear();
@@ -709,9 +749,13 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
             const size_t bin_first = sched.size();
             const bool may_defer = sliced && slice_cap >= 0 && b > slice_cap;
             deferred.clear();
-            for (size_t k = 0; k < by_bin[b].size(); k += per_block)
-                emit(b, l, by_bin[b].data() + k,
-                     (int32_t)std::min<size_t>(per_block, by_bin[b].size() - k), may_defer);
+            for (size_t k = 0; k < by_bin[b].size();) {
+                const int32_t* list = by_bin[b].data() + k;
+                const size_t left = by_bin[b].size() - k;
+                const int32_t count = with_rounds(b, list, (int32_t)std::min<size_t>(per_block, left), left, per_block);
+                emit(b, l, list, count, may_defer);
+                k += (size_t)count;
+            }
             deal_to_xcds(sched, bin_first);
             if (!deferred.empty()) {   // regrouped: 2^slice_cap lanes per row
                 const std::vector<int32_t> list = deferred;
@@ -724,6 +768,29 @@ static void make_schedule(const std::vector<int64_t>& start, const std::vector<i
         }
     }
     seg[L] = (int32_t)sched.size();
+}
+
+// The schedule, with blocks in rounds only where they carry at least a quarter of the stored
+// entries: a schedule with any such block runs the product kernels' instantiation with the round
+// loop (a few more registers), which a handful of such blocks does not pay for.
+static void make_schedule(const std::vector<int64_t>& start, const std::vector<int32_t>& base,
+                          const std::vector<int32_t>& top, const std::vector<uint8_t>& wide,
+                          const TileCounts& tc, int64_t ncols,
+                          const std::vector<int64_t>& lp_rows, int U, int32_t win_max, bool split, bool sliced,
+                          int slice_cap, int lane_cap, std::vector<RowRef>& rows, std::vector<BlockDesc>& sched,
+                          std::vector<int32_t>& seg, std::vector<int32_t>& cum) {
+    make_schedule_pass(start, base, top, wide, tc, ncols, lp_rows, U, win_max, split, sliced, slice_cap, lane_cap,
+                       true, rows, sched, seg, cum);
+    int64_t in_rounds = 0, all = 0;
+    for (const BlockDesc& d : sched) {
+        int64_t q = 0;
+        for (int32_t r = 0; r < d.count; ++r) q += rows[(size_t)d.first + r].quads & ~kWide;
+        all += q;
+        if (d.count > (kBlock >> d.bin)) in_rounds += q;
+    }
+    if (in_rounds > 0 && 4 * in_rounds < all)
+        make_schedule_pass(start, base, top, wide, tc, ncols, lp_rows, U, win_max, split, sliced, slice_cap,
+                           lane_cap, false, rows, sched, seg, cum);
 }
 
 // lds_windows modes 4 and 5: sliced blocks regrouped with 16 and 8 lanes per row (bins 4, 3);
@@ -744,6 +811,7 @@ struct DevMatrix {
                                              // 4, 5: sliced blocks regrouped (16, 8 lanes per row),
                                              // 6, 7: every row at most 16, 8 lanes
     int32_t has_sliced = 0;                  // the current schedule has sliced blocks
+    int32_t has_rounds = 0;                  // ... blocks that take their rows in rounds
     TileCounts tiles;
     int64_t ncols = 0;                       // length of the gathered vector
     std::vector<BlockDesc> sched_h;
@@ -931,13 +999,17 @@ struct DevMatrix {
         HIP_OK(hipStreamSynchronize(st));
         sched_h = b->sched;
         seg_h = b->seg;
-        has_sliced = 0;
-        for (const BlockDesc& d : sched_h) has_sliced |= d.ns > 0 ? 1 : 0;
+        has_sliced = has_rounds = 0;
+        for (const BlockDesc& d : sched_h) {
+            has_sliced |= d.ns > 0 ? 1 : 0;
+            has_rounds |= d.count > (kBlock >> d.bin) ? 1 : 0;
+        }
         use_act = false;
     }
-    void window_counts(int32_t& full, int32_t& split, int32_t& sliced, int32_t& all) const {
-        full = split = sliced = 0;
+    void window_counts(int32_t& full, int32_t& split, int32_t& sliced, int32_t& all, int32_t& rounds) const {
+        full = split = sliced = rounds = 0;
         for (const BlockDesc& d : sched_h) {
+            if (d.count > (kBlock >> d.bin)) ++rounds;
             if (d.wlen > 0) ++full;
             if (d.wlen < 0) ++split;
             if (d.ns > 0) ++sliced;
@@ -984,6 +1056,7 @@ struct DevMatrix {
         d.slice_w = win_max;
         d.ncols = (int32_t)ncols;
         d.has_sliced = has_sliced;
+        d.has_rounds = has_rounds;
         return d;
     }
 };
@@ -2227,8 +2300,12 @@ static void engine_kernel_stats(Engine* e, hpr_kernel_stats* out) {
     out->setup_upload_s = e->t_upload;
     out->setup_tune_s = e->t_tune;
     out->setup_power_s = e->t_power;
-    e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->sliced_blocks_a, out->blocks_a);
-    e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->sliced_blocks_at, out->blocks_at);
+    e->A.window_counts(out->full_blocks_a, out->split_blocks_a, out->sliced_blocks_a, out->blocks_a,
+                       out->round_blocks_a);
+    e->At.window_counts(out->full_blocks_at, out->split_blocks_at, out->sliced_blocks_at, out->blocks_at,
+                        out->round_blocks_at);
+    out->win_mode_a = e->A.win_mode;
+    out->win_mode_at = e->At.win_mode;
     out->narrow_quads_a = e->A.narrow_quads;
     out->packed_quads_a = e->A.packed_quads;
     out->narrow_quads_at = e->At.narrow_quads;

@@ -57,7 +57,8 @@ class hpr_kernel_stats(C.Structure):
                 ("setup_prep_s", C.c_double), ("setup_upload_s", C.c_double), ("setup_tune_s", C.c_double),
                 ("setup_power_s", C.c_double), ("narrow_quads_a", C.c_int64), ("packed_quads_a", C.c_int64),
                 ("narrow_quads_at", C.c_int64), ("packed_quads_at", C.c_int64), ("packed_a", C.c_int32),
-                ("packed_at", C.c_int32)]
+                ("packed_at", C.c_int32), ("win_mode_a", C.c_int32), ("win_mode_at", C.c_int32),
+                ("round_blocks_a", C.c_int32), ("round_blocks_at", C.c_int32)]
 
 
 class hpr_info(C.Structure):
@@ -76,11 +77,20 @@ EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", 
 
 
 def lib():
-    """Load libhprlp.so (raises if it was not built)."""
+    """Load libhprlp.so (raises if it was not built).
+
+    torch, when installed, is imported first: its wheel carries its own copy of the HIP runtime,
+    and the library then binds to the copy already loaded, so that one process holds a single
+    runtime. Loaded the other way round (the library's runtime first, torch's second), torch
+    found no GPU in that process."""
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             raise ImportError(f"{_LIB_PATH} is missing: build it with python -m paper_2510_10891_amd.build")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(_LIB_PATH)
         L.hpr_last_error.restype = C.c_char_p
         for name in EXPORTS[1:-1]:
@@ -145,7 +155,8 @@ def _kstats(s: hpr_kernel_stats) -> dict:
                                     tune=round(s.setup_tune_s, 4), power=round(s.setup_power_s, 4)),
                 narrow_quads_a=s.narrow_quads_a, packed_quads_a=s.packed_quads_a,
                 narrow_quads_at=s.narrow_quads_at, packed_quads_at=s.packed_quads_at,
-                packed_a=s.packed_a, packed_at=s.packed_at)
+                packed_a=s.packed_a, packed_at=s.packed_at, win_mode_a=s.win_mode_a, win_mode_at=s.win_mode_at,
+                round_blocks_a=s.round_blocks_a, round_blocks_at=s.round_blocks_at)
 
 
 def hpr_default_opts() -> hpr_opts:

@@ -5,6 +5,10 @@ element by element: same scaling, lambda, iteration, check schedule, restarts an
 sigma. FP64 agrees to rounding (1e-8 relative); FP32 storage to FP32 rounding over a
 few iterations. Full solves are judged by the oracle's FP64 KKT evaluator.
 """
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 
@@ -300,6 +304,32 @@ def test_lane_capped_window_modes_match_oracle(mode):
     assert_parity(o, info, x, y, z, FP64_RTOL)
 
 
+@pytest.mark.parametrize("precision,n", [(hprlp.HPR_FP64, 1900), (hprlp.HPR_FP32, 2600)])
+def test_blocks_in_rounds_match_oracle(precision, n):
+    """Rows of ~64 entries spread over n columns (8 or 16 lanes each with U = 2): the blocks of A
+    get full windows wider than half the LDS window (8 KB) and take their rows in rounds, up to
+    4 x 256/G rows per window copy. FP64: 65 iterations against the oracle. FP32: 2 against the
+    oracle, and 65 against the same solve with the vector gathered from global memory
+    (lds_windows = 0: no windows, one round per block)."""
+    lp = scuc.random_lp(np.random.default_rng(7), 512, n, density=64.0 / n)
+    K = 65
+    info, x, y, z, ks = _run_mode(lp, K, 1, precision)
+    assert ks["round_blocks_a"] > 0 and ks["win_mode_a"] == 1
+    if precision == hprlp.HPR_FP64:
+        o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K, lambda_in=1.0))
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+        return
+    o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=2, lambda_in=1.0))
+    i2, x2, y2, _, k2 = _run_mode(lp, 2, 1, precision)
+    assert k2["round_blocks_a"] > 0 and i2.iters == o.iters
+    assert_close(x2, o.x, FP32_RTOL * 20, "x")
+    assert_close(y2, o.y, FP32_RTOL * 20, "y")
+    i0, x0, y0, _, k0 = _run_mode(lp, K, 0, precision)
+    assert k0["round_blocks_a"] == 0 and i0.iters == info.iters
+    assert_close(x, x0, FP32_RTOL, "x")
+    assert_close(y, y0, FP32_RTOL, "y")
+
+
 def test_packed_quads_cover_both_index_paths():
     """Quads of narrow rows whose first offset fits 13 bits and gaps 6 bits can be read as one
     packed word, the others through their 16-bit offsets as well; a matrix reads the packed words
@@ -505,6 +535,23 @@ def test_bounded_lps_with_unbounded_columns_match_the_oracle(case):
     info32, x32, y32, z32 = hprlp.solve(lp, hprlp.Options(tol=1e-5, max_iter=400000, precision=hprlp.HPR_FP32))
     assert info32.term == "solved", (name, info32.term)
     assert abs(info32.pobj - o.pobj) <= 1e-3 * (1 + abs(o.pobj))
+
+
+def test_torch_sees_the_gpu_after_the_library_solved_first():
+    """In a fresh process: a solve through the library, and only then torch's first use of the
+    GPU (the binding imports torch before loading the library, so both use one HIP runtime)."""
+    pytest.importorskip("torch")
+    code = ("from paper_2510_10891_amd import hprlp, scuc\n"
+            "_, lp = scuc.make_instance('small', 0)\n"
+            "info, *_ = hprlp.solve(lp, hprlp.Options(tol=1e-4, max_iter=20000))\n"
+            "assert info.term == 'solved', info.term\n"
+            "import torch\n"
+            "assert torch.cuda.is_available()\n"
+            "assert float((torch.ones(4, device='cuda:0') * 2).sum().item()) == 8.0\n"
+            "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
 
 
 def test_create_from_device_arrays_matches_host_arrays():
