@@ -561,7 +561,9 @@ def large_leg(steps, stream, read_gbs, copy_gbs):
                          solved=info.term == "solved", rel_kkt_fp64_eval=info.rel_kkt,
                          primal_us=round(ks["primal_ms"] * 1e3, 2), dual_us=round(ks["dual_ms"] * 1e3, 2),
                          schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
-                                   "sliced_blocks_At": ks["sliced_blocks_at"]})
+                                   "window_mode_A": ks["win_mode_a"], "window_mode_At": ks["win_mode_at"],
+                                   "sliced_blocks_At": ks["sliced_blocks_at"],
+                                   "blocks_in_rounds_A": ks["round_blocks_a"]})
         log(f"large {name}: {info.term} iters={info.iters} solve={sec:.3f}s setup={info.setup_s:.2f}s "
             f"primal={ks['primal_ms'] * 1e3:.1f}us dual={ks['dual_ms'] * 1e3:.1f}us {ks['setup_phases_s']}")
     (i32, s32, k32, x32), (i64, s64, k64, x64) = res["fp32"], res["fp64"]
@@ -596,7 +598,10 @@ def roofline(lp, ks, workload, read_gbs, copy_gbs, fp32=True):
                 plain_csr_bytes_per_launch=int(kalg),
                 plain_csr_gbs=round(kalg / (kms * 1e-3) / 1e9, 1),
                 schedule={"unroll_A": ks["unroll_a"], "unroll_At": ks["unroll_at"],
-                          "nontemporal_A": ks["nt_a"], "nontemporal_At": ks["nt_at"]},
+                          "nontemporal_A": ks["nt_a"], "nontemporal_At": ks["nt_at"],
+                          "window_mode_A": ks["win_mode_a"], "window_mode_At": ks["win_mode_at"],
+                          "blocks_A": ks["blocks_a"], "blocks_At": ks["blocks_at"],
+                          "blocks_in_rounds_A": ks["round_blocks_a"], "blocks_in_rounds_At": ks["round_blocks_at"]},
                 stream_probe_gbs={"read": round(read_gbs, 1), "copy": round(copy_gbs, 1)},
                 frac_of_stream_read=round(achieved / read_gbs, 4))
 
