@@ -150,7 +150,8 @@ typedef struct {
                                    most 16 KB of vector entries copies them into LDS first; a
                                    block of rows with 8 or more lanes each whose window spans at
                                    least 8 KB takes up to 4 rounds of rows while that copy is
-                                   more than a quarter of its stored entries);
+                                   more than a quarter of its stored entries, in matrices where
+                                   such blocks hold at least a quarter of the entries);
                                    2 = full and "split" windows (the two aligned 8 KB tiles
                                    holding most of a block's entries, the rest read from global
                                    memory); 3 = full, split and "sliced" windows (a block walks
