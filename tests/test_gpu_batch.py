@@ -193,6 +193,29 @@ def test_batch_with_sliced_windows_matches_oracle_per_lp():
         assert_parity(o, info, x, y, z, FP64_RTOL)
 
 
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batch_with_blocks_in_rounds_matches_oracle_per_lp(use_graph):
+    """A batch of LPs whose rows of ~64 entries spread over 1,900 columns (FP64 windows of at most
+    2,048 entries): their blocks of A take the rows in rounds sharing one window copy, beside a
+    narrow member without such blocks; each member's iterates against the oracle run on that LP
+    alone, through captured iteration blocks and direct launches."""
+    lps = [scuc.random_lp(np.random.default_rng(s), 384 + 64 * s, 1900, density=64.0 / 1900) for s in range(3)]
+    lps.append(ragged_lp(3, m=200, n=400))
+    K = 130
+    opts = hprlp.Options(tol=0.0, max_iter=K, lds_windows=1, unroll=2, use_graph=use_graph, profile=1)
+    b = hprlp.hpr_batch_create(lps, opts)
+    try:
+        infos = hprlp.hpr_batch_solve(b)
+        ks = hprlp.hpr_batch_get_kernel_stats(b)
+        sols = [hprlp.hpr_batch_get_solution(b, i) for i in range(len(lps))]
+    finally:
+        hprlp.hpr_batch_destroy(b)
+    assert ks["round_blocks_a"] > 0, ks
+    for lp, info, (x, y, z) in zip(lps, infos, sols):
+        o = oracle.solve(lp, oracle.Options(tol=0.0, max_iter=K))
+        assert_parity(o, info, x, y, z, FP64_RTOL)
+
+
 @pytest.mark.parametrize("mode", [3, 4, 5])
 @pytest.mark.parametrize("precision", [hprlp.HPR_FP64, hprlp.HPR_FP32])
 def test_sliced_windows_of_a_with_rows_out_of_column_order(mode, precision):
