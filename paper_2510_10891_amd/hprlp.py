@@ -79,10 +79,10 @@ EXPORTS = ("hpr_default_opts", "hpr_create", "hpr_set_bounds", "hpr_set_start", 
 def lib():
     """Load libhprlp.so (raises if it was not built).
 
-    torch, when installed, is imported first: its wheel carries its own copy of the HIP runtime,
-    and the library then binds to the copy already loaded, so that one process holds a single
-    runtime. Loaded the other way round (the library's runtime first, torch's second), torch
-    found no GPU in that process."""
+    torch, when installed, is imported first. Its wheel ships HIP runtime libraries of its own;
+    with torch imported first, the library and torch both ran on the GPU in one process, while
+    loading the library first left torch without a GPU in that process (a test in a fresh process
+    covers the order)."""
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
